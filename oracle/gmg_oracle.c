@@ -1,0 +1,479 @@
+/*
+ * gmg_oracle.c -- plain FP64 CPU oracle for geometric multigrid on the
+ * finite-difference Poisson problem (Feng, Shu, Xu, Zhang, "Numerical Study of
+ * Geometric Multigrid Methods on CPU-GPU Heterogeneous Computers",
+ * arXiv:1208.4247).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is
+ * checked against.  Nothing in the product library may link, load or call it;
+ * only the test suite, the smoke check and the CPU-baseline leg of the bench
+ * use it.  It shares no code with the HIP path.
+ *
+ * Written for obviousness, not speed: plain loops, one point at a time, in the
+ * order the paper states the steps.  OpenMP only splits the outermost loop of
+ * a pointwise-independent update; reductions are summed in a fixed order so
+ * that results do not depend on the thread count.  Build with
+ * -O2 -ffp-contract=off so that no multiply-add is fused.
+ *
+ * Problem (Sec. 2.2, eq. (1) and the 5-/7-point schemes): -Lap u = f on
+ * (0,1)^d, u = 0 on the boundary, d = 2 or 3, uniform mesh h = 1/n.
+ *
+ * Storage: a level with n intervals per axis has m = n - 1 interior nodes per
+ * axis.  A grid function is a dense array of m^d doubles, x fastest:
+ * storage (i, j[, k]) in [0, m) holds node (i+1, j+1[, k+1]), i.e. the value
+ * at x = (i+1) h.  Boundary nodes (index 0 or n) are never stored; they read
+ * as zero.
+ *
+ * Readings adopted where the paper is silent or ambiguous (each is also
+ * listed in the design notes):
+ *  - operator scaling: A_l v = (2d v_p - sum of neighbours) / h_l^2 with the
+ *    physical f on every level (the printed scheme moves h^2 to the right
+ *    hand side; both are the same system);
+ *  - transfers: full weighting (tensor [1/4 1/2 1/4]) and (bi/tri)linear
+ *    interpolation (tensor [1/2 1 1/2]), the standard pair, instead of the
+ *    7-point restriction and simplex interpolation printed in Sec. 4;
+ *  - smoother: red-black Gauss-Seidel, red = even sum of node indices;
+ *    forward sweep = red then black, backward = black then red; weighted
+ *    Jacobi as the alternative (Remark 1, Table 5);
+ *  - V-cycle (Algorithm 1): coarse iterates start from zero on every descent;
+ *    the ascent runs l = L-2 .. 0; the 1-DOF coarsest level is solved
+ *    exactly (Remark on the coarsest-level solver);
+ *  - solve loop (Algorithm 3 with every level on one device): the norm is
+ *    the Euclidean norm with the square root; iterate while
+ *    res > tol * res0 and iter < maxit.
+ *
+ * Parity status of each function: every function is pinned by the tests
+ * (closed forms, the paper's printed FFT error columns, dense and DST exact
+ * solves, Fourier symbols, invariants, symmetry, local Fourier analysis).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* basic helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* number of points of a level with m interior nodes per axis */
+static long npts(int d, int m) { return d == 2 ? (long)m * m : (long)m * m * m; }
+
+/* value at node-offset storage index, zero outside [0, m) (Dirichlet data) */
+static double at2(const double *v, int m, int i, int j) {
+  if (i < 0 || j < 0 || i >= m || j >= m) return 0.0;
+  return v[(long)j * m + i];
+}
+static double at3(const double *v, int m, int i, int j, int k) {
+  if (i < 0 || j < 0 || k < 0 || i >= m || j >= m || k >= m) return 0.0;
+  return v[((long)k * m + j) * m + i];
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+/* levels of the hierarchy for a finest side m0 = 2^L - 1; -1 if m0 is not of
+ * that form.  Level l has n_l = 2^(L-l) intervals, level L-1 has one node
+ * (Sec. 3.1; Remark on the coarsest-level solver). */
+int orc_levels(int m0) {
+  if (m0 < 1) return -1;
+  long n = (long)m0 + 1;
+  if (n & (n - 1)) return -1;
+  int L = 0;
+  while (n > 1) { n >>= 1; L++; }
+  return L;
+}
+
+/* Euclidean norm, summed per outer index then in index order (deterministic) */
+double orc_norm2(int d, int m, const double *r) {
+  long plane = d == 2 ? m : (long)m * m;
+  double *part = (double *)malloc(sizeof(double) * (size_t)m);
+#pragma omp parallel for schedule(static)
+  for (int o = 0; o < m; o++) {
+    double s = 0.0;
+    const double *p = r + (long)o * plane;
+    for (long q = 0; q < plane; q++) s += p[q] * p[q];
+    part[o] = s;
+  }
+  double s = 0.0;
+  for (int o = 0; o < m; o++) s += part[o];
+  free(part);
+  return sqrt(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* operator and residual (Sec. 2.2 schemes; Sec. 4 eq. residual_2D and the   */
+/* 3D count)                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* out = A v with (A v)_p = (2d v_p - sum_{q nbr p} v_q) / h^2, h = 1/(m+1) */
+void orc_apply_A(int d, int m, const double *v, double *out) {
+  double n = (double)(m + 1);
+  double inv_h2 = n * n;
+  if (d == 2) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; j++)
+      for (int i = 0; i < m; i++) {
+        double nb = at2(v, m, i - 1, j) + at2(v, m, i + 1, j) + at2(v, m, i, j - 1) +
+                    at2(v, m, i, j + 1);
+        out[(long)j * m + i] = (4.0 * at2(v, m, i, j) - nb) * inv_h2;
+      }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < m; k++)
+      for (int j = 0; j < m; j++)
+        for (int i = 0; i < m; i++) {
+          double nb = at3(v, m, i - 1, j, k) + at3(v, m, i + 1, j, k) + at3(v, m, i, j - 1, k) +
+                      at3(v, m, i, j + 1, k) + at3(v, m, i, j, k - 1) + at3(v, m, i, j, k + 1);
+          out[((long)k * m + j) * m + i] = (6.0 * at3(v, m, i, j, k) - nb) * inv_h2;
+        }
+  }
+}
+
+/* r = f - A u */
+void orc_residual(int d, int m, const double *u, const double *f, double *r) {
+  long N = npts(d, m);
+  orc_apply_A(d, m, u, r);
+#pragma omp parallel for schedule(static)
+  for (long p = 0; p < N; p++) r[p] = f[p] - r[p];
+}
+
+/* ------------------------------------------------------------------------ */
+/* smoothers (Remark 1; eq. relax_2D and its 3D analogue; Table 5)           */
+/* ------------------------------------------------------------------------ */
+
+/* One colour of red-black Gauss-Seidel: every node whose node-index sum has
+ * parity `color` (0 = red = even, 1 = black) is set so that its own equation
+ * holds with the current neighbours:  u_p = (h^2 f_p + sum nbrs) / (2d).
+ * Points of one colour only neighbour the other colour, so the order inside a
+ * colour does not matter. */
+void orc_rbgs_color(int d, int m, double *u, const double *f, int color) {
+  double h = 1.0 / (double)(m + 1);
+  double h2 = h * h;
+  if (d == 2) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; j++)
+      for (int i = 0; i < m; i++) {
+        if ((((i + 1) + (j + 1)) & 1) != color) continue;
+        long p = (long)j * m + i;
+        double nb = at2(u, m, i - 1, j) + at2(u, m, i + 1, j) + at2(u, m, i, j - 1) +
+                    at2(u, m, i, j + 1);
+        u[p] = (h2 * f[p] + nb) / 4.0;
+      }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < m; k++)
+      for (int j = 0; j < m; j++)
+        for (int i = 0; i < m; i++) {
+          if ((((i + 1) + (j + 1) + (k + 1)) & 1) != color) continue;
+          long p = ((long)k * m + j) * m + i;
+          double nb = at3(u, m, i - 1, j, k) + at3(u, m, i + 1, j, k) + at3(u, m, i, j - 1, k) +
+                      at3(u, m, i, j + 1, k) + at3(u, m, i, j, k - 1) + at3(u, m, i, j, k + 1);
+          u[p] = (h2 * f[p] + nb) / 6.0;
+        }
+  }
+}
+
+/* nsweeps red-black sweeps; forward = red then black, backward = black then
+ * red (the V-cycle's Relax_forward / Relax_backward, Algorithm 1). */
+void orc_rbgs(int d, int m, double *u, const double *f, int nsweeps, int backward) {
+  for (int s = 0; s < nsweeps; s++) {
+    if (!backward) {
+      orc_rbgs_color(d, m, u, f, 0);
+      orc_rbgs_color(d, m, u, f, 1);
+    } else {
+      orc_rbgs_color(d, m, u, f, 1);
+      orc_rbgs_color(d, m, u, f, 0);
+    }
+  }
+}
+
+/* nsweeps weighted-Jacobi sweeps (Remark 1; Table 5):
+ *   u_new = (1 - omega) u + omega (h^2 f + sum nbrs) / (2d), all from old u.
+ * tmp must hold m^d doubles. */
+void orc_wj(int d, int m, double *u, const double *f, double omega, int nsweeps, double *tmp) {
+  double h = 1.0 / (double)(m + 1);
+  double h2 = h * h;
+  long N = npts(d, m);
+  for (int s = 0; s < nsweeps; s++) {
+    memcpy(tmp, u, sizeof(double) * (size_t)N);
+    if (d == 2) {
+#pragma omp parallel for schedule(static)
+      for (int j = 0; j < m; j++)
+        for (int i = 0; i < m; i++) {
+          long p = (long)j * m + i;
+          double nb = at2(tmp, m, i - 1, j) + at2(tmp, m, i + 1, j) + at2(tmp, m, i, j - 1) +
+                      at2(tmp, m, i, j + 1);
+          u[p] = (1.0 - omega) * tmp[p] + omega * ((h2 * f[p] + nb) / 4.0);
+        }
+    } else {
+#pragma omp parallel for schedule(static)
+      for (int k = 0; k < m; k++)
+        for (int j = 0; j < m; j++)
+          for (int i = 0; i < m; i++) {
+            long p = ((long)k * m + j) * m + i;
+            double nb = at3(tmp, m, i - 1, j, k) + at3(tmp, m, i + 1, j, k) +
+                        at3(tmp, m, i, j - 1, k) + at3(tmp, m, i, j + 1, k) +
+                        at3(tmp, m, i, j, k - 1) + at3(tmp, m, i, j, k + 1);
+            u[p] = (1.0 - omega) * tmp[p] + omega * ((h2 * f[p] + nb) / 6.0);
+          }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* grid transfers                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Full-weighting restriction: coarse node I gathers fine nodes 2I+o,
+ * o in {-1,0,1}^d, with the tensor weights [1/4, 1/2, 1/4].  mc interior
+ * coarse nodes per axis; the fine level has mf = 2 mc + 1.  Coarse storage
+ * index a holds coarse node a+1, i.e. fine node 2a+2, fine storage 2a+1. */
+void orc_restrict_fw(int d, int mc, const double *r, double *fc) {
+  int mf = 2 * mc + 1;
+  static const double w[3] = {0.25, 0.5, 0.25};
+  if (d == 2) {
+#pragma omp parallel for schedule(static)
+    for (int b = 0; b < mc; b++)
+      for (int a = 0; a < mc; a++) {
+        double s = 0.0;
+        for (int oy = -1; oy <= 1; oy++)
+          for (int ox = -1; ox <= 1; ox++)
+            s += w[ox + 1] * w[oy + 1] * at2(r, mf, 2 * a + 1 + ox, 2 * b + 1 + oy);
+        fc[(long)b * mc + a] = s;
+      }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < mc; c++)
+      for (int b = 0; b < mc; b++)
+        for (int a = 0; a < mc; a++) {
+          double s = 0.0;
+          for (int oz = -1; oz <= 1; oz++)
+            for (int oy = -1; oy <= 1; oy++)
+              for (int ox = -1; ox <= 1; ox++)
+                s += w[ox + 1] * w[oy + 1] * w[oz + 1] *
+                     at3(r, mf, 2 * a + 1 + ox, 2 * b + 1 + oy, 2 * c + 1 + oz);
+          fc[((long)c * mc + b) * mc + a] = s;
+        }
+  }
+}
+
+/* Per-axis linear interpolation weights from the coarse grid to fine node
+ * index `fi` (node numbering, 1..mf).  An even fine node coincides with coarse
+ * node fi/2 (weight 1); an odd one lies halfway between coarse nodes
+ * (fi-1)/2 and (fi+1)/2 (weight 1/2 each).  Returns the number of
+ * contributions; coarse node indices are written to idx[] as coarse storage
+ * indices (node - 1), which may fall outside [0, mc) on the boundary. */
+static int lin_weights(int fi, int idx[2], double wt[2]) {
+  if ((fi & 1) == 0) {
+    idx[0] = fi / 2 - 1;
+    wt[0] = 1.0;
+    return 1;
+  }
+  idx[0] = (fi - 1) / 2 - 1;
+  idx[1] = (fi + 1) / 2 - 1;
+  wt[0] = 0.5;
+  wt[1] = 0.5;
+  return 2;
+}
+
+/* u (fine, mf = 2 mc + 1) += P e, P the (bi/tri)linear interpolation:
+ * the tensor product of the per-axis weights above; coarse boundary values
+ * are zero. */
+void orc_prolong_add(int d, int mc, const double *e, double *u) {
+  int mf = 2 * mc + 1;
+  if (d == 2) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < mf; j++)
+      for (int i = 0; i < mf; i++) {
+        int ix[2], iy[2];
+        double wx[2], wy[2];
+        int nx = lin_weights(i + 1, ix, wx);
+        int ny = lin_weights(j + 1, iy, wy);
+        double s = 0.0;
+        for (int b = 0; b < ny; b++)
+          for (int a = 0; a < nx; a++) s += wx[a] * wy[b] * at2(e, mc, ix[a], iy[b]);
+        u[(long)j * mf + i] += s;
+      }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < mf; k++)
+      for (int j = 0; j < mf; j++)
+        for (int i = 0; i < mf; i++) {
+          int ix[2], iy[2], iz[2];
+          double wx[2], wy[2], wz[2];
+          int nx = lin_weights(i + 1, ix, wx);
+          int ny = lin_weights(j + 1, iy, wy);
+          int nz = lin_weights(k + 1, iz, wz);
+          double s = 0.0;
+          for (int c = 0; c < nz; c++)
+            for (int b = 0; b < ny; b++)
+              for (int a = 0; a < nx; a++)
+                s += wx[a] * wy[b] * wz[c] * at3(e, mc, ix[a], iy[b], iz[c]);
+          u[((long)k * mf + j) * mf + i] += s;
+        }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* V-cycle (Algorithm 1) and solve loop (Algorithm 3, all levels on one      */
+/* device)                                                                   */
+/* ------------------------------------------------------------------------ */
+
+enum { ORC_RBGS = 0, ORC_WJ = 1 };
+
+typedef struct {
+  int d, L;
+  int m[32];
+  double *u[32], *f[32], *r[32];
+} hier_t;
+
+static void hier_free(hier_t *H) {
+  for (int l = 0; l < H->L; l++) {
+    if (l > 0) {
+      free(H->u[l]);
+      free(H->f[l]);
+    }
+    free(H->r[l]);
+  }
+}
+
+/* allocate coarse levels 1..L-1 (u_l, f_l) and a scratch r_l on every level;
+ * level 0 aliases the caller's u, f. */
+static int hier_init(hier_t *H, int d, int m0, double *u0, const double *f0) {
+  memset(H, 0, sizeof(*H));
+  int L = orc_levels(m0);
+  if (L < 1 || (d != 2 && d != 3)) return -1;
+  H->d = d;
+  H->L = L;
+  for (int l = 0; l < L; l++) {
+    H->m[l] = (1 << (L - l)) - 1;
+    long N = npts(d, H->m[l]);
+    if (l == 0) {
+      H->u[0] = u0;
+      H->f[0] = (double *)f0;
+    } else {
+      H->u[l] = (double *)calloc((size_t)N, sizeof(double));
+      H->f[l] = (double *)calloc((size_t)N, sizeof(double));
+    }
+    H->r[l] = (double *)calloc((size_t)N, sizeof(double));
+  }
+  return 0;
+}
+
+static void smooth(hier_t *H, int l, int smoother, double omega, int nsweeps, int backward) {
+  if (nsweeps <= 0) return;
+  if (smoother == ORC_RBGS)
+    orc_rbgs(H->d, H->m[l], H->u[l], H->f[l], nsweeps, backward);
+  else
+    orc_wj(H->d, H->m[l], H->u[l], H->f[l], omega, nsweeps, H->r[l]);
+}
+
+/* Exact solve of the 1-DOF coarsest level: 2d u / h^2 = f. */
+static void coarsest_solve(hier_t *H) {
+  int l = H->L - 1;
+  double h = 1.0 / (double)(H->m[l] + 1);
+  H->u[l][0] = (h * h * H->f[l][0]) / (2.0 * H->d);
+}
+
+static void vcycle(hier_t *H, int nu1, int nu2, int smoother, double omega) {
+  int d = H->d, L = H->L;
+  for (int l = 0; l <= L - 2; l++) {
+    if (l > 0) memset(H->u[l], 0, sizeof(double) * (size_t)npts(d, H->m[l]));
+    smooth(H, l, smoother, omega, nu1, 0);
+    orc_residual(d, H->m[l], H->u[l], H->f[l], H->r[l]);
+    orc_restrict_fw(d, H->m[l + 1], H->r[l], H->f[l + 1]);
+  }
+  coarsest_solve(H);
+  for (int l = L - 2; l >= 0; l--) {
+    orc_prolong_add(d, H->m[l + 1], H->u[l + 1], H->u[l]);
+    smooth(H, l, smoother, omega, nu2, 1);
+  }
+}
+
+/* One V(nu1, nu2) cycle applied in place to u (level 0, side m0). */
+int orc_vcycle(int d, int m0, double *u, const double *f, int nu1, int nu2, int smoother,
+               double omega) {
+  hier_t H;
+  if (hier_init(&H, d, m0, u, f)) return -1;
+  vcycle(&H, nu1, nu2, smoother, omega);
+  hier_free(&H);
+  return 0;
+}
+
+/* Solve loop.  res0 = ||f - A u|| unless res0_in > 0 is given (resume);
+ * while res > rtol*res0 and it < maxit: V-cycle; it++.  Writes the
+ * iteration count, the final relative residual and (optionally) the residual
+ * history res_hist[0..it] (res_hist[0] = residual of the initial guess).
+ * Returns 0 converged, 1 maxit reached, -3 non-finite residual. */
+int orc_solve(int d, int m0, double *u, const double *f, int nu1, int nu2, int smoother,
+              double omega, double rtol, int maxit, double res0_in, int *iters, double *relres,
+              double *res_hist) {
+  hier_t H;
+  if (hier_init(&H, d, m0, u, f)) return -1;
+  orc_residual(d, m0, u, f, H.r[0]);
+  double res = orc_norm2(d, m0, H.r[0]);
+  double res0 = res0_in > 0.0 ? res0_in : res;
+  if (res_hist) res_hist[0] = res;
+  int it = 0, status = 0;
+  if (!isfinite(res)) status = -3;
+  while (status == 0 && res > rtol * res0 && it < maxit) {
+    vcycle(&H, nu1, nu2, smoother, omega);
+    it++;
+    orc_residual(d, m0, u, f, H.r[0]);
+    res = orc_norm2(d, m0, H.r[0]);
+    if (res_hist) res_hist[it] = res;
+    if (!isfinite(res)) status = -3;
+  }
+  if (status == 0 && res > rtol * res0) status = 1;
+  *iters = it;
+  *relres = res0 > 0.0 ? res / res0 : 0.0;
+  hier_free(&H);
+  return status;
+}
+
+/* Full multigrid (Algorithm 2): restrict f to every level by full weighting,
+ * solve the coarsest level exactly, then for l = L-2 .. 0 interpolate the
+ * level-(l+1) solution to level l and run one V(nu1, nu2) cycle on the
+ * sub-hierarchy l .. L-1.  u (level 0) is overwritten. */
+int orc_fmg(int d, int m0, double *u, const double *f, int nu1, int nu2, int smoother,
+            double omega) {
+  hier_t H;
+  if (hier_init(&H, d, m0, u, f)) return -1;
+  int L = H.L;
+  for (int l = 0; l <= L - 2; l++) orc_restrict_fw(d, H.m[l + 1], H.f[l], H.f[l + 1]);
+  coarsest_solve(&H);
+  for (int l = L - 2; l >= 0; l--) {
+    memset(H.u[l], 0, sizeof(double) * (size_t)npts(d, H.m[l]));
+    orc_prolong_add(d, H.m[l + 1], H.u[l + 1], H.u[l]);
+    /* one V-cycle on levels l..L-1 with level l as the finest */
+    hier_t S;
+    memset(&S, 0, sizeof(S));
+    S.d = d;
+    S.L = L - l;
+    for (int q = 0; q < S.L; q++) {
+      S.m[q] = H.m[l + q];
+      S.u[q] = H.u[l + q];
+      S.f[q] = H.f[l + q];
+      S.r[q] = H.r[l + q];
+    }
+    vcycle(&S, nu1, nu2, smoother, omega);
+  }
+  hier_free(&H);
+  return 0;
+}
