@@ -1,0 +1,164 @@
+"""Benchmark: fine-grid unknowns/s of the GMG Poisson solve to 1e-10 relative
+residual on one MI355X, plus the smoother's achieved HBM bandwidth.
+
+Default workload: 3D 7-point Poisson, 255^3 interior (h = 1/256), zero
+Dirichlet data, f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) + 1e-3 U[-1,1]
+(SplitMix64 seed 2), FP64 V(2,2) red-black Gauss-Seidel, full weighting /
+trilinear interpolation, one-node coarsest level, u0 = 0, rtol = 1e-10.
+A step = one gmg_solve from u = 0 with f already in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
+
+WORKLOADS = {
+    # name: (dim, levels, rhs builder, smoother, nu, precision, description)
+    "poisson3d_255_sine_noise_fp64_v22": dict(dim=3, L=8, rhs="sine_noise", prec="fp64"),
+    "poisson2d_127_sine_fp64_v22": dict(dim=2, L=7, rhs="sine", prec="fp64"),
+    "poisson3d_511_uniform_fp64_v22": dict(dim=3, L=9, rhs="uniform", prec="fp64"),
+    "poisson3d_511_uniform_mixed_v22": dict(dim=3, L=9, rhs="uniform", prec="mixed"),
+}
+DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
+
+
+def make_rhs(spec):
+    from paper_1208_4247_amd import workloads as wl
+
+    d, m = spec["dim"], (1 << spec["L"]) - 1
+    if spec["rhs"] == "sine_noise":
+        return wl.rhs_sine_plus_noise(d, m, 2)
+    if spec["rhs"] == "sine":
+        return wl.rhs_sine(d, m)
+    if spec["rhs"] == "uniform":
+        return wl.rhs_uniform(d, m, 3)
+    raise ValueError(spec["rhs"])
+
+
+def cpu_baseline(spec, f, budget_s=30.0):
+    """The FP64 CPU oracle (untuned) solving the same workload on the host
+    cores, bounded in time: full solve when it fits, else a fixed number of
+    V-cycles scaled to unknowns/s at the GPU's cycle count."""
+    import oracle
+
+    oracle.build()
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    m = f.shape[0]
+    N = f.size
+    t0 = time.perf_counter()
+    u = oracle.vcycle(f * 0.0, f)
+    t_cycle = time.perf_counter() - t0
+    est = t_cycle * 12
+    if est <= budget_s:
+        t0 = time.perf_counter()
+        _, it, rel, st, _ = oracle.solve(f, rtol=1e-10)
+        t = time.perf_counter() - t0
+        return dict(value=N / t, unit="unknowns/s", cores=oracle.num_threads(), kind="oracle",
+                    sample="full solve of the same workload (%d V-cycles to relres %.1e), %.2f s"
+                    % (it, rel, t))
+    ncyc = max(1, int(budget_s / t_cycle))
+    t0 = time.perf_counter()
+    for _ in range(ncyc):
+        u = oracle.vcycle(u, f)
+    t = (time.perf_counter() - t0) / ncyc
+    return dict(value=N / (t * 12), unit="unknowns/s", cores=oracle.num_threads(), kind="oracle",
+                sample="%d V-cycles of the same workload at %.3f s each, scaled to 12 cycles"
+                % (ncyc, t))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--flags", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the solver runs every level of one "
+              "problem on a single device); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import Plan
+
+    spec = WORKLOADS[args.workload]
+    d, L = spec["dim"], spec["L"]
+    m = (1 << L) - 1
+    N = m ** d
+    f_host = make_rhs(spec)
+    torch.cuda.set_device(0)
+    f = torch.from_numpy(f_host).cuda()
+    u = torch.zeros_like(f)
+    plan = Plan(d, L, precision=spec["prec"], flags=args.flags | capi.GMG_PROFILE)
+    print("# workload %s: %d^%d, plan workspace %.1f MB" % (args.workload, m, d,
+          plan.workspace.numel() / 1e6), flush=True)
+
+    iters = []
+    for _ in range(args.warmup):
+        u.zero_()
+        st, it, rel = plan.solve(u, f, rtol=1e-10)
+    torch.cuda.synchronize()
+    plan.profile_reset()
+    t_total = 0.0
+    for k in range(args.steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, rel = plan.solve(u, f, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+        iters.append(it)
+    prof = plan.profile()
+    ms_per_step = 1e3 * t_total / args.steps
+    value = N / (t_total / args.steps)
+    print("# iters %s relres %.3e status %d" % (sorted(set(iters)), rel, st), flush=True)
+    for k, v in prof.items():
+        if v["launches"]:
+            print("#   %-22s launches %6d  avg %8.3f us  alg %8.1f GB/s" % (
+                k, v["launches"], 1e3 * v["ms"] / v["launches"],
+                v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0), flush=True)
+    dom = "smooth_pre_l0"
+    pv = prof[dom]
+    achieved = pv["bytes"] / (pv["ms"] * 1e-3) / 1e9 if pv["ms"] > 0 else 0.0
+    line = {
+        "metric": "fine-grid unknowns/s to 1e-10 rel. residual; smoother HBM GB/s % of peak",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if spec["prec"] == "fp64" else "f32-in-f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
+                   "cycle": "V(2,2) red-black GS", "rtol": 1e-10, "iters": iters[-1]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": dom},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec, f_host)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * gmg.h -- C ABI of an MI355X (gfx950) geometric-multigrid solver for the
+ * finite-difference Poisson problem
+ *
+ *     -Lap u = f  in (0,1)^d,   u = 0 on the boundary,   d = 2 or 3,
+ *
+ * discretised by the 5-point (2D) / 7-point (3D) central-difference scheme on
+ * a uniform mesh h = 1/n (Feng, Shu, Xu, Zhang, arXiv:1208.4247, Sec. 2.2,
+ * eq. (1) and the two difference schemes).  The solver is the multigrid
+ * V-cycle of Algorithm 1 inside the iteration loop of Algorithm 3, with every
+ * level, down to the one-node coarsest grid, kept on the GPU.
+ *
+ * DATA LAYOUT (all entry points)
+ *   A grid function on a level with n = 2^k intervals per axis is a dense
+ *   array of m^d values, m = n - 1 interior nodes per axis, x fastest:
+ *   element i + m*(j + m*k) holds node (i+1, j+1, k+1), i.e. x = (i+1)h.
+ *   Boundary nodes are not stored (homogeneous Dirichlet data).  f holds the
+ *   physical right-hand side f(x) (not h^2 f).  FP64 unless stated.
+ *
+ * OWNERSHIP
+ *   The caller owns every device buffer (u, f, the workspace) and the stream;
+ *   the library never allocates device memory.  The library owns only the
+ *   host-side plan object.  Device pointers must be hipMalloc'ed (or
+ *   torch-allocated) memory of the current device, 8-byte aligned.  Arrays
+ *   passed to one call must not overlap unless stated.
+ *
+ * ERRORS
+ *   Every entry point returns a gmg_status; nothing aborts or throws across
+ *   the ABI.  Arguments are validated before any HIP call, so invalid input
+ *   is reported the same way with or without a GPU.  HIP failures map to
+ *   GMG_ERR_HIP.  GMG_NOT_CONVERGED still fills iteration counts and
+ *   residuals.
+ *
+ * THREADING / STREAMS
+ *   A plan is bound to the stream given at setup; calls on one plan must not
+ *   run concurrently from several host threads.  gmg_vcycle and the gmg_op_*
+ *   calls without a host output only enqueue work; gmg_solve and
+ *   gmg_batch_solve synchronise on the stream once per convergence check.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GMG_OK = 0,
+  GMG_NOT_CONVERGED = 1,    /* maxit reached before rtol; outputs filled    */
+  GMG_ERR_INVALID_ARG = -1, /* bad size, order, pointer, tolerance, ...     */
+  GMG_ERR_WORKSPACE = -2,   /* workspace missing, too small or misaligned   */
+  GMG_ERR_NONFINITE = -3,   /* a residual norm was NaN or Inf               */
+  GMG_ERR_DIVERGED = -4,    /* relative residual grew above 1e3             */
+  GMG_ERR_HIP = -5,         /* a HIP runtime call failed                    */
+  GMG_ERR_UNSUPPORTED = -6  /* valid request this build does not provide    */
+} gmg_status;
+
+/* Smoother (Sec. 3.2, Remark 1; Table 5).  RBGS: red-black Gauss-Seidel,
+ * red = nodes whose node-index sum is even.  A forward sweep relaxes red then
+ * black; a backward sweep black then red.  WJ: weighted Jacobi
+ * u <- (1-omega) u + omega (h^2 f + sum of neighbours) / (2d). */
+typedef enum { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_WJ = 1 } gmg_smoother;
+
+/* Precision of a plan.  FP64: every level in FP64.  MIXED_FP32_IR: an FP64
+ * defect-correction loop (residual, update and norm in FP64) around FP32
+ * V-cycles whose one-node coarsest solve is done in FP64. */
+typedef enum { GMG_FP64 = 0, GMG_MIXED_FP32_IR = 1 } gmg_precision;
+
+/* Element type of the gmg_op_* primitives. */
+typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
+
+/* gmg_config.flags */
+#define GMG_USE_GRAPH 0x1u          /* replay cycles from a captured hipGraph   */
+#define GMG_AUTOTUNE 0x2u           /* time tile variants at setup, cache them  */
+#define GMG_PROFILE 0x4u            /* time every kernel launch with hipEvents  */
+#define GMG_POST_FORWARD 0x8u       /* post-smooth red->black (textbook order)
+                                       instead of Algorithm 1's backward sweep */
+#define GMG_NO_TEMPORAL_BLOCKING 0x10u /* one fused sweep per pass at most     */
+
+typedef struct {
+  int dim;                 /* 2 or 3                                            */
+  int levels;              /* L: finest side m0 = 2^L - 1, coarsest has 1 node  */
+  gmg_smoother smoother;   /* default GMG_SMOOTH_RBGS                           */
+  int nu1, nu2;            /* pre/post sweeps (V(nu1,nu2)); nu1 + nu2 >= 1     */
+  double omega;            /* WJ weight in (0, 1]; ignored by RBGS; 0 = default
+                              2d/(2d+1) (4/5 in 2D, 6/7 in 3D)                   */
+  gmg_precision precision; /* default GMG_FP64                                  */
+  int inner_cycles;        /* FP32 V-cycles per refinement step (>= 1)          */
+  unsigned flags;          /* GMG_* flags above                                 */
+} gmg_config;
+
+typedef struct gmg_plan gmg_plan; /* opaque, host side */
+
+/* Fill *cfg with defaults: RBGS V(2,2), FP64, one inner cycle, no flags. */
+gmg_status gmg_config_default(gmg_config *cfg, int dim, int levels);
+
+/* Create a plan (Algorithm 3's set-up: level table, workspace carving).
+ * Two-phase: with workspace == NULL only *ws_bytes is written (the bytes the
+ * plan needs) and *out is left untouched.  Otherwise workspace must point to
+ * at least *ws_bytes bytes of device memory, 256-byte aligned, which the plan
+ * uses until gmg_destroy; the caller keeps ownership.
+ * nproblems == 1: dims/levels may be NULL (cfg->dim and cfg->levels apply).
+ * nproblems > 1 (batch): dims[p] and levels[p] give each problem's dimension
+ * and level count; cfg->dim/levels are ignored.
+ * stream: a hipStream_t (NULL = the default stream).
+ * Errors: GMG_ERR_INVALID_ARG (dim not 2/3, levels < 1 or too large for the
+ * int32 index space, nu1 + nu2 < 1, nu > 8, omega outside (0,1],
+ * inner_cycles < 1, nproblems < 1, NULL out/ws_bytes), GMG_ERR_WORKSPACE
+ * (workspace smaller than required or not 256-byte aligned),
+ * GMG_ERR_UNSUPPORTED (a combination this build does not run, e.g. batch
+ * with mixed precision), GMG_ERR_HIP. */
+gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, const int *levels,
+                     void *workspace, size_t *ws_bytes, void *stream, gmg_plan **out);
+
+/* One V(nu1,nu2) cycle (Algorithm 1) applied in place to u for right-hand
+ * side f (single-problem plans).  Enqueue only.  In MIXED_FP32_IR mode: one
+ * refinement step x <- x + V32(f - A x).  u and f: device, m0^d FP64. */
+gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f);
+
+/* Solve loop of Algorithm 3 with every level on the GPU: res0 = ||f - A u||_2
+ * for the initial u (or *res0_opt when resuming); repeat V-cycles while
+ * ||f - A u||_2 > rtol * res0 and the cycle count is below maxit.  The
+ * Euclidean norm is used.  u is the initial guess on entry and the result on
+ * return.  Outputs (host, may be NULL): *iters = cycles done,
+ * *relres = final ||f - A u|| / res0 (0 when res0 == 0).
+ * Returns GMG_OK, GMG_NOT_CONVERGED, GMG_ERR_NONFINITE, GMG_ERR_DIVERGED,
+ * GMG_ERR_INVALID_ARG (rtol <= 0, maxit < 1, NULL u/f), GMG_ERR_HIP. */
+gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int maxit,
+                     const double *res0_opt, int *iters, double *relres);
+
+/* Batch solve (plans made with nproblems > 1): u[q], f[q] are device
+ * pointers (host array of nproblems pointers) to problem q's grids.  Every
+ * problem runs the same algorithm as gmg_solve with its own stop test; the
+ * cycles of all problems are interleaved level by level.  iters[q],
+ * relres[q], st[q] (host arrays, may be NULL) get per-problem results; the
+ * return value is the worst per-problem status. */
+gmg_status gmg_batch_solve(gmg_plan *p, double *const *u, const double *const *f, double rtol,
+                           int maxit, int *iters, double *relres, gmg_status *st);
+
+/* Release the plan (host memory only; the workspace stays the caller's). */
+gmg_status gmg_destroy(gmg_plan *p);
+
+/* Static string naming a status. */
+const char *gmg_status_string(gmg_status s);
+
+/* Bytes of workspace the plan uses (0 for NULL). */
+size_t gmg_plan_workspace_bytes(const gmg_plan *p);
+
+/* Interior side m_l of level l of problem q (-1 if out of range).  Level 0 is
+ * the finest; level levels-1 has one node. */
+int gmg_level_side(const gmg_plan *p, int problem, int level);
+
+/* Tile shapes of the fused smoothing passes.  A pass applies `stages`
+ * stages in one sweep over memory (red-black: 2 per sweep; weighted Jacobi:
+ * 1 per sweep); each stage count has a few tile shapes.  Returns the number
+ * of shapes (0: that stage count is not provided). */
+int gmg_tile_variant_count(int dim, gmg_smoother smoother, int stages);
+
+/* Override the tile shape (index < gmg_tile_variant_count) and the z-chunk
+ * (output planes per workgroup; 0 = automatic) used on level `level` of
+ * problem 0 for passes with `stages` stages.  Results do not depend on the
+ * choice (tests check this bitwise); only speed does.  Host only. */
+gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, int tz);
+
+/* ---------------------------------------------------------------------- */
+/* Operator primitives.  Each runs exactly the kernels the cycle runs for  */
+/* one step, on problem 0's level `level` (side m = gmg_level_side(p,0,l)).*/
+/* Pointers: device arrays of m^d (fine) or mc^d (coarse, mc = (m-1)/2)    */
+/* elements of dtype dt.  Enqueue only unless a host output is requested. */
+/* ---------------------------------------------------------------------- */
+
+/* Smoothing (Algorithm 1, Relax_forward / Relax_backward): u_out =
+ * nsweeps sweeps of the plan's smoother applied to the start value
+ * u_in + P e_coarse (u_in NULL = zero; e_coarse NULL = no correction;
+ * P = (bi/tri)linear interpolation from level+1), with right-hand side f.
+ * backward selects black->red order (RBGS only).  If res_in_norm is not
+ * NULL, ||f - A u_in||_2 (of the start value, e_coarse must be NULL) is
+ * written there (synchronises).  u_out must not alias u_in, f or e_coarse. */
+gmg_status gmg_op_smooth(gmg_plan *p, int level, gmg_dtype dt, int nsweeps, int backward,
+                         const void *u_in, const void *f, const void *e_coarse, void *u_out,
+                         double *res_in_norm);
+
+/* Residual and full-weighting restriction (Algorithm 1, r_l = f_l - A_l u_l;
+ * f_{l+1} = R r_l): f_coarse = FW(f - A u), r never stored.  level must be
+ * below the coarsest. */
+gmg_status gmg_op_restrict_residual(gmg_plan *p, int level, gmg_dtype dt, const void *u,
+                                    const void *f, void *f_coarse);
+
+/* Residual r = f - A u (r may be NULL) and its norm ||r||_2 (norm may be
+ * NULL; synchronises when given). */
+gmg_status gmg_op_residual(gmg_plan *p, int level, gmg_dtype dt, const void *u, const void *f,
+                           void *r, double *norm);
+
+/* ---------------------------------------------------------------------- */
+/* Profiling (plans set up with GMG_PROFILE): per kernel class, launches,  */
+/* summed hipEvent durations on the plan's stream and algorithmic bytes.   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  char name[48];
+  long long launches;
+  double total_ms;
+  double alg_bytes; /* algorithmic HBM bytes summed over the launches */
+} gmg_kernel_stat;
+
+int gmg_profile_count(const gmg_plan *p);
+gmg_status gmg_profile_get(gmg_plan *p, int idx, gmg_kernel_stat *out); /* synchronises */
+gmg_status gmg_profile_reset(gmg_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMG_H */

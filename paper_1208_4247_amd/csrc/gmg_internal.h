@@ -1,0 +1,140 @@
+// gmg_internal.h -- declarations shared by the HIP kernels and the host
+// orchestration of the multigrid library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gmg {
+
+// Flags of a fused smoothing pass.
+enum PassFlags : int {
+  F_ZERO_IN = 1,     // start value is zero: u_in is not read
+  F_PROLONG = 2,     // start value is u_in + P e_coarse (linear interpolation)
+  F_NORM_IN = 4,     // emit per-workgroup partial sums of |f - A u_in|^2
+  F_BLACK_FIRST = 8, // red-black order black -> red (backward sweep)
+};
+
+// Device-resident state of one solve (one per problem in batch mode).
+struct SolveState {
+  int active;   // 1 while further cycles should run
+  int iter;     // cycles started (the finalize step counts the cycle it admits)
+  int maxit;
+  int status;   // 0 converged/running, 1 maxit, -3 non-finite, -4 diverged
+  double rtol;
+  double res0;  // < 0: take from the first norm
+  double res;   // last residual norm
+  double pad;
+};
+
+template <typename T>
+struct PassArgs {
+  const T *u_in;        // start value (ignored with F_ZERO_IN)
+  const T *f;           // right-hand side of this level
+  T *u_out;             // result (never aliases u_in / f / e_c)
+  const T *e_c;         // coarse correction (F_PROLONG)
+  double *partials;     // F_NORM_IN: one double per workgroup
+  const int *active;    // skip the launch when *active == 0 (NULL: always run)
+  int m, mc;            // fine / coarse interior side
+  int ntx, nty, tz;     // tiles along x, y; output planes per z-chunk
+  int nblocks;          // grid size (for the XCD remap)
+  double h2;            // h^2 of the fine level
+  double inv_h2;
+  double omega;         // weighted Jacobi
+};
+
+template <typename T>
+struct RestrictArgs {
+  const T *u;
+  const T *f;
+  T *fc;
+  const int *active;
+  int m, mc;
+  double inv_h2;
+};
+
+template <typename T>
+struct ResidArgs {
+  const T *u;
+  const T *f;
+  T *r;                 // may be NULL (norm only)
+  double *partials;     // may be NULL
+  const int *active;
+  int m;
+  int nblocks;
+  double inv_h2;
+};
+
+// Bottom of the V-cycle for the small levels, one workgroup per problem.
+template <typename T>
+struct BottomArgs {
+  const T *f;           // right-hand side of the first bottom level (global)
+  T *u;                 // result on that level (global)
+  const int *active;
+  int dim, L;           // levels in the bottom sub-hierarchy (finest side 2^L-1)
+  int nu1, nu2;
+  int smoother;         // 0 RBGS, 1 WJ
+  int post_forward;     // post-smoothing in forward order
+  double omega;
+};
+
+// Outer step of iterative refinement (FP64 residual around FP32 cycles).
+struct IrArgs {
+  const double *x;      // current iterate
+  const float *e;       // correction from the FP32 cycle (NULL: none)
+  const double *f;
+  double *x_out;        // x + e (never aliases x)
+  float *r32;           // (float)(f - A (x + e))
+  double *partials;
+  const int *active;
+  int m, nblocks;
+  double inv_h2;
+};
+
+// ---------------------------------------------------------------- launchers
+// Tile shape of a fused smoothing pass; the host picks one per level.
+struct PassTile {
+  int exp_;  // pairs per extended row (= output pairs + halo pairs)
+  int ey;    // extended rows (3D) / 1 (2D)
+  int nt;    // threads per workgroup
+};
+
+// Geometry of a pass launch (computed by pass_geometry).
+struct PassGeom {
+  int ntx, nty, ntz, tz, nblocks;
+};
+
+int pass_variant_count(int dim, int stages, int wj);
+PassTile pass_variant(int dim, int stages, int wj, int v);
+PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz);
+
+template <typename T>
+hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<T> a,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_wj_pass(int dim, int sweeps, int flags, int variant, PassArgs<T> a,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s);
+template <typename T>
+hipError_t launch_residual(int dim, ResidArgs<T> a, hipStream_t s);
+int residual_blocks(int dim, int m);
+template <typename T>
+hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const T *const *f_list,
+                         T *const *u_list, hipStream_t s);
+size_t bottom_lds_bytes(int dim, int L, int smoother, size_t elem);
+hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s);
+int ir_blocks(int dim, int m);
+
+template <typename T>
+hipError_t launch_prolong_add(int dim, int m, int mc, const T *in, const T *ec, T *out,
+                              const int *active, hipStream_t s);
+hipError_t launch_axpy_f32(double *x, const float *e, size_t n, const int *active, hipStream_t s);
+
+hipError_t launch_finalize(const double *partials, int n, SolveState *st, hipStream_t s);
+hipError_t launch_state_init(SolveState *st, int maxit, double rtol, double res0, hipStream_t s);
+hipError_t launch_reduce_norm(const double *partials, int n, double *out, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, const int *active, hipStream_t s);
+hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace gmg

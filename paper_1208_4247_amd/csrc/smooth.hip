@@ -1,0 +1,639 @@
+// smooth.hip -- fused smoothing passes for gfx950 (red-black Gauss-Seidel and
+// weighted Jacobi) on the 5-/7-point Poisson stencil.
+//
+// Smoother: Sec. 3.2 Remark 1 and the relaxation formula of Sec. 4 (eq.
+// relax_2D, u = (h^2 f + sum of neighbours) / (2d)); red-black colouring by
+// parity of the node-index sum (red even); a forward sweep relaxes red then
+// black, a backward sweep black then red (Algorithm 1's Relax_forward /
+// Relax_backward).  Weighted Jacobi: Remark 1 and Table 5.
+//
+// One launch = one pass over HBM that applies S stages (S half-sweeps for
+// red-black, S full sweeps for Jacobi) -- temporal blocking:
+//
+//  * A workgroup owns an output tile of TX x TY columns (3D; TX x 1 in 2D) and
+//    marches along the outermost axis (z in 3D, y in 2D) over a chunk of
+//    planes.  Stage s lags the input by s planes; every stage keeps a
+//    three-plane window of its values in registers (the marching-axis
+//    neighbours) and publishes its newest plane in LDS for the in-plane
+//    neighbours.  The tile carries a halo of S points on each in-plane side so
+//    that the last stage is exact on the output tile; halo values are
+//    recomputed redundantly by neighbouring tiles (cheap: the kernel is HBM
+//    bound at ~0.3 flop/byte).
+//  * Each lane owns a PAIR of adjacent x columns.  In any row and plane
+//    exactly one element of the pair has a given colour, and which one is the
+//    same for all lanes of the row, so a red-black half-sweep does exactly one
+//    update per lane with no divergence, and one of the two x-neighbours of
+//    that element is the other element of the lane's own pair.
+//  * Optional fusions: the start value may be zero (coarse levels of the
+//    correction scheme), or the previous iterate plus the (bi/tri)linearly
+//    interpolated coarse correction (the prolongation of Algorithm 1's ascent);
+//    the pass may emit per-workgroup sums of |f - A u_in|^2 (the convergence
+//    test of Algorithm 3 evaluated on the pass's input, which the pass reads
+//    anyway).
+//  * Workgroup -> tile mapping is XCD-aware: the 8 XCDs receive contiguous
+//    ranges of tiles, so halo re-reads of neighbouring tiles hit the same L2.
+#include "gmg_internal.h"
+
+namespace gmg {
+
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int per = n >> 3, rem = n & 7;
+  return xcd * per + min(xcd, rem) + loc;
+}
+
+// Per-axis linear interpolation from the coarse grid to fine storage index x:
+// fine node x+1 even -> coarse storage (x-1)/2 with weight 1; odd -> coarse
+// storage x/2-1 and x/2 with weight 1/2 each.
+template <typename T>
+__device__ __forceinline__ int lin_axis(int x, int *c, T *w) {
+  if (x & 1) {  // node x+1 even
+    c[0] = (x - 1) >> 1;
+    w[0] = T(1);
+    return 1;
+  }
+  c[0] = (x >> 1) - 1;
+  c[1] = x >> 1;
+  w[0] = T(0.5);
+  w[1] = T(0.5);
+  return 2;
+}
+
+// (P e)(x, y, z): tensor-product linear interpolation, zero coarse boundary.
+template <typename T, int DIM>
+__device__ __forceinline__ T interp(const T *__restrict__ ec, int mc, int x, int y, int z) {
+  int cx[2], cy[2], cz[2];
+  T wx[2], wy[2], wz[2];
+  const int nx = lin_axis<T>(x, cx, wx);
+  const int ny = lin_axis<T>(y, cy, wy);
+  T s = T(0);
+  if (DIM == 2) {
+    for (int b = 0; b < ny; ++b)
+      for (int a = 0; a < nx; ++a) {
+        const int i = cx[a], j = cy[b];
+        if (i >= 0 && i < mc && j >= 0 && j < mc) s += wx[a] * wy[b] * ec[(size_t)j * mc + i];
+      }
+  } else {
+    const int nz = lin_axis<T>(z, cz, wz);
+    for (int c = 0; c < nz; ++c)
+      for (int b = 0; b < ny; ++b)
+        for (int a = 0; a < nx; ++a) {
+          const int i = cx[a], j = cy[b], k = cz[c];
+          if (i >= 0 && i < mc && j >= 0 && j < mc && k >= 0 && k < mc)
+            s += wx[a] * wy[b] * wz[c] * ec[((size_t)k * mc + j) * mc + i];
+        }
+  }
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum_store(double acc, double *out) {
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    out[blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Red-black Gauss-Seidel pass: S half-sweeps, colour of stage s is
+// (C1 + s - 1) mod 2 with C1 = 0 (red first) or 1 (black first).
+// ------------------------------------------------------------------------
+template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
+__global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
+  if (a.active && *a.active == 0) return;
+  constexpr int NS = (EXP * EY + NT - 1) / NT;  // slots per thread
+  constexpr int HP = S / 2;                     // halo in pairs
+  constexpr int TXP = EXP - 2 * HP;             // output pairs per row
+  constexpr int TY = DIM == 3 ? EY - 2 * S : 1;
+  constexpr bool ZERO = (FL & F_ZERO_IN) != 0;
+  constexpr bool PRO = (FL & F_PROLONG) != 0;
+  constexpr bool NORM = (FL & F_NORM_IN) != 0;
+  constexpr int C1 = (FL & F_BLACK_FIRST) ? 1 : 0;
+  constexpr int C0 = 1 - C1;  // colour the first stage reads
+  constexpr int PL = EXP * EY;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);  // [S (+1)][PL]
+
+  const int m = a.m;
+  const int bid = xcd_remap(blockIdx.x, a.nblocks);
+  const int tx = bid % a.ntx;
+  const int rest = bid / a.ntx;
+  const int ty = DIM == 3 ? rest % a.nty : 0;
+  const int tzc = DIM == 3 ? rest / a.nty : rest;
+  const int X0 = tx * 2 * TXP;
+  const int Y0 = ty * TY;
+  const int Z0 = tzc * a.tz;
+  const int Z1 = min(Z0 + a.tz, m);
+  const size_t rowS = (size_t)m;
+  const size_t planeS = DIM == 3 ? (size_t)m * m : (size_t)m;
+  const T h2 = T(a.h2);
+  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
+
+  int q[NS], xb[NS], yy[NS], lq[NS], rq[NS], uq[NS], dq[NS];
+  bool live[NS], yin[NS], outp[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    q[i] = threadIdx.x + NT * i;
+    live[i] = q[i] < PL;
+    const int p = q[i] % EXP, r = q[i] / EXP;
+    xb[i] = X0 - S + 2 * p;
+    yy[i] = DIM == 3 ? Y0 - S + r : 0;
+    yin[i] = DIM == 2 || (yy[i] >= 0 && yy[i] < m);
+    outp[i] = live[i] && yin[i] && p >= HP && p < HP + TXP &&
+              (DIM == 2 || (r >= S && r < S + TY)) && xb[i] < m;
+    const int rr = min(r, EY - 1);
+    lq[i] = rr * EXP + max(p - 1, 0);
+    rq[i] = rr * EXP + min(p + 1, EXP - 1);
+    uq[i] = max(rr - 1, 0) * EXP + p;
+    dq[i] = min(rr + 1, EY - 1) * EXP + p;
+  }
+
+  T W[S][NS][3];  // stage windows: [0] newest plane, [1] previous, [2] two back
+  T WB[NORM ? NS : 1][3];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) W[s][i][0] = W[s][i][1] = W[s][i][2] = T(0);
+#pragma unroll
+  for (int i = 0; i < (NORM ? NS : 1); ++i) WB[i][0] = WB[i][1] = WB[i][2] = T(0);
+  double acc = 0.0;
+
+  for (int t = Z0 - S; t < Z1 + S; ++t) {
+    const bool tin = t >= 0 && t < m;
+    // ---- stage 0: start value on plane t
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      T v0 = T(0), v1 = T(0);
+      const int e0 = (C0 + yy[i] + t + DIM) & 1;  // element holding colour C0
+      if (live[i] && tin && yin[i]) {
+        const size_t base = (size_t)t * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+        const int x0 = xb[i];
+        if (!ZERO) {
+          if (x0 >= 0 && x0 < m) v0 = a.u_in[base + x0];
+          if (x0 + 1 >= 0 && x0 + 1 < m) v1 = a.u_in[base + x0 + 1];
+        }
+        if (PRO) {
+          const int xe = x0 + e0;
+          if (xe >= 0 && xe < m) {
+            const T c = DIM == 3 ? interp<T, 3>(a.e_c, a.mc, xe, yy[i], t)
+                                 : interp<T, 2>(a.e_c, a.mc, xe, t, 0);
+            if (e0)
+              v1 += c;
+            else
+              v0 += c;
+          }
+        }
+      }
+      W[0][i][2] = W[0][i][1];
+      W[0][i][1] = W[0][i][0];
+      W[0][i][0] = e0 ? v1 : v0;
+      if (NORM) {
+        WB[i][2] = WB[i][1];
+        WB[i][1] = WB[i][0];
+        WB[i][0] = e0 ? v0 : v1;
+      }
+    }
+    // ---- residual of the start value on plane t-1 (convergence test)
+    if (NORM) {
+      const int zr = t - 1;
+      if (zr >= Z0 && zr < Z1) {
+        const T *L0 = lds;            // colour C0 values of plane t-1
+        const T *LB = lds + S * PL;   // colour C1 values of plane t-1
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          if (!outp[i]) continue;
+          const int e0 = (C0 + yy[i] + zr + DIM) & 1;
+          const size_t base = (size_t)zr * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {  // c = 0: the C0 element, 1: the C1 element
+            const int e = c == 0 ? e0 : 1 - e0;
+            const int x = xb[i] + e;
+            if (x >= m) continue;
+            const T self = c == 0 ? W[0][i][1] : WB[i][1];
+            const T own = c == 0 ? WB[i][1] : W[0][i][1];
+            const T *Ln = c == 0 ? LB : L0;
+            const T side = e ? Ln[rq[i]] : Ln[lq[i]];
+            T nb = e ? own : side;
+            nb += e ? side : own;
+            if (DIM == 3) {
+              nb += Ln[uq[i]];
+              nb += Ln[dq[i]];
+            }
+            nb += c == 0 ? WB[i][2] : W[0][i][2];
+            nb += c == 0 ? WB[i][0] : W[0][i][0];
+            const double r = double(a.f[base + x]) -
+                             (double(T(2 * DIM) * self) - double(nb)) * a.inv_h2;
+            acc += r * r;
+          }
+        }
+      }
+    }
+    // ---- stages 1..S
+    T newS[NS];
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+      const int zs = t - s;
+      const bool zin = zs >= 0 && zs < m;
+      const int cs = (C1 + s - 1) & 1;
+      const T *L = lds + (s - 1) * PL;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int es = (cs + yy[i] + zs + DIM) & 1;
+        const T own = W[s - 1][i][1];
+        const T side = es ? L[rq[i]] : L[lq[i]];
+        T nb = es ? own : side;  // x - 1
+        nb += es ? side : own;   // x + 1
+        if (DIM == 3) {
+          nb += L[uq[i]];        // y - 1
+          nb += L[dq[i]];        // y + 1
+        }
+        nb += W[s - 1][i][2];    // marching axis - 1
+        nb += W[s - 1][i][0];    // marching axis + 1
+        const int x = xb[i] + es;
+        T v = T(0);
+        if (live[i] && zin && yin[i] && x >= 0 && x < m) {
+          const size_t idx = (size_t)zs * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0) + x;
+          v = fma(h2, a.f[idx], nb) * inv2d;
+        }
+        if (s < S) {
+          W[s][i][2] = W[s][i][1];
+          W[s][i][1] = W[s][i][0];
+          W[s][i][0] = v;
+        } else {
+          newS[i] = v;
+        }
+      }
+    }
+    // ---- output plane t-S: last stage's colour from newS, the other from S-1
+    const int zo = t - S;
+    if (zo >= Z0 && zo < Z1) {
+      constexpr int CS = (C1 + S - 1) & 1;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        if (!outp[i]) continue;
+        const int es = (CS + yy[i] + zo + DIM) & 1;
+        const T o_new = newS[i], o_old = W[S - 1][i][1];
+        const size_t base = (size_t)zo * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+        const int x0 = xb[i];
+        a.u_out[base + x0] = es ? o_old : o_new;
+        if (x0 + 1 < m) a.u_out[base + x0 + 1] = es ? o_new : o_old;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      if (!live[i]) continue;
+#pragma unroll
+      for (int s = 0; s < S; ++s) lds[s * PL + q[i]] = W[s][i][0];
+      if (NORM) lds[S * PL + q[i]] = WB[i][0];
+    }
+    __syncthreads();
+  }
+  if (NORM) block_sum_store<NT>(acc, a.partials);
+}
+
+// ------------------------------------------------------------------------
+// Weighted-Jacobi pass: S full sweeps, every stage updates both elements of
+// every pair from the previous stage's values.
+// ------------------------------------------------------------------------
+template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
+__global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> a) {
+  if (a.active && *a.active == 0) return;
+  constexpr int NS = (EXP * EY + NT - 1) / NT;
+  constexpr int HP = (S + 1) / 2;  // halo in pairs (>= S points)
+  constexpr int H = 2 * HP;
+  constexpr int TXP = EXP - 2 * HP;
+  constexpr int TY = DIM == 3 ? EY - 2 * H : 1;
+  constexpr bool ZERO = (FL & F_ZERO_IN) != 0;
+  constexpr bool PRO = (FL & F_PROLONG) != 0;
+  constexpr bool NORM = (FL & F_NORM_IN) != 0;
+  constexpr int PL = EXP * EY;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);  // [S][2][PL]
+
+  const int m = a.m;
+  const int bid = xcd_remap(blockIdx.x, a.nblocks);
+  const int tx = bid % a.ntx;
+  const int rest = bid / a.ntx;
+  const int ty = DIM == 3 ? rest % a.nty : 0;
+  const int tzc = DIM == 3 ? rest / a.nty : rest;
+  const int X0 = tx * 2 * TXP;
+  const int Y0 = ty * TY;
+  const int Z0 = tzc * a.tz;
+  const int Z1 = min(Z0 + a.tz, m);
+  const size_t rowS = (size_t)m;
+  const size_t planeS = DIM == 3 ? (size_t)m * m : (size_t)m;
+  const T h2 = T(a.h2);
+  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
+  const T om = T(a.omega);
+  const T om1 = T(1.0 - a.omega);
+
+  int q[NS], xb[NS], yy[NS], lq[NS], rq[NS], uq[NS], dq[NS];
+  bool live[NS], yin[NS], outp[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    q[i] = threadIdx.x + NT * i;
+    live[i] = q[i] < PL;
+    const int p = q[i] % EXP, r = q[i] / EXP;
+    xb[i] = X0 - H + 2 * p;
+    yy[i] = DIM == 3 ? Y0 - H + r : 0;
+    yin[i] = DIM == 2 || (yy[i] >= 0 && yy[i] < m);
+    outp[i] = live[i] && yin[i] && p >= HP && p < HP + TXP &&
+              (DIM == 2 || (r >= H && r < H + TY)) && xb[i] < m;
+    const int rr = min(r, EY - 1);
+    lq[i] = rr * EXP + max(p - 1, 0);
+    rq[i] = rr * EXP + min(p + 1, EXP - 1);
+    uq[i] = max(rr - 1, 0) * EXP + p;
+    dq[i] = min(rr + 1, EY - 1) * EXP + p;
+  }
+
+  T W[S][NS][2][3];  // stage windows per element
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) W[s][i][e][0] = W[s][i][e][1] = W[s][i][e][2] = T(0);
+  double acc = 0.0;
+
+  for (int t = Z0 - S; t < Z1 + S; ++t) {
+    const bool tin = t >= 0 && t < m;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      T v[2] = {T(0), T(0)};
+      if (live[i] && tin && yin[i]) {
+        const size_t base = (size_t)t * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int x = xb[i] + e;
+          if (x < 0 || x >= m) continue;
+          if (!ZERO) v[e] = a.u_in[base + x];
+          if (PRO)
+            v[e] += DIM == 3 ? interp<T, 3>(a.e_c, a.mc, x, yy[i], t)
+                             : interp<T, 2>(a.e_c, a.mc, x, t, 0);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        W[0][i][e][2] = W[0][i][e][1];
+        W[0][i][e][1] = W[0][i][e][0];
+        W[0][i][e][0] = v[e];
+      }
+    }
+    if (NORM) {
+      const int zr = t - 1;
+      if (zr >= Z0 && zr < Z1) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          if (!outp[i]) continue;
+          const size_t base = (size_t)zr * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int x = xb[i] + e;
+            if (x >= m) continue;
+            const T *Ln = lds + (1 - e) * PL;  // the other element of neighbouring pairs
+            const T *Ls = lds + e * PL;        // same element (y neighbours)
+            const T own = W[0][i][1 - e][1];
+            const T side = e ? Ln[rq[i]] : Ln[lq[i]];
+            T nb = e ? own : side;
+            nb += e ? side : own;
+            if (DIM == 3) {
+              nb += Ls[uq[i]];
+              nb += Ls[dq[i]];
+            }
+            nb += W[0][i][e][2];
+            nb += W[0][i][e][0];
+            const double r = double(a.f[base + x]) -
+                             (double(T(2 * DIM) * W[0][i][e][1]) - double(nb)) * a.inv_h2;
+            acc += r * r;
+          }
+        }
+      }
+    }
+    T newS[NS][2];
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+      const int zs = t - s;
+      const bool zin = zs >= 0 && zs < m;
+      const T *L = lds + (s - 1) * 2 * PL;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const size_t base = (size_t)zs * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+        T nv[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const T *Ln = L + (1 - e) * PL;
+          const T *Ls = L + e * PL;
+          const T own = W[s - 1][i][1 - e][1];
+          const T side = e ? Ln[rq[i]] : Ln[lq[i]];
+          T nb = e ? own : side;
+          nb += e ? side : own;
+          if (DIM == 3) {
+            nb += Ls[uq[i]];
+            nb += Ls[dq[i]];
+          }
+          nb += W[s - 1][i][e][2];
+          nb += W[s - 1][i][e][0];
+          const int x = xb[i] + e;
+          T v = T(0);
+          if (live[i] && zin && yin[i] && x >= 0 && x < m)
+            v = om1 * W[s - 1][i][e][1] + om * (fma(h2, a.f[base + x], nb) * inv2d);
+          nv[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (s < S) {
+            W[s][i][e][2] = W[s][i][e][1];
+            W[s][i][e][1] = W[s][i][e][0];
+            W[s][i][e][0] = nv[e];
+          } else {
+            newS[i][e] = nv[e];
+          }
+        }
+      }
+    }
+    const int zo = t - S;
+    if (zo >= Z0 && zo < Z1) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        if (!outp[i]) continue;
+        const size_t base = (size_t)zo * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+        const int x0 = xb[i];
+        a.u_out[base + x0] = newS[i][0];
+        if (x0 + 1 < m) a.u_out[base + x0 + 1] = newS[i][1];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      if (!live[i]) continue;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        lds[(s * 2 + 0) * PL + q[i]] = W[s][i][0][0];
+        lds[(s * 2 + 1) * PL + q[i]] = W[s][i][1][0];
+      }
+    }
+    __syncthreads();
+  }
+  if (NORM) block_sum_store<NT>(acc, a.partials);
+}
+
+// ------------------------------------------------------------------------
+// Tile tables and dispatch.
+// ------------------------------------------------------------------------
+// Each entry: pairs per extended row, extended rows, threads.  Output tile:
+// TX = 2*(EXP - 2*halo_pairs), TY = EY - 2*halo (3D).
+#define GMG_RB3_S2(X) X(3, 2, 66, 30, 512) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 256)
+#define GMG_RB3_S4(X) X(3, 4, 68, 30, 512) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
+#define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
+#define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
+#define GMG_WJ3_S1(X) X(3, 1, 66, 18, 256) X(3, 1, 34, 18, 128)
+#define GMG_WJ3_S2(X) X(3, 2, 66, 22, 256) X(3, 2, 34, 20, 128)
+#define GMG_WJ2_S1(X) X(2, 1, 64, 1, 64) X(2, 1, 128, 1, 128)
+#define GMG_WJ2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
+
+namespace {
+struct TileRow {
+  int dim, s, exp_, ey, nt;
+};
+#define GMG_ROW(D, S, E, Y, N) {D, S, E, Y, N},
+const TileRow kRbTiles[] = {GMG_RB3_S2(GMG_ROW) GMG_RB3_S4(GMG_ROW) GMG_RB2_S2(GMG_ROW)
+                                GMG_RB2_S4(GMG_ROW)};
+const TileRow kWjTiles[] = {GMG_WJ3_S1(GMG_ROW) GMG_WJ3_S2(GMG_ROW) GMG_WJ2_S1(GMG_ROW)
+                                GMG_WJ2_S2(GMG_ROW)};
+#undef GMG_ROW
+
+template <int N>
+int find_rows(const TileRow (&tab)[N], int dim, int s, int *idx) {
+  int n = 0;
+  for (int i = 0; i < N; ++i)
+    if (tab[i].dim == dim && tab[i].s == s) idx[n++] = i;
+  return n;
+}
+}  // namespace
+
+int pass_variant_count(int dim, int stages, int wj) {
+  int idx[16];
+  return wj ? find_rows(kWjTiles, dim, stages, idx) : find_rows(kRbTiles, dim, stages, idx);
+}
+
+PassTile pass_variant(int dim, int stages, int wj, int v) {
+  int idx[16];
+  int n = wj ? find_rows(kWjTiles, dim, stages, idx) : find_rows(kRbTiles, dim, stages, idx);
+  PassTile t{0, 0, 0};
+  if (n == 0) return t;
+  if (v < 0 || v >= n) v = 0;
+  const TileRow &r = wj ? kWjTiles[idx[v]] : kRbTiles[idx[v]];
+  t.exp_ = r.exp_;
+  t.ey = r.ey;
+  t.nt = r.nt;
+  return t;
+}
+
+PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz) {
+  // halo in points: S for red-black, rounded up to a pair for Jacobi
+  const int hp = (stages + 1) / 2;
+  const int tx = 2 * (t.exp_ - 2 * hp);
+  PassGeom g;
+  g.ntx = (m + tx - 1) / tx;
+  if (dim == 3) {
+    const int ty = t.ey - 4 * hp;
+    g.nty = (m + ty - 1) / ty;
+  } else {
+    g.nty = 1;
+  }
+  g.tz = tz > 0 ? tz : m;
+  if (g.tz > m) g.tz = m;
+  g.ntz = (m + g.tz - 1) / g.tz;
+  g.nblocks = g.ntx * g.nty * g.ntz;
+  return g;
+}
+
+namespace {
+template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
+hipError_t run_rb(PassArgs<T> a, hipStream_t st) {
+  const size_t lds = sizeof(T) * EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0));
+  auto k = k_rb_pass<T, DIM, S, EXP, EY, NT, FL>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(NT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
+hipError_t run_wj(PassArgs<T> a, hipStream_t st) {
+  const size_t lds = sizeof(T) * EXP * EY * 2 * S;
+  auto k = k_wj_pass<T, DIM, S, EXP, EY, NT, FL>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(NT), lds, st, a);
+  return hipGetLastError();
+}
+
+// The fused-flag combinations a cycle uses.
+#define GMG_FLAG_SWITCH(RUN, T, D, S, E, Y, N)                                            \
+  switch (flags) {                                                                     \
+    case 0: return RUN<T, D, S, E, Y, N, 0>(a, st);                                    \
+    case F_ZERO_IN: return RUN<T, D, S, E, Y, N, F_ZERO_IN>(a, st);                    \
+    case F_PROLONG: return RUN<T, D, S, E, Y, N, F_PROLONG>(a, st);                    \
+    case F_NORM_IN: return RUN<T, D, S, E, Y, N, F_NORM_IN>(a, st);                    \
+    case F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_BLACK_FIRST>(a, st);            \
+    case F_ZERO_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_ZERO_IN | F_BLACK_FIRST>(a, st); \
+    case F_PROLONG | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST>(a, st); \
+    case F_NORM_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_NORM_IN | F_BLACK_FIRST>(a, st); \
+    default: return hipErrorInvalidValue;                                              \
+  }
+}  // namespace
+
+template <typename T>
+hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<T> a,
+                          hipStream_t st) {
+  const PassTile t = pass_variant(dim, stages, 0, variant);
+  if (t.nt == 0) return hipErrorInvalidValue;
+#define GMG_TRY(D, S, E, Y, N)                                       \
+  if (dim == D && stages == S && t.exp_ == E && t.ey == Y && t.nt == N) { \
+    GMG_FLAG_SWITCH(run_rb, T, D, S, E, Y, N)                         \
+  }
+  GMG_RB3_S2(GMG_TRY) GMG_RB3_S4(GMG_TRY) GMG_RB2_S2(GMG_TRY) GMG_RB2_S4(GMG_TRY)
+#undef GMG_TRY
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_wj_pass(int dim, int sweeps, int flags, int variant, PassArgs<T> a,
+                          hipStream_t st) {
+  const PassTile t = pass_variant(dim, sweeps, 1, variant);
+  if (t.nt == 0) return hipErrorInvalidValue;
+  flags &= ~F_BLACK_FIRST;
+#define GMG_TRY(D, S, E, Y, N)                                       \
+  if (dim == D && sweeps == S && t.exp_ == E && t.ey == Y && t.nt == N) { \
+    GMG_FLAG_SWITCH(run_wj, T, D, S, E, Y, N)                         \
+  }
+  GMG_WJ3_S1(GMG_TRY) GMG_WJ3_S2(GMG_TRY) GMG_WJ2_S1(GMG_TRY) GMG_WJ2_S2(GMG_TRY)
+#undef GMG_TRY
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_rb_pass<double>(int, int, int, int, PassArgs<double>, hipStream_t);
+template hipError_t launch_rb_pass<float>(int, int, int, int, PassArgs<float>, hipStream_t);
+template hipError_t launch_wj_pass<double>(int, int, int, int, PassArgs<double>, hipStream_t);
+template hipError_t launch_wj_pass<float>(int, int, int, int, PassArgs<float>, hipStream_t);
+
+}  // namespace gmg

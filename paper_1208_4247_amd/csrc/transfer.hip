@@ -1,0 +1,487 @@
+// transfer.hip -- residual, full-weighting restriction, norm reduction and the
+// solve-state update for the multigrid library (gfx950).
+//
+// Residual: r = f - A u with (A u)_p = (2d u_p - sum of neighbours) / h^2
+// (Sec. 4, eq. residual_2D and its 3D count).  Restriction: full weighting,
+// the tensor product of [1/4, 1/2, 1/4] (Algorithm 1's f_{l+1} = R r_l with
+// the standard weights).  Norm: Euclidean norm of the residual (Sec. 4, eq.
+// Inner_product2D, with the square root), summed in a fixed order so that the
+// stop decision is reproducible.
+#include "gmg_internal.h"
+
+namespace gmg {
+
+__device__ __forceinline__ int xcd_remap_t(int bid, int n) {
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int per = n >> 3, rem = n & 7;
+  return xcd * per + min(xcd, rem) + loc;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld0(const T *__restrict__ p, int m, int x, int y, int z, int dim) {
+  if (x < 0 || y < 0 || x >= m || y >= m) return T(0);
+  if (dim == 3) {
+    if (z < 0 || z >= m) return T(0);
+    return p[((size_t)z * m + y) * m + x];
+  }
+  return p[(size_t)y * m + x];
+}
+
+// ------------------------------------------------------------------------
+// Residual + full weighting: the residual is formed in LDS one fine plane at
+// a time and reduced to coarse points without ever being stored.
+// Workgroup: a CX x CY block of coarse columns (3D), marching over coarse z.
+// ------------------------------------------------------------------------
+template <typename T, int DIM, int CX, int CY, int NT>
+__global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> a, int ncx, int ncy, int czc,
+                                                 int nblocks) {
+  if (a.active && *a.active == 0) return;
+  const int m = a.m, mc = a.mc;
+  const int bid = xcd_remap_t(blockIdx.x, nblocks);
+  const int bx = bid % ncx;
+  const int rest = bid / ncx;
+  const int by = DIM == 3 ? rest % ncy : 0;
+  const int bz = DIM == 3 ? rest / ncy : rest;
+  // coarse ranges
+  const int A0 = bx * CX;
+  const int B0 = DIM == 3 ? by * CY : 0;
+  const int C0 = bz * czc;  // coarse planes (3D) / rows (2D) of this block
+  const int C1 = min(C0 + czc, mc);
+  // fine residual region (storage): x in [2A0, 2A0 + 2CX], y likewise (3D)
+  constexpr int RX = 2 * CX + 1;
+  constexpr int RY = DIM == 3 ? 2 * CY + 1 : 1;
+  constexpr int UX = RX + 2;
+  constexpr int UY = DIM == 3 ? RY + 2 : 1;
+  __shared__ T su[3][UY * UX];  // fine u planes z-1, z, z+1 (ring)
+  __shared__ T sr[RY * RX];     // fine residual of the current plane
+  const T inv_h2 = T(a.inv_h2);
+  const T two_d = T(2 * DIM);
+  const int xF0 = 2 * A0 - 1;           // u region origin (fine storage)
+  const int yF0 = DIM == 3 ? 2 * B0 - 1 : 0;
+  const size_t planeS = DIM == 3 ? (size_t)m * m : (size_t)m;
+
+  // coarse point owned by this thread (one per thread in the restriction step)
+  const int cxl = threadIdx.x % CX;
+  const int cyl = DIM == 3 ? (threadIdx.x / CX) % CY : 0;
+  const bool cown = threadIdx.x < CX * (DIM == 3 ? CY : 1);
+  const int cx = A0 + cxl, cy = B0 + cyl;
+  T acc_cur = T(0), acc_next = T(0);
+
+  // fine planes needed: 2*C0 .. 2*C1 (storage), u planes one more each side
+  const int zf_begin = 2 * C0, zf_end = 2 * C1;  // inclusive range of r planes
+  auto load_u_plane = [&](int slot, int zf) {
+    for (int q = threadIdx.x; q < UY * UX; q += NT) {
+      const int ux = q % UX, uy = q / UX;
+      const int x = xF0 + ux, y = DIM == 3 ? yF0 + uy : zf;
+      T v = T(0);
+      if (DIM == 3)
+        v = ld0(a.u, m, x, y, zf, 3);
+      else
+        v = ld0(a.u, m, x, zf, 0, 2);
+      su[slot][q] = v;
+    }
+  };
+  // ring: slot of fine plane z is (z + 3) % 3 (z may be -1)
+  load_u_plane((zf_begin - 1 + 3) % 3, zf_begin - 1);
+  load_u_plane((zf_begin + 3) % 3, zf_begin);
+  for (int zf = zf_begin; zf <= zf_end; ++zf) {
+    load_u_plane((zf + 1 + 3) % 3, zf + 1);
+    __syncthreads();
+    const T *um = su[(zf - 1 + 3) % 3];
+    const T *u0 = su[(zf + 3) % 3];
+    const T *up = su[(zf + 1 + 3) % 3];
+    for (int q = threadIdx.x; q < RY * RX; q += NT) {
+      const int rx = q % RX, ry = q / RX;
+      const int x = 2 * A0 + rx, y = DIM == 3 ? 2 * B0 + ry : zf;
+      T r = T(0);
+      if (x < m && y < m && zf < m) {
+        const int c = (ry + (DIM == 3 ? 1 : 0)) * UX + rx + 1;  // centre in the u tile
+        T nb = u0[c - 1] + u0[c + 1];
+        if (DIM == 3) {
+          nb += u0[c - UX];
+          nb += u0[c + UX];
+          nb += um[c];
+          nb += up[c];
+        } else {
+          nb += um[c];
+          nb += up[c];
+        }
+        const T fv = DIM == 3 ? a.f[(size_t)zf * planeS + (size_t)y * m + x]
+                              : a.f[(size_t)zf * m + x];
+        r = fv - (two_d * u0[c] - nb) * inv_h2;
+      }
+      sr[q] = r;
+    }
+    __syncthreads();
+    // weight of this fine plane for coarse planes: zf = 2c+1 -> 1/2 for c;
+    // zf = 2c+2 -> 1/4 for c and c+1.  In 2D the "plane" is a fine row.
+    if (cown && cx < mc && (DIM == 2 || cy < mc)) {
+      const int lx = 2 * cxl + 1;  // fine centre column in the r tile
+      T sxy;
+      if (DIM == 3) {
+        const int ly = 2 * cyl + 1;
+        const T *r0 = sr + (ly - 1) * RX, *r1 = sr + ly * RX, *r2 = sr + (ly + 1) * RX;
+        const T a0 = T(0.25) * r0[lx - 1] + T(0.5) * r0[lx] + T(0.25) * r0[lx + 1];
+        const T a1 = T(0.25) * r1[lx - 1] + T(0.5) * r1[lx] + T(0.25) * r1[lx + 1];
+        const T a2 = T(0.25) * r2[lx - 1] + T(0.5) * r2[lx] + T(0.25) * r2[lx + 1];
+        sxy = T(0.25) * a0 + T(0.5) * a1 + T(0.25) * a2;
+      } else {
+        sxy = T(0.25) * sr[lx - 1] + T(0.5) * sr[lx] + T(0.25) * sr[lx + 1];
+      }
+      if (zf & 1) {
+        acc_cur += T(0.5) * sxy;
+      } else {
+        const int c = zf / 2 - 1;  // coarse plane completed by this fine plane
+        if (c >= C0) {
+          acc_cur += T(0.25) * sxy;
+          const size_t o = DIM == 3 ? ((size_t)c * mc + cy) * mc + cx : (size_t)c * mc + cx;
+          a.fc[o] = acc_cur;
+        }
+        acc_cur = T(0.25) * sxy;  // contribution to coarse plane c+1
+      }
+    }
+    __syncthreads();
+  }
+  (void)acc_next;
+}
+
+// ------------------------------------------------------------------------
+// Residual (and/or per-block sums of its square), one thread per point.
+// ------------------------------------------------------------------------
+template <typename T, int DIM, int NT>
+__global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a) {
+  if (a.active && *a.active == 0) return;
+  const int m = a.m;
+  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
+  double acc = 0.0;
+  const T inv_h2 = T(a.inv_h2);
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
+    const int x = (int)(p % m);
+    const size_t rest = p / m;
+    const int y = (int)(rest % m);
+    const int z = DIM == 3 ? (int)(rest / m) : 0;
+    T nb;
+    T c;
+    if (DIM == 3) {
+      c = a.u[p];
+      nb = ld0(a.u, m, x - 1, y, z, 3) + ld0(a.u, m, x + 1, y, z, 3);
+      nb += ld0(a.u, m, x, y - 1, z, 3);
+      nb += ld0(a.u, m, x, y + 1, z, 3);
+      nb += ld0(a.u, m, x, y, z - 1, 3);
+      nb += ld0(a.u, m, x, y, z + 1, 3);
+    } else {
+      c = a.u[p];
+      nb = ld0(a.u, m, x - 1, y, 0, 2) + ld0(a.u, m, x + 1, y, 0, 2);
+      nb += ld0(a.u, m, x, y - 1, 0, 2);
+      nb += ld0(a.u, m, x, y + 1, 0, 2);
+    }
+    const T r = a.f[p] - (T(2 * DIM) * c - nb) * inv_h2;
+    if (a.r) a.r[p] = r;
+    acc += double(r) * double(r);
+  }
+  if (a.partials) {
+    __shared__ double red[NT / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w];
+      a.partials[blockIdx.x] = s;
+    }
+  }
+}
+
+int residual_blocks(int dim, int m) {
+  const size_t N = dim == 3 ? (size_t)m * m * m : (size_t)m * m;
+  size_t b = (N + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// ------------------------------------------------------------------------
+// Refinement step: x_out = x + e (FP64), r32 = float(f - A x_out), norm
+// partials.  Both x and e are read at the neighbours, so x_out never aliases
+// x (the caller ping-pongs).
+// ------------------------------------------------------------------------
+template <int DIM, int NT>
+__global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
+  if (a.active && *a.active == 0) return;
+  const int m = a.m;
+  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
+  double acc = 0.0;
+  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
+    const int x = (int)(p % m);
+    const size_t rest = p / m;
+    const int y = (int)(rest % m);
+    const int z = DIM == 3 ? (int)(rest / m) : 0;
+    auto val = [&](int i, int j, int k) -> double {
+      if (i < 0 || j < 0 || i >= m || j >= m) return 0.0;
+      if (DIM == 3 && (k < 0 || k >= m)) return 0.0;
+      const size_t o = DIM == 3 ? ((size_t)k * m + j) * m + i : (size_t)j * m + i;
+      double v = a.x[o];
+      if (a.e) v += double(a.e[o]);
+      return v;
+    };
+    const double c = val(x, y, z);
+    double nb = val(x - 1, y, z) + val(x + 1, y, z);
+    nb += val(x, y - 1, z);
+    nb += val(x, y + 1, z);
+    if (DIM == 3) {
+      nb += val(x, y, z - 1);
+      nb += val(x, y, z + 1);
+    }
+    const double r = a.f[p] - (double(2 * DIM) * c - nb) * a.inv_h2;
+    if (a.e) a.x_out[p] = c;
+    a.r32[p] = float(r);
+    acc += r * r;
+  }
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    a.partials[blockIdx.x] = s;
+  }
+}
+
+int ir_blocks(int dim, int m) { return residual_blocks(dim, m); }
+
+// ------------------------------------------------------------------------
+// Fixed-order reduction of per-block partial sums; updates the solve state
+// (Algorithm 3's while test).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double sum_partials(const double *p, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) s += p[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  return s;
+}
+
+__global__ void __launch_bounds__(64) k_finalize(const double *partials, int n, SolveState *st) {
+  if (st->active == 0) return;
+  const double tot = sum_partials(partials, n);
+  if (threadIdx.x == 0) {
+    const double res = sqrt(tot);
+    if (st->res0 < 0.0) st->res0 = res;
+    st->res = res;
+    const double res0 = st->res0;
+    if (!isfinite(res)) {
+      st->status = -3;
+      st->active = 0;
+    } else if (!(res > st->rtol * res0)) {
+      st->status = 0;
+      st->active = 0;
+    } else if (res > 1e3 * res0 && st->iter > 0) {
+      st->status = -4;
+      st->active = 0;
+    } else if (st->iter >= st->maxit) {
+      st->status = 1;
+      st->active = 0;
+    } else {
+      st->iter += 1;  // admit one more cycle
+    }
+  }
+}
+
+__global__ void k_reduce_norm(const double *partials, int n, double *out) {
+  const double tot = sum_partials(partials, n);
+  if (threadIdx.x == 0) *out = sqrt(tot);
+}
+
+__global__ void k_state_init(SolveState *st, int maxit, double rtol, double res0) {
+  if (threadIdx.x == 0) {
+    st->active = 1;
+    st->iter = 0;
+    st->maxit = maxit;
+    st->status = 0;
+    st->rtol = rtol;
+    st->res0 = res0;
+    st->res = 0.0;
+    st->pad = 0.0;
+  }
+}
+
+__global__ void k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n2,
+                       const unsigned char *__restrict__ src_tail,
+                       unsigned char *__restrict__ dst_tail, size_t tail, const int *active) {
+  if (active && *active == 0) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+  if (blockIdx.x == 0 && threadIdx.x < tail) dst_tail[threadIdx.x] = src_tail[threadIdx.x];
+}
+
+__global__ void k_fill_zero(unsigned char *dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = 0;
+}
+
+// ------------------------------------------------------------------------
+// out = in + P e (in NULL = zero), one thread per fine point.  Used when a
+// level has no post-smoothing sweep (nu2 = 0); in may alias out.
+// ------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_prolong_add(const T *in, const T *__restrict__ ec, T *out,
+                                                     int m, int mc, const int *active) {
+  if (active && *active == 0) return;
+  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
+  for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+    const int x = (int)(p % m);
+    const size_t rest = p / m;
+    const int y = (int)(rest % m);
+    const int z = DIM == 3 ? (int)(rest / m) : 0;
+    auto axis = [](int v, int *c, T *w) -> int {
+      if (v & 1) {
+        c[0] = (v - 1) >> 1;
+        w[0] = T(1);
+        return 1;
+      }
+      c[0] = (v >> 1) - 1;
+      c[1] = v >> 1;
+      w[0] = w[1] = T(0.5);
+      return 2;
+    };
+    int cx[2], cy[2], cz[2] = {0, 0};
+    T wx[2], wy[2], wz[2] = {T(1), T(1)};
+    const int nx = axis(x, cx, wx), ny = axis(y, cy, wy);
+    const int nz = DIM == 3 ? axis(z, cz, wz) : 1;
+    T s = T(0);
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const int a = cx[i], b = cy[j], c = cz[k];
+          if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) continue;
+          const size_t o = DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a;
+          s += (DIM == 3 ? wx[i] * wy[j] * wz[k] : wx[i] * wy[j]) * ec[o];
+        }
+    out[p] = (in ? in[p] : T(0)) + s;
+  }
+}
+
+// x += e (FP64 += FP32), in place.
+__global__ void __launch_bounds__(256) k_axpy_f32(double *x, const float *__restrict__ e, size_t n,
+                                                  const int *active) {
+  if (active && *active == 0) return;
+  for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (size_t)gridDim.x * 256)
+    x[p] += double(e[p]);
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+namespace {
+constexpr int kRX3 = 32, kRY3 = 8, kRX2 = 64;
+}
+
+template <typename T>
+hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s) {
+  if (dim == 3) {
+    const int ncx = (a.mc + kRX3 - 1) / kRX3, ncy = (a.mc + kRY3 - 1) / kRY3;
+    const int czc = a.mc < 16 ? a.mc : 16;
+    const int ncz = (a.mc + czc - 1) / czc;
+    const int nb = ncx * ncy * ncz;
+    hipLaunchKernelGGL((k_restrict<T, 3, kRX3, kRY3, 256>), dim3(nb), dim3(256), 0, s, a, ncx,
+                       ncy, czc, nb);
+  } else {
+    const int ncx = (a.mc + kRX2 - 1) / kRX2;
+    const int czc = a.mc < 32 ? a.mc : 32;
+    const int ncz = (a.mc + czc - 1) / czc;
+    const int nb = ncx * ncz;
+    hipLaunchKernelGGL((k_restrict<T, 2, kRX2, 1, 128>), dim3(nb), dim3(128), 0, s, a, ncx, 1,
+                       czc, nb);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual(int dim, ResidArgs<T> a, hipStream_t s) {
+  const int nb = a.nblocks > 0 ? a.nblocks : residual_blocks(dim, a.m);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_residual<T, 3, 256>), dim3(nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_residual<T, 2, 256>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s) {
+  const int nb = a.nblocks > 0 ? a.nblocks : ir_blocks(dim, a.m);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_ir_step<3, 256>), dim3(nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_ir_step<2, 256>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int n, SolveState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, n, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const double *partials, int n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(64), 0, s, partials, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(SolveState *st, int maxit, double rtol, double res0, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, rtol, res0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, const int *active,
+                       hipStream_t s) {
+  const size_t n2 = bytes / 16, tail = bytes % 16;
+  size_t nb = (n2 + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const double2 *)src,
+                     (double2 *)dst, n2, (const unsigned char *)src + n2 * 16,
+                     (unsigned char *)dst + n2 * 16, tail, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s) {
+  size_t nb = (bytes + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, (unsigned char *)dst,
+                     bytes);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(int dim, int m, int mc, const T *in, const T *ec, T *out,
+                              const int *active, hipStream_t s) {
+  const int nb = residual_blocks(dim, m);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+  else
+    hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_f32(double *x, const float *e, size_t n, const int *active, hipStream_t s) {
+  size_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_axpy_f32, dim3((unsigned)nb), dim3(256), 0, s, x, e, n, active);
+  return hipGetLastError();
+}
+
+template hipError_t launch_prolong_add<double>(int, int, int, const double *, const double *,
+                                               double *, const int *, hipStream_t);
+template hipError_t launch_prolong_add<float>(int, int, int, const float *, const float *, float *,
+                                              const int *, hipStream_t);
+template hipError_t launch_restrict<double>(int, RestrictArgs<double>, hipStream_t);
+template hipError_t launch_restrict<float>(int, RestrictArgs<float>, hipStream_t);
+template hipError_t launch_residual<double>(int, ResidArgs<double>, hipStream_t);
+template hipError_t launch_residual<float>(int, ResidArgs<float>, hipStream_t);
+
+}  // namespace gmg

@@ -1,0 +1,131 @@
+"""Thin torch-facing wrapper of the C ABI: torch supplies device memory (the
+workspace and the grids) and the stream; the library does all the work.
+
+    plan = Plan(dim=3, levels=8)                 # 255^3, RB-GS V(2,2), FP64
+    status, iters, relres = plan.solve(u, f, rtol=1e-10)
+
+Grids are torch tensors on the current CUDA (HIP) device, contiguous, shape
+(m,)*dim with the last axis x (fastest), float64 (float32 for the FP32
+primitives).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import capi
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    def __init__(self, dim: int, levels: int, smoother: str = "rbgs", nu1: int = 2, nu2: int = 2,
+                 omega: float = 0.0, precision: str = "fp64", inner_cycles: int = 1,
+                 flags: int = 0):
+        L = capi.lib()
+        cfg = capi.config_default(dim, levels)
+        cfg.smoother = {"rbgs": capi.GMG_SMOOTH_RBGS, "wj": capi.GMG_SMOOTH_WJ}[smoother]
+        cfg.nu1, cfg.nu2 = int(nu1), int(nu2)
+        cfg.omega = float(omega)
+        cfg.precision = {"fp64": capi.GMG_FP64, "mixed": capi.GMG_MIXED_FP32_IR}[precision]
+        cfg.inner_cycles = int(inner_cycles)
+        cfg.flags = int(flags)
+        self.cfg = cfg
+        self.dim, self.levels = dim, levels
+        self.m0 = (1 << levels) - 1
+        s, nbytes = capi.workspace_bytes(cfg)
+        capi.check(s, "gmg_setup(size query)")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        n = ctypes.c_size_t(nbytes)
+        plan = ctypes.c_void_p()
+        s = L.gmg_setup(ctypes.byref(cfg), 1, None, None, _ptr(self.workspace), ctypes.byref(n),
+                        _stream(), ctypes.byref(plan))
+        capi.check(s, "gmg_setup")
+        self._plan = plan
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_plan", None):
+            capi.lib().gmg_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._plan
+
+    def side(self, level: int) -> int:
+        return capi.lib().gmg_level_side(self._plan, 0, int(level))
+
+    # ------------------------------------------------------------------
+    def vcycle(self, u: torch.Tensor, f: torch.Tensor) -> None:
+        capi.check(capi.lib().gmg_vcycle(self._plan, _ptr(u), _ptr(f)), "gmg_vcycle")
+
+    def solve(self, u: torch.Tensor, f: torch.Tensor, rtol: float = 1e-10, maxit: int = 100,
+              res0: float | None = None):
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        r0 = ctypes.byref(ctypes.c_double(res0)) if res0 is not None else None
+        s = capi.lib().gmg_solve(self._plan, _ptr(u), _ptr(f), float(rtol), int(maxit), r0,
+                                 ctypes.byref(it), ctypes.byref(rel))
+        capi.check(s, "gmg_solve")
+        return s, it.value, rel.value
+
+    def set_tile(self, level: int, stages: int, variant: int, tz: int = 0) -> None:
+        capi.check(capi.lib().gmg_plan_set_tile(self._plan, int(level), int(stages), int(variant),
+                                                int(tz)), "gmg_plan_set_tile")
+
+    def tile_variants(self, stages: int) -> int:
+        return capi.lib().gmg_tile_variant_count(self.dim, self.cfg.smoother, int(stages))
+
+    # ---------------------------------------------------------- primitives
+    def op_smooth(self, level, nsweeps, backward, u_in, f, e_coarse, u_out, want_norm=False):
+        dt = capi.GMG_F64 if f.dtype == torch.float64 else capi.GMG_F32
+        nrm = ctypes.c_double(0.0)
+        s = capi.lib().gmg_op_smooth(self._plan, int(level), dt, int(nsweeps), int(bool(backward)),
+                                     _ptr(u_in), _ptr(f), _ptr(e_coarse), _ptr(u_out),
+                                     ctypes.byref(nrm) if want_norm else None)
+        capi.check(s, "gmg_op_smooth")
+        return nrm.value if want_norm else None
+
+    def op_restrict_residual(self, level, u, f, fc):
+        dt = capi.GMG_F64 if f.dtype == torch.float64 else capi.GMG_F32
+        capi.check(capi.lib().gmg_op_restrict_residual(self._plan, int(level), dt, _ptr(u), _ptr(f),
+                                                       _ptr(fc)), "gmg_op_restrict_residual")
+
+    def op_residual(self, level, u, f, r=None, want_norm=True):
+        dt = capi.GMG_F64 if f.dtype == torch.float64 else capi.GMG_F32
+        nrm = ctypes.c_double(0.0)
+        capi.check(capi.lib().gmg_op_residual(self._plan, int(level), dt, _ptr(u), _ptr(f), _ptr(r),
+                                              ctypes.byref(nrm) if want_norm else None),
+                   "gmg_op_residual")
+        return nrm.value if want_norm else None
+
+    # ------------------------------------------------------------ profile
+    def profile(self):
+        L = capi.lib()
+        out = {}
+        for i in range(L.gmg_profile_count(self._plan)):
+            st = capi.GmgKernelStat()
+            capi.check(L.gmg_profile_get(self._plan, i, ctypes.byref(st)), "gmg_profile_get")
+            out[st.name.decode()] = dict(launches=st.launches, ms=st.total_ms, bytes=st.alg_bytes)
+        return out
+
+    def profile_reset(self):
+        capi.check(capi.lib().gmg_profile_reset(self._plan), "gmg_profile_reset")

@@ -1,0 +1,104 @@
+"""Host-only checks of the C ABI: the library loads, exports every entry
+point the public header declares, and rejects invalid arguments before any
+HIP call (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_1208_4247_amd import capi as c
+
+    if not os.path.exists(c.LIB_PATH):
+        from paper_1208_4247_amd import build
+
+        build.build()
+    c.lib()
+    return c
+
+
+def declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "gmg.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmg_[a-z_0-9]+)\s*\(", hdr)))
+
+
+def test_every_declared_symbol_is_exported(capi):
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    lib = capi.lib()
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(capi.EXPORTED)
+
+
+def test_status_strings(capi):
+    for s, name in [(0, "GMG_OK"), (1, "GMG_NOT_CONVERGED"), (-1, "GMG_ERR_INVALID_ARG"),
+                    (-2, "GMG_ERR_WORKSPACE"), (-5, "GMG_ERR_HIP"), (-6, "GMG_ERR_UNSUPPORTED")]:
+        assert capi.status_string(s) == name
+
+
+def test_config_default(capi):
+    c = capi.config_default(3, 8)
+    assert (c.dim, c.levels, c.nu1, c.nu2, c.smoother, c.precision, c.inner_cycles) == (3, 8, 2, 2, 0, 0, 1)
+
+
+@pytest.mark.parametrize("field,value", [("dim", 1), ("dim", 4), ("levels", 0), ("levels", 11),
+                                         ("nu1", -1), ("nu2", 9), ("inner_cycles", 0),
+                                         ("precision", 7), ("smoother", 3)])
+def test_invalid_config_rejected_without_gpu(capi, field, value):
+    c = capi.config_default(3, 5)
+    setattr(c, field, value)
+    s, n = capi.workspace_bytes(c)
+    assert s == capi.GMG_ERR_INVALID_ARG
+
+
+def test_zero_sweeps_rejected(capi):
+    c = capi.config_default(2, 5)
+    c.nu1 = c.nu2 = 0
+    assert capi.workspace_bytes(c)[0] == capi.GMG_ERR_INVALID_ARG
+
+
+def test_wj_omega_range(capi):
+    c = capi.config_default(2, 5)
+    c.smoother = capi.GMG_SMOOTH_WJ
+    c.omega = 1.5
+    assert capi.workspace_bytes(c)[0] == capi.GMG_ERR_INVALID_ARG
+    c.omega = 0.8
+    assert capi.workspace_bytes(c)[0] == capi.GMG_OK
+
+
+def test_workspace_size_model(capi):
+    """Workspace ~ coarse u, w, f (3 * N0 / (2^d - 1)) + one level-0
+    ping-pong array (N0) + small fixed state, the paper's memory model
+    (Sec. 4 remark on space complexity) plus the pre-smoothed copy."""
+    for d, L in [(2, 10), (3, 8)]:
+        c = capi.config_default(d, L)
+        s, n = capi.workspace_bytes(c)
+        assert s == 0
+        N0 = ((1 << L) - 1) ** d
+        model = 8 * (N0 + 3 * N0 / (2 ** d - 1))
+        assert 0.9 * model < n < 1.1 * model + (1 << 20), (n, model)
+
+
+def test_setup_null_checks(capi):
+    lib = capi.lib()
+    c = capi.config_default(3, 5)
+    n = ctypes.c_size_t(0)
+    assert lib.gmg_setup(ctypes.byref(c), 1, None, None, None, None, None, None) == capi.GMG_ERR_INVALID_ARG
+    assert lib.gmg_setup(ctypes.byref(c), 0, None, None, None, ctypes.byref(n), None, None) == capi.GMG_ERR_INVALID_ARG
+    # a workspace that is too small is refused before any device access
+    n.value = 16
+    plan = ctypes.c_void_p()
+    assert lib.gmg_setup(ctypes.byref(c), 1, None, None, ctypes.c_void_p(4096), ctypes.byref(n), None,
+                         ctypes.byref(plan)) == capi.GMG_ERR_WORKSPACE
+    assert lib.gmg_solve(None, None, None, 1e-10, 10, None, None, None) == capi.GMG_ERR_INVALID_ARG
+    assert lib.gmg_vcycle(None, None, None) == capi.GMG_ERR_INVALID_ARG
+    assert lib.gmg_destroy(None) == capi.GMG_ERR_INVALID_ARG
+    assert lib.gmg_plan_workspace_bytes(None) == 0
+    assert lib.gmg_level_side(None, 0, 0) == -1
