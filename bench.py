@@ -29,6 +29,7 @@ WORKLOADS = {
     "poisson2d_127_sine_fp64_v22": dict(dim=2, L=7, rhs="sine", prec="fp64"),
     "poisson3d_511_uniform_fp64_v22": dict(dim=3, L=9, rhs="uniform", prec="fp64"),
     "poisson3d_511_uniform_mixed_v22": dict(dim=3, L=9, rhs="uniform", prec="mixed"),
+    "batch256_uneven_fp64_v22": dict(dim=0, L=0, rhs="batch", prec="fp64"),
 }
 DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
 
@@ -78,6 +79,50 @@ def cpu_baseline(spec, f, budget_s=30.0):
                 % (ncyc, t))
 
 
+def bench_batch(args):
+    """256 independent problems of uneven size (128 2D with side 2^k-1,
+    k ~ U{6..10}; 128 3D with k ~ U{5..7}; U[-1,1] right-hand sides, seed 4),
+    FP64 V(2,2) RB-GS to 1e-10 each; value = total unknowns / solve time."""
+    import torch
+
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd import workloads as wl
+    from paper_1208_4247_amd.solver import BatchPlan
+
+    probs = wl.batch_problems(4)
+    N = sum(m ** d for d, m in probs)
+    torch.cuda.set_device(0)
+    fs = [torch.from_numpy(wl.batch_rhs(4, q, d, m)).cuda() for q, (d, m) in enumerate(probs)]
+    us = [torch.zeros_like(f) for f in fs]
+    flags = args.flags | capi.GMG_USE_GRAPH
+    plan = BatchPlan([(d, (m + 1).bit_length() - 1) for d, m in probs], flags=flags)
+    for _ in range(args.warmup):
+        for u in us:
+            u.zero_()
+        plan.solve(us, fs)
+    torch.cuda.synchronize()
+    t_total = 0.0
+    for _ in range(args.steps):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, its, rels, sts = plan.solve(us, fs)
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+    value = N / (t_total / args.steps)
+    line = {
+        "metric": "fine-grid unknowns/s to 1e-10 rel. residual (batch of 256 uneven problems)",
+        "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch256_uneven_fp64_v22", "problems": len(probs),
+                   "unknowns": N, "max_cycles": max(its), "min_cycles": min(its)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +131,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver runs every level of one "
@@ -98,6 +144,8 @@ def main():
     from paper_1208_4247_amd.solver import Plan
 
     spec = WORKLOADS[args.workload]
+    if spec["rhs"] == "batch":
+        return bench_batch(args)
     d, L = spec["dim"], spec["L"]
     m = (1 << L) - 1
     N = m ** d
@@ -105,16 +153,23 @@ def main():
     torch.cuda.set_device(0)
     f = torch.from_numpy(f_host).cuda()
     u = torch.zeros_like(f)
-    plan = Plan(d, L, precision=spec["prec"], flags=args.flags | capi.GMG_PROFILE)
+    flags = args.flags | capi.GMG_PROFILE
+    if not args.no_autotune:
+        flags |= capi.GMG_AUTOTUNE
+    plan = Plan(d, L, precision=spec["prec"], flags=flags)
     print("# workload %s: %d^%d, plan workspace %.1f MB" % (args.workload, m, d,
           plan.workspace.numel() / 1e6), flush=True)
 
-    iters = []
+    # warm-up (the first solve also runs the tile autotuner)
     for _ in range(args.warmup):
         u.zero_()
         st, it, rel = plan.solve(u, f, rtol=1e-10)
     torch.cuda.synchronize()
+    # timed region: hipEvents only around the level-0 smoothing passes
+    smoothers = ["smooth_pre_l0", "smooth_post_l0"]
+    plan.profile_only(smoothers)
     plan.profile_reset()
+    iters = []
     t_total = 0.0
     for k in range(args.steps):
         u.zero_()
@@ -127,15 +182,26 @@ def main():
     prof = plan.profile()
     ms_per_step = 1e3 * t_total / args.steps
     value = N / (t_total / args.steps)
-    print("# iters %s relres %.3e status %d" % (sorted(set(iters)), rel, st), flush=True)
-    for k, v in prof.items():
-        if v["launches"]:
-            print("#   %-22s launches %6d  avg %8.3f us  alg %8.1f GB/s" % (
-                k, v["launches"], 1e3 * v["ms"] / v["launches"],
-                v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0), flush=True)
-    dom = "smooth_pre_l0"
+    dom = max(smoothers, key=lambda k: prof[k]["ms"])
     pv = prof[dom]
     achieved = pv["bytes"] / (pv["ms"] * 1e-3) / 1e9 if pv["ms"] > 0 else 0.0
+    avg_us = 1e3 * pv["ms"] / max(pv["launches"], 1)
+    bytes_per_launch = pv["bytes"] / max(pv["launches"], 1)
+    print("# iters %s relres %.3e status %d; %.3f ms per solve" % (sorted(set(iters)), rel, st,
+          ms_per_step), flush=True)
+    # per-kernel breakdown from a separate, fully profiled run (events around
+    # every launch perturb the timing, so it is not the timed region)
+    plan.profile_only(plan.PROFILE_CLASSES)
+    plan.profile_reset()
+    for _ in range(2):
+        u.zero_()
+        plan.solve(u, f, rtol=1e-10)
+    full = plan.profile()
+    for k, v in full.items():
+        if v["launches"]:
+            print("#   %-22s launches %6d  avg %9.3f us  alg %8.1f GB/s" % (
+                k, v["launches"], 1e3 * v["ms"] / v["launches"],
+                v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0), flush=True)
     line = {
         "metric": "fine-grid unknowns/s to 1e-10 rel. residual; smoother HBM GB/s % of peak",
         "value": value,
@@ -153,7 +219,7 @@ def main():
                    "cycle": "V(2,2) red-black GS", "rtol": 1e-10, "iters": iters[-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": dom},
+                     "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, f_host)

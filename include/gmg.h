@@ -206,6 +206,9 @@ typedef struct {
 } gmg_kernel_stat;
 
 int gmg_profile_count(const gmg_plan *p);
+/* Restrict event timing to the kernel classes whose bit (1 << idx) is set in
+ * mask (default: all).  Fewer events perturb the timed run less. */
+gmg_status gmg_profile_set_mask(gmg_plan *p, unsigned mask);
 gmg_status gmg_profile_get(gmg_plan *p, int idx, gmg_kernel_stat *out); /* synchronises */
 gmg_status gmg_profile_reset(gmg_plan *p);
 

@@ -9,211 +9,255 @@
 // coarsest-level solver) runs out of LDS with workgroup barriers between the
 // colours.  In batch mode the grid has one workgroup per problem.
 //
-// In-place red-black Gauss-Seidel is race-free here because a colour's
-// updates only read the other colour and every colour ends with a barrier.
+// LDS layout: a level with n = m + 1 = 2^k intervals is stored with pitch n
+// in x and y plus zero pad planes, element (x, y, z) at ((z+1) n + y) n + x
+// (2D: (y+1) n + x).  Column x = m, row y = m and planes 0 and n are never
+// written, so every neighbour is at a fixed offset (+-1, +-n, +-n^2) and the
+// Dirichlet zeros come for free.  In-place red-black Gauss-Seidel is
+// race-free because a colour's updates only read the other colour and every
+// colour ends with a barrier.
 #include "gmg_internal.h"
 
 namespace gmg {
 
-template <typename T>
-struct BLevel {
-  int m;
-  T *u, *f;
+namespace {
+
+struct BL {
+  int m, k, n;  // side, log2(n), n = m + 1
+  int size;     // padded elements
 };
 
-template <typename T>
-__device__ __forceinline__ T at(const T *v, int m, int dim, int x, int y, int z) {
-  if (x < 0 || y < 0 || x >= m || y >= m) return T(0);
-  if (dim == 3) {
-    if (z < 0 || z >= m) return T(0);
-    return v[(z * m + y) * m + x];
-  }
-  return v[y * m + x];
+__device__ __forceinline__ BL bl_make(int dim, int L, int l) {
+  BL b;
+  b.k = L - l;
+  b.n = 1 << b.k;
+  b.m = b.n - 1;
+  b.size = dim == 3 ? (b.n + 1) * b.n * b.n : (b.n + 1) * b.n;
+  return b;
 }
 
-template <typename T>
-__device__ __forceinline__ T nbsum(const T *v, int m, int dim, int x, int y, int z) {
-  T nb = at(v, m, dim, x - 1, y, z) + at(v, m, dim, x + 1, y, z);
-  nb += at(v, m, dim, x, y - 1, z);
-  nb += at(v, m, dim, x, y + 1, z);
-  if (dim == 3) {
-    nb += at(v, m, dim, x, y, z - 1);
-    nb += at(v, m, dim, x, y, z + 1);
+// one colour of red-black Gauss-Seidel on an LDS level
+template <typename T, int DIM>
+__device__ void b_rb_colour(const BL &b, T *u, const T *f, int colour, T h2) {
+  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
+  const int half = b.n >> 1;
+  const int rows = DIM == 3 ? b.n * b.m : b.m;  // (y incl. pad row) x z, or y
+  const int total = half * rows;
+  const int sy = b.n, sz = b.n * b.n;
+  for (int h = threadIdx.x; h < total; h += blockDim.x) {
+    const int j = h & (half - 1);
+    const int row = h >> (b.k - 1);
+    int y, z;
+    if (DIM == 3) {
+      y = row & (b.n - 1);
+      z = row >> b.k;
+      if (y == b.m) continue;
+    } else {
+      y = row;
+      z = 0;
+    }
+    const int x = 2 * j + ((y + z + DIM + colour) & 1);
+    if (x >= b.m) continue;
+    const int i = DIM == 3 ? ((z + 1) * b.n + y) * b.n + x : (y + 1) * b.n + x;
+    T nb = u[i - 1] + u[i + 1];
+    nb += u[i - sy];
+    nb += u[i + sy];
+    if (DIM == 3) {
+      nb += u[i - sz];
+      nb += u[i + sz];
+    }
+    u[i] = fma(h2, f[i], nb) * inv2d;
   }
-  return nb;
+  __syncthreads();
 }
 
-template <typename T>
-__device__ void b_rb_colour(BLevel<T> L, int dim, int colour) {
-  const int N = dim == 3 ? L.m * L.m * L.m : L.m * L.m;
-  const T h = T(1) / T(L.m + 1);
+// visit every interior point of a level: fn(i, x, y, z)
+template <int DIM, typename F>
+__device__ __forceinline__ void b_for_all(const BL &b, F fn) {
+  const int total = DIM == 3 ? b.m * b.n * b.n : b.m * b.n;
+  for (int h = threadIdx.x; h < total; h += blockDim.x) {
+    const int x = h & (b.n - 1);
+    const int y = DIM == 3 ? (h >> b.k) & (b.n - 1) : h >> b.k;
+    const int z = DIM == 3 ? h >> (2 * b.k) : 0;
+    if (x == b.m || (DIM == 3 && y == b.m)) continue;
+    const int i = h + (DIM == 3 ? b.n * b.n : b.n);  // skip the leading pad plane/row
+    fn(i, x, y, z);
+  }
+}
+
+template <typename T, int DIM>
+__device__ void b_wj(const BL &b, T *u, const T *f, T *tmp, T h2, T omega) {
+  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
+  const int sy = b.n, sz = b.n * b.n;
+  b_for_all<DIM>(b, [&](int i, int, int, int) {
+    T nb = u[i - 1] + u[i + 1];
+    nb += u[i - sy];
+    nb += u[i + sy];
+    if (DIM == 3) {
+      nb += u[i - sz];
+      nb += u[i + sz];
+    }
+    tmp[i] = (T(1) - omega) * u[i] + omega * (fma(h2, f[i], nb) * inv2d);
+  });
+  __syncthreads();
+  b_for_all<DIM>(b, [&](int i, int, int, int) { u[i] = tmp[i]; });
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void b_smooth(const BL &b, T *u, const T *f, T *tmp, int nsw, bool black_first,
+                         int smoother, T omega) {
+  const T h = T(1) / T(b.n);
   const T h2 = h * h;
-  const T inv2d = dim == 3 ? T(1.0 / 6.0) : T(0.25);
-  for (int p = threadIdx.x; p < N; p += blockDim.x) {
-    const int x = p % L.m, y = (p / L.m) % L.m, z = dim == 3 ? p / (L.m * L.m) : 0;
-    if (((x + y + z + dim) & 1) != colour) continue;
-    const T nb = nbsum(L.u, L.m, dim, x, y, z);
-    L.u[p] = fma(h2, L.f[p], nb) * inv2d;
-  }
-  __syncthreads();
-}
-
-template <typename T>
-__device__ void b_wj(BLevel<T> L, int dim, T *tmp, T omega) {
-  const int N = dim == 3 ? L.m * L.m * L.m : L.m * L.m;
-  const T h = T(1) / T(L.m + 1);
-  const T h2 = h * h;
-  const T inv2d = dim == 3 ? T(1.0 / 6.0) : T(0.25);
-  for (int p = threadIdx.x; p < N; p += blockDim.x) {
-    const int x = p % L.m, y = (p / L.m) % L.m, z = dim == 3 ? p / (L.m * L.m) : 0;
-    const T nb = nbsum(L.u, L.m, dim, x, y, z);
-    tmp[p] = (T(1) - omega) * L.u[p] + omega * (fma(h2, L.f[p], nb) * inv2d);
-  }
-  __syncthreads();
-  for (int p = threadIdx.x; p < N; p += blockDim.x) L.u[p] = tmp[p];
-  __syncthreads();
-}
-
-template <typename T>
-__device__ void b_smooth(BLevel<T> L, int dim, int nsw, bool black_first, int smoother, T *tmp,
-                         T omega) {
   for (int s = 0; s < nsw; ++s) {
     if (smoother == 0) {
-      b_rb_colour(L, dim, black_first ? 1 : 0);
-      b_rb_colour(L, dim, black_first ? 0 : 1);
+      b_rb_colour<T, DIM>(b, u, f, black_first ? 1 : 0, h2);
+      b_rb_colour<T, DIM>(b, u, f, black_first ? 0 : 1, h2);
     } else {
-      b_wj(L, dim, tmp, omega);
+      b_wj<T, DIM>(b, u, f, tmp, h2, omega);
     }
   }
 }
 
-// f_c = FW(f - A u) with the residual formed on the fly (27 / 9 points).
-template <typename T>
-__device__ void b_restrict(BLevel<T> F, BLevel<T> C, int dim) {
-  const int Nc = dim == 3 ? C.m * C.m * C.m : C.m * C.m;
-  const T h = T(1) / T(F.m + 1);
-  const T inv_h2 = T(1) / (h * h);
-  const T w[3] = {T(0.25), T(0.5), T(0.25)};
-  for (int p = threadIdx.x; p < Nc; p += blockDim.x) {
-    const int a = p % C.m, b = (p / C.m) % C.m, c = dim == 3 ? p / (C.m * C.m) : 0;
-    T s = T(0);
-    const int nz = dim == 3 ? 3 : 1;
-    for (int oz = 0; oz < nz; ++oz)
-      for (int oy = 0; oy < 3; ++oy)
-        for (int ox = 0; ox < 3; ++ox) {
-          const int x = 2 * a + ox, y = 2 * b + oy, z = dim == 3 ? 2 * c + oz : 0;
-          const int q = dim == 3 ? (z * F.m + y) * F.m + x : y * F.m + x;
-          const T r = F.f[q] - (T(2 * dim) * F.u[q] - nbsum(F.u, F.m, dim, x, y, z)) * inv_h2;
-          const T wt = dim == 3 ? w[ox] * w[oy] * w[oz] : w[ox] * w[oy];
-          s += wt * r;
-        }
-    C.f[p] = s;
-  }
+// fc = FW(f - A u): the residual goes to r (LDS scratch) first
+template <typename T, int DIM>
+__device__ void b_restrict(const BL &F, const T *u, const T *f, T *r, const BL &C, T *fc) {
+  const T inv_h2 = T(F.n) * T(F.n);
+  const int sy = F.n, sz = F.n * F.n;
+  b_for_all<DIM>(F, [&](int i, int, int, int) {
+    T nb = u[i - 1] + u[i + 1];
+    nb += u[i - sy];
+    nb += u[i + sy];
+    if (DIM == 3) {
+      nb += u[i - sz];
+      nb += u[i + sz];
+    }
+    r[i] = f[i] - (T(2 * DIM) * u[i] - nb) * inv_h2;
+  });
   __syncthreads();
-}
-
-// F.u += P C.u (linear interpolation, zero coarse boundary).
-template <typename T>
-__device__ void b_prolong(BLevel<T> F, BLevel<T> C, int dim) {
-  const int N = dim == 3 ? F.m * F.m * F.m : F.m * F.m;
-  for (int p = threadIdx.x; p < N; p += blockDim.x) {
-    const int x = p % F.m, y = (p / F.m) % F.m, z = dim == 3 ? p / (F.m * F.m) : 0;
-    int cx[2], cy[2], cz[2];
-    T wx[2], wy[2], wz[2];
-    auto axis = [](int v, int *c, T *wt) -> int {
-      if (v & 1) {
-        c[0] = (v - 1) >> 1;
-        wt[0] = T(1);
-        return 1;
-      }
-      c[0] = (v >> 1) - 1;
-      c[1] = v >> 1;
-      wt[0] = wt[1] = T(0.5);
-      return 2;
+  b_for_all<DIM>(C, [&](int ic, int a, int bb, int c) {
+    // fine centre (2a+1, 2b+1, 2c+1)
+    const int i = DIM == 3 ? ((2 * c + 2) * F.n + 2 * bb + 1) * F.n + 2 * a + 1
+                           : (2 * bb + 2) * F.n + 2 * a + 1;
+    auto rowsum = [&](int j) { return T(0.25) * r[j - 1] + T(0.5) * r[j] + T(0.25) * r[j + 1]; };
+    auto plane = [&](int j) {
+      return T(0.25) * rowsum(j - sy) + T(0.5) * rowsum(j) + T(0.25) * rowsum(j + sy);
     };
-    const int nx = axis(x, cx, wx), ny = axis(y, cy, wy);
-    const int nz = dim == 3 ? axis(z, cz, wz) : 1;
-    if (dim == 2) {
-      cz[0] = 0;
-      wz[0] = T(1);
-    }
-    T s = T(0);
-    for (int k = 0; k < nz; ++k)
-      for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-          const T v = at(C.u, C.m, dim, cx[i], cy[j], cz[k]);
-          s += (dim == 3 ? wx[i] * wy[j] * wz[k] : wx[i] * wy[j]) * v;
-        }
-    F.u[p] += s;
-  }
+    fc[ic] = DIM == 3 ? T(0.25) * plane(i - sz) + T(0.5) * plane(i) + T(0.25) * plane(i + sz)
+                      : plane(i);
+  });
   __syncthreads();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_bottom(BottomArgs<T> a, const T *const *f_list,
-                                                 T *const *u_list, int active_stride) {
-  const int prob = blockIdx.x;
-  if (a.active && a.active[(size_t)prob * active_stride] == 0) return;
-  const T *fin = f_list ? f_list[prob] : a.f;
-  T *uout = u_list ? u_list[prob] : a.u;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *sm = reinterpret_cast<T *>(smem_raw);
-  const int dim = a.dim, L = a.L;
-  BLevel<T> lv[12];
-  size_t off = 0;
-  for (int l = 0; l < L; ++l) {
-    lv[l].m = (1 << (L - l)) - 1;
-    const int N = dim == 3 ? lv[l].m * lv[l].m * lv[l].m : lv[l].m * lv[l].m;
-    lv[l].u = sm + off;
-    off += N;
-    lv[l].f = sm + off;
-    off += N;
-  }
-  T *tmp = sm + off;
-  const T omega = T(a.omega);
-  const int N0 = dim == 3 ? lv[0].m * lv[0].m * lv[0].m : lv[0].m * lv[0].m;
-  for (int p = threadIdx.x; p < N0; p += blockDim.x) {
-    lv[0].f[p] = fin[p];
-    lv[0].u[p] = T(0);
+// u_F += P u_C (linear interpolation; coarse pads supply the boundary zeros)
+template <typename T, int DIM>
+__device__ void b_prolong(const BL &F, T *u, const BL &C, const T *uc) {
+  const int sy = C.n, sz = C.n * C.n;
+  b_for_all<DIM>(F, [&](int i, int x, int y, int z) {
+    // per axis: fine storage x odd -> coarse storage (x-1)/2; even -> x/2-1 and x/2
+    const int cx = (x - 1) >> 1, cy = (y - 1) >> 1, cz = (z - 1) >> 1;
+    const bool ox = x & 1, oy = y & 1, oz = z & 1;
+    // coarse index of (cx, cy, cz); the pad row/plane at index -1 reads as 0
+    const int ci = DIM == 3 ? ((cz + 1) * C.n + cy) * C.n + cx : (cy + 1) * C.n + cx;
+    auto xs = [&](int j) { return ox ? uc[j] : T(0.5) * (uc[j] + uc[j + 1]); };
+    auto ys = [&](int j) { return oy ? xs(j) : T(0.5) * (xs(j) + xs(j + sy)); };
+    T s;
+    if (DIM == 3)
+      s = oz ? ys(ci) : T(0.5) * (ys(ci) + ys(ci + sz));
+    else
+      s = ys(ci);
+    u[i] += s;
+  });
+  __syncthreads();
+}
+
+// element offset of level l's u array (f follows it); levels are packed
+// finest first, each as u then f, and the scratch follows the last level
+__device__ __forceinline__ int bl_offset(int dim, int L, int l) {
+  int off = 0;
+  for (int j = 0; j < l; ++j) off += 2 * bl_make(dim, L, j).size;
+  return off;
+}
+
+template <typename T, int DIM>
+__device__ void bottom_body(const BottomArgs<T> &a, const T *fin, T *uout, T *sm) {
+  const int L = a.L;
+  const int total = bl_offset(DIM, L, L) + bl_make(DIM, L, 0).size;
+  T *R = sm + bl_offset(DIM, L, L);  // residual / Jacobi scratch, size of level 0
+  for (int i = threadIdx.x; i < total; i += blockDim.x) sm[i] = T(0);
+  __syncthreads();
+  const BL b0 = bl_make(DIM, L, 0);
+  {
+    T *F0 = sm + b0.size;
+    b_for_all<DIM>(b0, [&](int i, int x, int y, int z) {
+      const int m = b0.m;
+      F0[i] = fin[DIM == 3 ? (z * m + y) * m + x : y * m + x];
+    });
   }
   __syncthreads();
+  const T omega = T(a.omega);
   for (int l = 0; l + 1 < L; ++l) {
-    if (l > 0) {
-      const int N = dim == 3 ? lv[l].m * lv[l].m * lv[l].m : lv[l].m * lv[l].m;
-      for (int p = threadIdx.x; p < N; p += blockDim.x) lv[l].u[p] = T(0);
-      __syncthreads();
-    }
-    b_smooth(lv[l], dim, a.nu1, false, a.smoother, tmp, omega);
-    b_restrict(lv[l], lv[l + 1], dim);
+    const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
+    T *U = sm + bl_offset(DIM, L, l);
+    T *F = U + b.size;
+    T *Fc = sm + bl_offset(DIM, L, l + 1) + c.size;
+    b_smooth<T, DIM>(b, U, F, R, a.nu1, false, a.smoother, omega);
+    b_restrict<T, DIM>(b, U, F, R, c, Fc);
   }
-  // one-node level: exact solve 2d u / h^2 = f, evaluated in FP64
-  if (threadIdx.x == 0) {
-    const double h = 1.0 / double(lv[L - 1].m + 1);
-    lv[L - 1].u[0] = T((h * h * double(lv[L - 1].f[0])) / double(2 * dim));
+  if (threadIdx.x == 0) {  // one-node level: 2d u / h^2 = f, in FP64
+    const BL c = bl_make(DIM, L, L - 1);
+    T *U = sm + bl_offset(DIM, L, L - 1);
+    const int i = DIM == 3 ? c.n * c.n : c.n;  // element (0,0[,0])
+    const double h = 1.0 / double(c.n);
+    U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
   }
   __syncthreads();
   for (int l = L - 2; l >= 0; --l) {
-    b_prolong(lv[l], lv[l + 1], dim);
-    b_smooth(lv[l], dim, a.nu2, !a.post_forward, a.smoother, tmp, omega);
+    const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
+    T *U = sm + bl_offset(DIM, L, l);
+    T *F = U + b.size;
+    const T *Uc = sm + bl_offset(DIM, L, l + 1);
+    b_prolong<T, DIM>(b, U, c, Uc);
+    b_smooth<T, DIM>(b, U, F, R, a.nu2, !a.post_forward, a.smoother, omega);
   }
-  for (int p = threadIdx.x; p < N0; p += blockDim.x) uout[p] = lv[0].u[p];
+  b_for_all<DIM>(b0, [&](int i, int x, int y, int z) {
+    const int m = b0.m;
+    uout[DIM == 3 ? (z * m + y) * m + x : y * m + x] = sm[i];
+  });
+}
+
+}  // namespace
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_bottom(BottomArgs<T> arg, const BottomArgs<T> *tbl) {
+  const BottomArgs<T> a = tbl ? tbl[blockIdx.x] : arg;  // batch: one problem per workgroup
+  if (a.active && *a.active == 0) return;
+  const T *fin = a.f;
+  T *uout = a.u;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sm = reinterpret_cast<T *>(smem_raw);
+  if (a.dim == 3)
+    bottom_body<T, 3>(a, fin, uout, sm);
+  else
+    bottom_body<T, 2>(a, fin, uout, sm);
 }
 
 size_t bottom_lds_bytes(int dim, int L, int smoother, size_t elem) {
-  size_t n = 0;
+  (void)smoother;  // weighted Jacobi reuses the residual scratch
+  size_t n_el = 0;
   for (int l = 0; l < L; ++l) {
-    const size_t m = ((size_t)1 << (L - l)) - 1;
-    n += 2 * (dim == 3 ? m * m * m : m * m);
+    const size_t n = (size_t)1 << (L - l);
+    n_el += 2 * (dim == 3 ? (n + 1) * n * n : (n + 1) * n);
   }
-  const size_t m0 = ((size_t)1 << L) - 1;
-  if (smoother == 1) n += dim == 3 ? m0 * m0 * m0 : m0 * m0;
-  return n * elem;
+  const size_t n0 = (size_t)1 << L;
+  n_el += dim == 3 ? (n0 + 1) * n0 * n0 : (n0 + 1) * n0;
+  return n_el * elem;
 }
 
 template <typename T>
-hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const T *const *f_list, T *const *u_list,
-                         hipStream_t s) {
-  const size_t lds = bottom_lds_bytes(a.dim, a.L, a.smoother, sizeof(T));
+hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const BottomArgs<T> *tbl, hipStream_t s,
+                         size_t lds_bytes) {
+  const size_t lds = lds_bytes ? lds_bytes : bottom_lds_bytes(a.dim, a.L, a.smoother, sizeof(T));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void *)k_bottom<T>,
@@ -221,14 +265,14 @@ hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const T *const *f_list,
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int stride = (int)(sizeof(SolveState) / sizeof(int));
-  hipLaunchKernelGGL(k_bottom<T>, dim3(nproblems), dim3(1024), lds, s, a, f_list, u_list, stride);
+  const int nt = (a.dim == 3 && a.L <= 3) || (a.dim == 2 && a.L <= 4) ? 256 : 1024;
+  hipLaunchKernelGGL(k_bottom<T>, dim3(nproblems), dim3(nt), lds, s, a, tbl);
   return hipGetLastError();
 }
 
-template hipError_t launch_bottom<double>(int, BottomArgs<double>, const double *const *,
-                                          double *const *, hipStream_t);
-template hipError_t launch_bottom<float>(int, BottomArgs<float>, const float *const *,
-                                         float *const *, hipStream_t);
+template hipError_t launch_bottom<double>(int, BottomArgs<double>, const BottomArgs<double> *,
+                                          hipStream_t, size_t);
+template hipError_t launch_bottom<float>(int, BottomArgs<float>, const BottomArgs<float> *,
+                                         hipStream_t, size_t);
 
 }  // namespace gmg

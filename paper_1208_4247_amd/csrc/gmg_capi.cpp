@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -67,6 +68,12 @@ struct PendingEv {
   double bytes;
 };
 
+struct PassChoice {
+  int smax = 2;
+  std::array<int, 5> var{{0, 0, 0, 0, 0}};
+  std::array<int, 5> tz{{0, 0, 0, 0, 0}};
+};
+
 template <typename T>
 struct LevelSet {
   // per level: f (RHS), w (after pre-smoothing), u (after post-smoothing),
@@ -75,6 +82,48 @@ struct LevelSet {
 };
 
 }  // namespace
+
+// ---------------------------------------------------------------- batch plans
+// One problem of a batch: its level table and workspace arrays.
+struct BProblem {
+  int dim = 3, L = 2, B = 1;
+  std::vector<int> m;
+  std::vector<double *> f, w, u, t;  // per level (level 0: w, t only)
+  double *partials = nullptr;        // slice for its level-0 norm pass
+  int npart = 0;
+  SolveState *st = nullptr;
+};
+
+// One launch of the batched cycle; its argument entries live in a device
+// table (byte offset tbl_off in the table region).
+enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3 };
+struct BOp {
+  int kind = BO_PASS;
+  int dim = 3, stages = 0, flags = 0, variant = 0, wj = 0, nent = 0;
+  size_t tbl_off = 0;
+  int cls = 0;
+  double bytes = 0.0;
+  size_t lds = 0;      // bottom: LDS bytes for the largest entry
+  int bottom_L = 0;    // bottom: largest sub-hierarchy
+  int bottom_dim = 3;
+};
+
+struct Batch {
+  std::vector<BProblem> pb;
+  std::vector<BOp> ops;
+  std::vector<char> host_tbl;  // host image of the table region
+  char *dev_tbl = nullptr;     // the table region inside the workspace
+  char *pinned = nullptr;      // pinned staging copy for uploads
+  struct Patch {
+    size_t off;  // byte offset of a pointer field in the table image
+    int prob;
+    int which;   // 0: caller's u, 1: caller's f
+  };
+  std::vector<Patch> patches;
+  SolveState *states = nullptr;
+  SolveState *hstates = nullptr;  // pinned
+  hipGraphExec_t graph = nullptr;
+};
 
 struct gmg_plan {
   gmg_config cfg;
@@ -85,8 +134,9 @@ struct gmg_plan {
 
   int dim = 3, L = 1, B = 1;  // B: first level handled by the bottom kernel
   std::vector<int> m;         // sides
-  int smax = 2;               // sweeps fused per pass
+  int smax_cap = 2;           // most sweeps fused into one pass
   bool need_tmp = false;
+  bool tuned = false;
 
   SolveState *state = nullptr;
   double *partials = nullptr;
@@ -96,18 +146,27 @@ struct gmg_plan {
   LevelSet<float> s;   // FP32 levels (mixed precision)
   double *x2 = nullptr;  // FP64 ping-pong partner of the caller's u (mixed)
 
-  // per level tile variant for each fused-stage count (index: stages)
-  std::vector<std::array<int, 5>> var;
-  std::vector<std::array<int, 5>> tz;
+  // per level and role (0: descent / pre-smoothing, 1: ascent / post-smoothing
+  // with the fused prolongation): sweeps per pass and the tile shape and
+  // z-chunk for each stage count
+  std::vector<std::array<PassChoice, 2>> ch;
 
   // profiling
   bool profile = false;
+  unsigned prof_mask = ~0u;
   std::vector<Prof> prof;
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> evpool;
 
   SolveState *hstate = nullptr;  // pinned host copy
   double *hscalar = nullptr;
+
+  // hipGraph of the coarse part of one cycle (levels >= 1 and the bottom),
+  // per precision and per "gated by the solve state or not"
+  hipGraphExec_t coarse_graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipStream_t capture_stream = nullptr;
+
+  struct Batch *batch = nullptr;  // batch plans (nproblems > 1)
 };
 
 namespace {
@@ -155,13 +214,13 @@ struct ProfScope {
   double bytes;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(gmg_plan *p_, int cls_, double bytes_) : p(p_), cls(cls_), bytes(bytes_) {
-    if (!p->profile) return;
+    if (!p->profile || !((p->prof_mask >> cls) & 1u)) return;
     a = get_event(p);
     b = get_event(p);
     if (a) (void)hipEventRecord(a, p->stream);
   }
   ~ProfScope() {
-    if (!p->profile || !a || !b) return;
+    if (!a || !b) return;
     (void)hipEventRecord(b, p->stream);
     p->pending.push_back({cls, a, b, bytes});
   }
@@ -190,14 +249,16 @@ int stages_of(const gmg_plan *p, int sweeps) {
 }
 
 template <typename T>
-hipError_t one_pass(gmg_plan *p, int level, int sweeps, int flags, const T *src, const T *ec,
-                    const T *f, T *dst, double *partials, const int *active, int cls) {
+hipError_t one_pass(gmg_plan *p, int level, int role, int sweeps, int flags, const T *src,
+                    const T *ec, const T *f, T *dst, double *partials, const int *active,
+                    int cls) {
   const int dim = p->dim, m = p->m[level];
   const int st = stages_of(p, sweeps);
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
-  const int v = p->var[level][st];
+  const PassChoice &c = p->ch[level][role];
+  const int v = c.var[st];
   const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
-  const PassGeom g = pass_geometry(dim, m, st, t, p->tz[level][st]);
+  const PassGeom g = pass_geometry(dim, m, st, t, c.tz[st]);
   PassArgs<T> a;
   a.u_in = src;
   a.f = f;
@@ -222,11 +283,12 @@ hipError_t one_pass(gmg_plan *p, int level, int sweeps, int flags, const T *src,
             : launch_rb_pass<T>(dim, st, flags, v, a, p->stream);
 }
 
-int pass_blocks(const gmg_plan *p, int level, int sweeps) {
+int pass_blocks(const gmg_plan *p, int level, int role, int sweeps) {
   const int st = stages_of(p, sweeps);
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
-  const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, p->var[level][st]);
-  return pass_geometry(p->dim, p->m[level], st, t, p->tz[level][st]).nblocks;
+  const PassChoice &c = p->ch[level][role];
+  const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, c.var[st]);
+  return pass_geometry(p->dim, p->m[level], st, t, c.tz[st]).nblocks;
 }
 
 // nsweeps of the plan's smoother from (src [+ P ec]) to dst through fused
@@ -237,6 +299,8 @@ template <typename T>
 hipError_t smooth_chain(gmg_plan *p, int level, int nsweeps, bool backward, const T *src,
                         const T *ec, const T *f, T *dst, T *tmp, double *partials,
                         const int *active, int cls, int *nparts) {
+  const int role = ec ? 1 : 0;
+  const int smax = p->ch[level][role].smax;
   const int dim = p->dim;
   const int m = p->m[level];
   const int mc = level + 1 < p->L ? p->m[level + 1] : 0;
@@ -267,12 +331,12 @@ hipError_t smooth_chain(gmg_plan *p, int level, int nsweeps, bool backward, cons
     if (!src) return launch_fill_zero(dst, npts(dim, m) * sizeof(T), p->stream);
     return launch_copy(src, dst, npts(dim, m) * sizeof(T), active, p->stream);
   }
-  const int K = (nsweeps + p->smax - 1) / p->smax;
+  const int K = (nsweeps + smax - 1) / smax;
   int left = nsweeps;
   const T *in = src;
   for (int k = 1; k <= K; ++k) {
-    const int sw = std::min(p->smax, left - (K - k));  // keep later passes non-empty
-    const int swk = std::min(sw, p->smax);
+    const int sw = std::min(smax, left - (K - k));  // keep later passes non-empty
+    const int swk = std::min(sw, smax);
     T *out = ((K - k) % 2 == 1) ? tmp : dst;
     int flags = backward ? F_BLACK_FIRST : 0;
     if (k == 1) {
@@ -280,10 +344,10 @@ hipError_t smooth_chain(gmg_plan *p, int level, int nsweeps, bool backward, cons
       if (ec) flags |= F_PROLONG;
       if (partials) {
         flags |= F_NORM_IN;
-        if (nparts) *nparts = pass_blocks(p, level, swk);
+        if (nparts) *nparts = pass_blocks(p, level, role, swk);
       }
     }
-    hipError_t e = one_pass<T>(p, level, swk, flags, in, k == 1 ? ec : nullptr, f, out,
+    hipError_t e = one_pass<T>(p, level, role, swk, flags, in, k == 1 ? ec : nullptr, f, out,
                                k == 1 ? partials : nullptr, active, cls);
     if (e != hipSuccess) return e;
     in = out;
@@ -323,6 +387,81 @@ LevelSet<float> &levels_of<float>(gmg_plan *p) {
   return p->s;
 }
 
+// Levels 1..B-1 of the descent, the bottom kernel and levels B-1..1 of the
+// ascent: everything of a cycle that touches only workspace arrays.
+template <typename T>
+hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
+  LevelSet<T> &S = levels_of<T>(p);
+  const int L = p->L, B = p->B;
+  const bool bwd = !(p->cfg.flags & GMG_POST_FORWARD);
+  const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
+  hipError_t e;
+  for (int l = 1; l < B; ++l) {
+    e = smooth_chain<T>(p, l, nu1, false, nullptr, nullptr, S.f[l], S.w[l], S.t[l], nullptr,
+                        active, PC_PRE_C, nullptr);
+    if (e != hipSuccess) return e;
+    e = restrict_level<T>(p, l, S.w[l], S.f[l], S.f[l + 1], active, PC_RES_C);
+    if (e != hipSuccess) return e;
+  }
+  {
+    BottomArgs<T> ba;
+    ba.active = active;
+    ba.dim = p->dim;
+    ba.nu1 = nu1;
+    ba.nu2 = nu2;
+    ba.smoother = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+    ba.post_forward = bwd ? 0 : 1;
+    ba.omega = p->cfg.omega;
+    ba.f = S.f[B];
+    ba.u = S.u[B];
+    ba.L = L - B;
+    ProfScope ps(p, PC_BOTTOM, (double)npts(p->dim, p->m[B]) * sizeof(T) * 2);
+    e = launch_bottom<T>(1, ba, nullptr, p->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int l = B - 1; l >= 1; --l) {
+    e = smooth_chain<T>(p, l, nu2, bwd, S.w[l], S.u[l + 1], S.f[l], S.u[l], S.t[l], nullptr,
+                        active, PC_POST_C, nullptr);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The coarse part, eagerly or as a replay of a hipGraph captured on first
+// use (GMG_USE_GRAPH; not while events are being recorded for these kernels).
+template <typename T>
+hipError_t run_coarse(gmg_plan *p, const int *active) {
+  const unsigned coarse_cls = (1u << PC_PRE_C) | (1u << PC_RES_C) | (1u << PC_POST_C) |
+                              (1u << PC_BOTTOM) | (1u << PC_MISC);
+  const bool events = p->profile && (p->prof_mask & coarse_cls);
+  if (!(p->cfg.flags & GMG_USE_GRAPH) || events) return enqueue_coarse<T>(p, active);
+  const int ti = sizeof(T) == 8 ? 0 : 1, ai = active ? 1 : 0;
+  if (!p->coarse_graph[ti][ai]) {
+    hipError_t e;
+    if (!p->capture_stream) {
+      e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    hipStream_t keep = p->stream;
+    p->stream = p->capture_stream;
+    e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      p->stream = keep;
+      return e;
+    }
+    hipError_t ee = enqueue_coarse<T>(p, active);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->capture_stream, &g);
+    p->stream = keep;
+    if (ee != hipSuccess) return ee;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&p->coarse_graph[ti][ai], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+  }
+  return hipGraphLaunch(p->coarse_graph[ti][ai], p->stream);
+}
+
 // One V-cycle on the plan's hierarchy in precision T.  Level 0: start value
 // u0_in (NULL = zero), result u0_out (must not alias u0_in), RHS f0.
 // norm_partials != NULL: the level-0 pre-pass emits the residual norm of
@@ -360,7 +499,7 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
     ba.u = u0_out;
     ba.L = 1;
     ProfScope ps(p, PC_BOTTOM, 2.0 * sizeof(T));
-    return launch_bottom<T>(1, ba, nullptr, nullptr, p->stream);
+    return launch_bottom<T>(1, ba, nullptr, p->stream);
   }
   // ---- descent
   e = smooth_chain<T>(p, 0, nu1, false, u0_in, nullptr, f0, S.w[0], S.t[0], norm_partials, active,
@@ -376,28 +515,8 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
   const T *w0 = S.w[0];
   e = restrict_level<T>(p, 0, w0, f0, S.f[1], active, PC_RES0);
   if (e != hipSuccess) return e;
-  for (int l = 1; l < B; ++l) {
-    e = smooth_chain<T>(p, l, nu1, false, nullptr, nullptr, S.f[l], S.w[l], S.t[l], nullptr,
-                        active, PC_PRE_C, nullptr);
-    if (e != hipSuccess) return e;
-    e = restrict_level<T>(p, l, S.w[l], S.f[l], S.f[l + 1], active, PC_RES_C);
-    if (e != hipSuccess) return e;
-  }
-  // ---- bottom (levels B..L-1 in one workgroup)
-  {
-    ba.f = S.f[B];
-    ba.u = S.u[B];
-    ba.L = L - B;
-    ProfScope ps(p, PC_BOTTOM, (double)npts(p->dim, p->m[B]) * sizeof(T) * 2);
-    e = launch_bottom<T>(1, ba, nullptr, nullptr, p->stream);
-    if (e != hipSuccess) return e;
-  }
-  // ---- ascent
-  for (int l = B - 1; l >= 1; --l) {
-    e = smooth_chain<T>(p, l, nu2, bwd, S.w[l], S.u[l + 1], S.f[l], S.u[l], S.t[l], nullptr,
-                        active, PC_POST_C, nullptr);
-    if (e != hipSuccess) return e;
-  }
+  e = run_coarse<T>(p, active);
+  if (e != hipSuccess) return e;
   return smooth_chain<T>(p, 0, nu2, bwd, w0, S.u[1], f0, u0_out, S.t[0], nullptr, active,
                          PC_POST0, nullptr);
 }
@@ -485,28 +604,58 @@ void bind(LevelSet<T> &S, char *ws, const std::vector<size_t> &F, const std::vec
   }
 }
 
-// default tile variant and z-chunk for a level and stage count
-void default_tiles(gmg_plan &p) {
-  p.var.assign(p.L, {0, 0, 0, 0, 0});
-  p.tz.assign(p.L, {0, 0, 0, 0, 0});
-  const bool wj = p.cfg.smoother == GMG_SMOOTH_WJ;
-  for (int l = 0; l < p.L; ++l) {
-    for (int st = 1; st <= 4; ++st) {
-      const int nv = pass_variant_count(p.dim, st, wj ? 1 : 0);
-      if (nv == 0) continue;
-      // prefer the large tile on big levels, the small one otherwise
-      const int v = (p.m[l] >= 255 || nv == 1) ? 0 : 1;
-      p.var[l][st] = v;
-      const PassTile t = pass_variant(p.dim, st, wj ? 1 : 0, v);
-      const PassGeom g0 = pass_geometry(p.dim, p.m[l], st, t, p.m[l]);
-      // enough workgroups to cover the 256 CUs a few times, z-chunks >= 16
-      const int xy = g0.ntx * g0.nty;
-      int ntz = std::max(1, (3 * 256 + xy - 1) / xy);
-      int tzv = (p.m[l] + ntz - 1) / ntz;
-      tzv = std::max(tzv, std::min(p.m[l], 16));
-      p.tz[l][st] = tzv;
+// z-chunk giving a few workgroups per compute unit for a tile shape
+int auto_tz(int dim, int m, int st, const PassTile &t) {
+  const PassGeom g0 = pass_geometry(dim, m, st, t, m);
+  const int xy = g0.ntx * g0.nty;
+  const int ntz = std::max(1, (3 * 256 + xy - 1) / xy);
+  int tzv = (m + ntz - 1) / ntz;
+  return std::max(tzv, std::min(m, 8));
+}
+
+// Default pass choice for a level and role, from measurements on MI355X
+// (single-sweep passes win on small grids and for the prolongation pass;
+// two fused sweeps win for plain smoothing of large grids).
+PassChoice choice_for(const gmg_config &cfg, int dim, int m, int role, int smax_cap) {
+  PassChoice c;
+  const bool wj = cfg.smoother == GMG_SMOOTH_WJ;
+  const bool big = dim == 3 ? m >= 255 : m >= 2047;
+  c.smax = std::min(smax_cap, (big && role == 0) ? 2 : 1);
+  if (dim == 2) c.smax = std::min(smax_cap, 2);
+  for (int st = 1; st <= 4; ++st) {
+    const int nv = pass_variant_count(dim, st, wj ? 1 : 0);
+    if (nv == 0) continue;
+    int v = 0, tz = 0;
+    if (dim == 3 && !wj) {
+      if (m <= 127) {
+        v = st == 2 ? 2 : 1;  // (66,14,512) / (36,24,256)
+        tz = m <= 63 ? 2 : 4;
+      } else if (m <= 255) {
+        v = 1;
+        tz = 32;
+      } else {
+        v = 0;
+        tz = st == 4 ? 0 : 32;
+      }
+    } else {
+      v = (m >= 255 || nv == 1) ? 0 : 1;
     }
+    v = std::min(v, nv - 1);
+    c.var[st] = v;
+    const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
+    c.tz[st] = tz > 0 ? std::min(tz, m) : auto_tz(dim, m, st, t);
   }
+  return c;
+}
+
+PassChoice default_choice(const gmg_plan &p, int l, int role) {
+  return choice_for(p.cfg, p.dim, p.m[l], role, p.smax_cap);
+}
+
+void default_tiles(gmg_plan &p) {
+  p.ch.resize(p.L);
+  for (int l = 0; l < p.L; ++l)
+    for (int role = 0; role < 2; ++role) p.ch[l][role] = default_choice(p, l, role);
 }
 
 gmg_status validate_cfg(const gmg_config *c) {
@@ -541,8 +690,10 @@ gmg_status init_plan_shape(gmg_plan &p, const gmg_config *cfg) {
       break;
     }
   if (p.L == 1) p.B = 1;
-  p.smax = (cfg->flags & GMG_NO_TEMPORAL_BLOCKING) ? 1 : 2;
-  p.need_tmp = std::max(cfg->nu1, cfg->nu2) > p.smax;
+  p.smax_cap = (cfg->flags & GMG_NO_TEMPORAL_BLOCKING) ? 1 : 2;
+  // chained passes need a scratch array whenever a level may run more than
+  // one pass (any choice of sweeps per pass, so tuning never changes layout)
+  p.need_tmp = std::max(cfg->nu1, cfg->nu2) >= 2;
   p.profile = (cfg->flags & GMG_PROFILE) != 0;
   return GMG_OK;
 }
@@ -567,6 +718,561 @@ int estimate_cycles(const SolveState &st, int done) {
   const double need = std::log(st.rtol / rel) / std::log(rho);
   int k = (int)std::ceil(need);
   return std::max(1, std::min(k, 64));
+}
+
+// ------------------------------------------------------------------ autotuner
+// Times every candidate pass choice (sweeps per pass x tile shape x z-chunk)
+// of every level and role on the plan's own buffers with hipEvents and keeps
+// the fastest.  Results are bitwise independent of the choice, so tuning only
+// changes speed.  A process-wide cache (and, when GMG_TUNE_CACHE names a
+// file, an on-disk one) is keyed by device architecture and problem shape.
+std::map<std::string, PassChoice> &tune_cache() {
+  static std::map<std::string, PassChoice> c;
+  return c;
+}
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tune_key(const gmg_plan &p, int l, int role, size_t elem) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d", arch_name().c_str(), p.dim,
+                p.m[l], (int)(elem * 8), p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs",
+                role == 0 ? p.cfg.nu1 : p.cfg.nu2, role, p.smax_cap);
+  return buf;
+}
+
+void tune_cache_load() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char *path = std::getenv("GMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *fh = std::fopen(path, "r");
+  if (!fh) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), fh)) {
+    char key[256];
+    PassChoice c;
+    int st = 0, v = 0, tz = 0;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d",
+                    key, &c.smax, &st, &v, &tz) == 5 && st >= 1 && st <= 4) {
+      auto it = tune_cache().find(key);
+      PassChoice &d = it == tune_cache().end() ? (tune_cache()[key] = c) : it->second;
+      d.smax = c.smax;
+      d.var[st] = v;
+      d.tz[st] = tz;
+    }
+  }
+  std::fclose(fh);
+}
+
+void tune_cache_store(const std::string &key, const PassChoice &c, int st, double us) {
+  tune_cache()[key] = c;
+  const char *path = std::getenv("GMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *fh = std::fopen(path, "a");
+  if (!fh) return;
+  std::fprintf(fh, "{\"key\": \"%s\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, \"us\": %.2f}\n",
+               key.c_str(), c.smax, st, c.var[st], c.tz[st], us);
+  std::fclose(fh);
+}
+
+template <typename T>
+hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, const T *f, T *dst,
+                     T *tmp, double *partials, size_t elem) {
+  const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;
+  if (nu == 0) return hipSuccess;
+  const std::string key = tune_key(*p, l, role, elem);
+  auto it = tune_cache().find(key);
+  if (it != tune_cache().end()) {
+    p->ch[l][role] = it->second;
+    return hipSuccess;
+  }
+  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
+  const int m = p->m[l];
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) return err;
+  const size_t N = npts(p->dim, m);
+  const int reps = N > (1u << 24) ? 2 : (N > (1u << 20) ? 4 : 10);
+  const PassChoice base = p->ch[l][role];
+  PassChoice best = base;
+  double best_us = 1e30;
+  int best_st = stages_of(p, std::min(base.smax, nu));
+  for (int sm = 1; sm <= std::min(p->smax_cap, nu); ++sm) {
+    const int st = stages_of(p, sm);
+    const int nv = pass_variant_count(p->dim, st, wj ? 1 : 0);
+    for (int v = 0; v < nv; ++v) {
+      const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, v);
+      int tzs[6] = {4, 8, 16, 32, 64, 0};
+      int last = -1;
+      for (int k = 0; k < 6; ++k) {
+        int tzv = tzs[k] > 0 ? std::min(tzs[k], m) : auto_tz(p->dim, m, st, t);
+        if (tzv == last) continue;
+        last = tzv;
+        if (pass_geometry(p->dim, m, st, t, tzv).nblocks > kMaxPartials) continue;
+        PassChoice c = base;
+        c.smax = sm;
+        c.var[st] = v;
+        c.tz[st] = tzv;
+        p->ch[l][role] = c;
+        err = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials, nullptr,
+                              PC_MISC, nullptr);
+        if (err != hipSuccess) break;
+        err = hipEventRecord(e0, p->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r)
+          err = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials, nullptr,
+                                PC_MISC, nullptr);
+        if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) break;
+        const double us = 1e3 * ms / reps;
+        if (us < best_us) {
+          best_us = us;
+          best = c;
+          best_st = st;
+        }
+      }
+      if (err != hipSuccess) break;
+    }
+    if (err != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->ch[l][role] = best;
+  if (err == hipSuccess) tune_cache_store(key, best, best_st, best_us);
+  return err;
+}
+
+// Tune every pass-kernel level of the plan in precision T.  src0/f0: level-0
+// start value and right-hand side (read only); the workspace arrays are used
+// as outputs and scratch.
+template <typename T>
+hipError_t tune_plan(gmg_plan *p, const T *src0, const T *f0, double *partials0) {
+  tune_cache_load();
+  LevelSet<T> &S = levels_of<T>(p);
+  const bool prof = p->profile;
+  p->profile = false;
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < p->B && l + 1 < p->L && e == hipSuccess; ++l) {
+    const T *f = l == 0 ? f0 : S.f[l];
+    // descent: level 0 reads the start value (and reports its residual norm)
+    e = tune_role<T>(p, l, 0, l == 0 ? src0 : nullptr, nullptr, f, S.w[l], S.t[l],
+                     l == 0 ? partials0 : nullptr, sizeof(T));
+    if (e != hipSuccess) break;
+    // ascent with the fused prolongation from level l+1
+    const T *src = l == 0 ? (src0 ? src0 : S.w[0]) : S.w[l];
+    T *dst = l == 0 ? (src0 ? S.w[0] : S.u[0]) : S.u[l];
+    e = tune_role<T>(p, l, 1, src, S.u[l + 1], f, dst, S.t[l], nullptr, sizeof(T));
+  }
+  p->profile = prof;
+  p->tuned = true;
+  return e;
+}
+
+// ------------------------------------------------------------------ batch
+// Problems are grouped by dimension and level size: every kernel launch of a
+// batched cycle covers all problems that have a level of that size (the
+// table entry of a problem is its blockIdx.y), the bottom levels of all
+// problems run in one launch with one workgroup per problem, and each
+// problem keeps its own solve state, so converged problems drop out (their
+// workgroups return at once) while the others continue.
+struct BatchBuilder {
+  gmg_plan *p;
+  Batch *b;
+  char *ws;  // workspace base (nullptr while sizing)
+  size_t cur = 0;
+  size_t take_bytes(size_t n) { return take(cur, n); }
+  template <typename E>
+  size_t push(const E &e) {
+    const size_t off = b->host_tbl.size();
+    b->host_tbl.resize(off + sizeof(E));
+    std::memcpy(b->host_tbl.data() + off, &e, sizeof(E));
+    return off;
+  }
+  void align_tbl() { b->host_tbl.resize(align_up(b->host_tbl.size())); }
+};
+
+int bottom_first_level(int dim, int L, int smoother) {
+  const int mb = bottom_side_max(dim, smoother, sizeof(double));
+  for (int l = 1; l < L; ++l)
+    if ((1 << (L - l)) - 1 <= mb) return l;
+  return L - 1;
+}
+
+// One chain of passes (nu sweeps) for a set of entries that share a level
+// size.  Per entry: src/ec/f/dst/tmp pointers, which of them are the
+// caller's arrays (patched per call), partial-sum slice and state.
+struct ChainEnt {
+  int q, level;
+  double *src, *ec, *f, *dst, *tmp;
+  bool src_user, f_user, dst_user;
+  double *partials;
+};
+
+void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_flags, bool backward,
+                 const std::vector<ChainEnt> &ents, int cls) {
+  gmg_plan *p = bb.p;
+  Batch *b = bb.b;
+  if (ents.empty() || nu == 0) return;
+  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
+  const PassChoice c = choice_for(p->cfg, dim, m, role, p->smax_cap);
+  const int K = (nu + c.smax - 1) / c.smax;
+  int left = nu;
+  const double h = 1.0 / double(m + 1);
+  const int mc = (m - 1) / 2;
+  for (int k = 1; k <= K; ++k) {
+    const int sw = std::min(c.smax, left - (K - k));
+    const int st = wj ? sw : 2 * sw;
+    const int v = c.var[st];
+    const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
+    const PassGeom g = pass_geometry(dim, m, st, t, c.tz[st]);
+    int flags = backward ? F_BLACK_FIRST : 0;
+    if (k == 1) flags |= first_flags;
+    BOp op;
+    op.kind = BO_PASS;
+    op.dim = dim;
+    op.stages = st;
+    op.flags = flags;
+    op.variant = v;
+    op.wj = wj ? 1 : 0;
+    op.nent = (int)ents.size();
+    op.cls = cls;
+    bb.align_tbl();
+    op.tbl_off = b->host_tbl.size();
+    for (const ChainEnt &e : ents) {
+      // pass k reads buf_{k-1} and writes buf_k; intermediates alternate
+      // between tmp and dst so the last pass lands in dst
+      auto out_of = [&](int j) -> double * { return ((K - j) % 2 == 1) ? e.tmp : e.dst; };
+      auto out_user = [&](int j) -> bool { return ((K - j) % 2 == 1) ? false : e.dst_user; };
+      PassArgs<double> a{};
+      a.u_in = k == 1 ? e.src : out_of(k - 1);
+      a.f = e.f;
+      a.u_out = out_of(k);
+      a.e_c = k == 1 ? e.ec : nullptr;
+      a.partials = (k == 1 && (first_flags & F_NORM_IN)) ? e.partials : nullptr;
+      a.active = &b->pb[e.q].st->active;
+      a.m = m;
+      a.mc = mc;
+      a.ntx = g.ntx;
+      a.nty = g.nty;
+      a.tz = g.tz;
+      a.nblocks = g.nblocks;
+      a.h2 = h * h;
+      a.inv_h2 = 1.0 / (h * h);
+      a.omega = p->cfg.omega;
+      const size_t off = bb.push(a);
+      const bool in_user = k == 1 ? e.src_user : out_user(k - 1);
+      if (in_user) b->patches.push_back({off + offsetof(PassArgs<double>, u_in), e.q, 0});
+      if (e.f_user) b->patches.push_back({off + offsetof(PassArgs<double>, f), e.q, 1});
+      if (out_user(k)) b->patches.push_back({off + offsetof(PassArgs<double>, u_out), e.q, 0});
+      op.bytes += (double)npts(dim, m) * 8.0 * ((k == 1 && (first_flags & F_ZERO_IN)) ? 2 : 3);
+    }
+    b->ops.push_back(op);
+    left -= sw;
+  }
+}
+
+int first_pass_blocks(const gmg_plan *p, int dim, int m, int nu) {
+  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
+  const PassChoice c = choice_for(p->cfg, dim, m, 0, p->smax_cap);
+  const int K = (nu + c.smax - 1) / c.smax;
+  const int sw = std::min(c.smax, nu - (K - 1));
+  const int st = wj ? sw : 2 * sw;
+  return pass_geometry(dim, m, st, pass_variant(dim, st, wj ? 1 : 0, c.var[st]), c.tz[st]).nblocks;
+}
+
+// Lay out the workspace and build the launch list.  ws == nullptr: sizing
+// only (the pointers recorded are offsets and never dereferenced).
+size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *levels, char *ws) {
+  BatchBuilder bb{p, b, ws};
+  const int sm = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+  b->pb.assign(n, BProblem());
+  auto P = [&](size_t off) { return reinterpret_cast<double *>(ws + off); };
+  const size_t st_off = bb.take_bytes(sizeof(SolveState) * (size_t)n);
+  b->states = reinterpret_cast<SolveState *>(ws + st_off);
+  for (int q = 0; q < n; ++q) {
+    BProblem &pr = b->pb[q];
+    pr.dim = dims[q];
+    pr.L = levels[q];
+    pr.B = bottom_first_level(pr.dim, pr.L, sm);
+    pr.m.resize(pr.L);
+    for (int l = 0; l < pr.L; ++l) pr.m[l] = (1 << (pr.L - l)) - 1;
+    pr.st = b->states + q;
+    pr.npart = first_pass_blocks(p, pr.dim, pr.m[0], p->cfg.nu1);
+    pr.partials = P(bb.take_bytes(sizeof(double) * pr.npart));
+    pr.f.assign(pr.L, nullptr);
+    pr.w.assign(pr.L, nullptr);
+    pr.u.assign(pr.L, nullptr);
+    pr.t.assign(pr.L, nullptr);
+    for (int l = 0; l <= pr.B; ++l) {
+      const size_t nb = npts(pr.dim, pr.m[l]) * sizeof(double);
+      if (l == 0) {
+        pr.w[0] = P(bb.take_bytes(nb));
+        if (p->need_tmp) pr.t[0] = P(bb.take_bytes(nb));
+      } else if (l < pr.B) {
+        pr.f[l] = P(bb.take_bytes(nb));
+        pr.w[l] = P(bb.take_bytes(nb));
+        pr.u[l] = P(bb.take_bytes(nb));
+        if (p->need_tmp) pr.t[l] = P(bb.take_bytes(nb));
+      } else {
+        pr.f[l] = P(bb.take_bytes(nb));
+        pr.u[l] = P(bb.take_bytes(nb));
+      }
+    }
+  }
+  const bool bwd = !(p->cfg.flags & GMG_POST_FORWARD);
+  const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
+  b->host_tbl.clear();
+  b->ops.clear();
+  b->patches.clear();
+  for (int dim = 3; dim >= 2; --dim) {
+    int Emax = 0;
+    for (auto &pr : b->pb)
+      if (pr.dim == dim) Emax = std::max(Emax, pr.L);
+    for (int e = Emax; e >= 2; --e) {
+      const int m = (1 << e) - 1;
+      std::vector<ChainEnt> top, coarse;
+      std::vector<int> tops;
+      for (int q = 0; q < n; ++q) {
+        BProblem &pr = b->pb[q];
+        if (pr.dim != dim) continue;
+        const int l = pr.L - e;
+        if (l < 0 || l >= pr.B) continue;
+        if (l == 0) {
+          top.push_back({q, 0, nullptr, nullptr, nullptr, pr.w[0], pr.t[0], true, true, false,
+                         pr.partials});
+          tops.push_back(q);
+        } else {
+          coarse.push_back({q, l, nullptr, nullptr, pr.f[l], pr.w[l], pr.t[l], false, false,
+                            false, nullptr});
+        }
+      }
+      build_chain(bb, dim, m, 0, nu1, F_NORM_IN, false, top, PC_PRE0);
+      if (!tops.empty()) {
+        BOp op;
+        op.kind = BO_FIN;
+        op.nent = (int)tops.size();
+        op.cls = PC_FIN;
+        bb.align_tbl();
+        op.tbl_off = b->host_tbl.size();
+        for (int q : tops) bb.push(FinEntry{b->pb[q].partials, b->pb[q].npart, b->pb[q].st});
+        b->ops.push_back(op);
+      }
+      build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C);
+      // residual + restriction for every entry of this size
+      std::vector<ChainEnt> all = top;
+      all.insert(all.end(), coarse.begin(), coarse.end());
+      if (!all.empty()) {
+        BOp op;
+        op.kind = BO_RESTRICT;
+        op.dim = dim;
+        op.nent = (int)all.size();
+        op.cls = PC_RES_C;
+        bb.align_tbl();
+        op.tbl_off = b->host_tbl.size();
+        const double h = 1.0 / double(m + 1);
+        for (const ChainEnt &ce : all) {
+          BProblem &pr = b->pb[ce.q];
+          RestrictArgs<double> a{};
+          a.u = pr.w[ce.level];
+          a.f = ce.level == 0 ? nullptr : pr.f[ce.level];
+          a.fc = pr.f[ce.level + 1];
+          a.active = &pr.st->active;
+          a.m = m;
+          a.mc = (m - 1) / 2;
+          a.inv_h2 = 1.0 / (h * h);
+          const size_t off = bb.push(a);
+          if (ce.level == 0) b->patches.push_back({off + offsetof(RestrictArgs<double>, f), ce.q, 1});
+          op.bytes += (double)npts(dim, m) * 16.0 + (double)npts(dim, (m - 1) / 2) * 8.0;
+        }
+        b->ops.push_back(op);
+      }
+    }
+  }
+  {  // bottom levels of every problem, one workgroup each
+    BOp op;
+    op.kind = BO_BOTTOM;
+    op.nent = n;
+    op.cls = PC_BOTTOM;
+    bb.align_tbl();
+    op.tbl_off = b->host_tbl.size();
+    for (int q = 0; q < n; ++q) {
+      BProblem &pr = b->pb[q];
+      BottomArgs<double> a{};
+      a.f = pr.f[pr.B];
+      a.u = pr.u[pr.B];
+      a.active = &pr.st->active;
+      a.dim = pr.dim;
+      a.L = pr.L - pr.B;
+      a.nu1 = nu1;
+      a.nu2 = nu2;
+      a.smoother = sm;
+      a.post_forward = bwd ? 0 : 1;
+      a.omega = p->cfg.omega;
+      bb.push(a);
+      const size_t lds = bottom_lds_bytes(pr.dim, a.L, sm, sizeof(double));
+      if (lds > op.lds) {
+        op.lds = lds;
+        op.bottom_L = a.L;
+        op.bottom_dim = pr.dim;
+      }
+    }
+    b->ops.push_back(op);
+  }
+  for (int dim = 3; dim >= 2; --dim) {
+    int Emax = 0;
+    for (auto &pr : b->pb)
+      if (pr.dim == dim) Emax = std::max(Emax, pr.L);
+    for (int e = 2; e <= Emax; ++e) {
+      const int m = (1 << e) - 1;
+      std::vector<ChainEnt> ents;
+      for (int q = 0; q < n; ++q) {
+        BProblem &pr = b->pb[q];
+        if (pr.dim != dim) continue;
+        const int l = pr.L - e;
+        if (l < 0 || l >= pr.B) continue;
+        ents.push_back({q, l, pr.w[l], pr.u[l + 1], l == 0 ? nullptr : pr.f[l],
+                        l == 0 ? nullptr : pr.u[l], pr.t[l], false, l == 0, l == 0, nullptr});
+      }
+      build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, ents, PC_POST_C);
+    }
+  }
+  bb.align_tbl();
+  const size_t tbl_off = bb.take_bytes(b->host_tbl.size());
+  b->dev_tbl = ws + tbl_off;
+  return bb.cur;
+}
+
+hipError_t batch_enqueue_cycle(gmg_plan *p) {
+  Batch *b = p->batch;
+  for (const BOp &op : b->ops) {
+    const char *tbl = b->dev_tbl + op.tbl_off;
+    const char *host = b->host_tbl.data() + op.tbl_off;
+    hipError_t e = hipSuccess;
+    ProfScope ps(p, op.cls, op.bytes);
+    switch (op.kind) {
+      case BO_PASS: {
+        PassArgs<double> a;
+        std::memcpy(&a, host, sizeof(a));
+        e = op.wj ? launch_wj_pass<double>(op.dim, op.stages, op.flags, op.variant, a, p->stream,
+                                           (const PassArgs<double> *)tbl, op.nent)
+                  : launch_rb_pass<double>(op.dim, op.stages, op.flags, op.variant, a, p->stream,
+                                           (const PassArgs<double> *)tbl, op.nent);
+        break;
+      }
+      case BO_RESTRICT: {
+        RestrictArgs<double> a;
+        std::memcpy(&a, host, sizeof(a));
+        e = launch_restrict<double>(op.dim, a, p->stream, (const RestrictArgs<double> *)tbl,
+                                    op.nent);
+        break;
+      }
+      case BO_FIN:
+        e = launch_finalize_batch((const FinEntry *)tbl, op.nent, p->stream);
+        break;
+      case BO_BOTTOM: {
+        BottomArgs<double> a{};
+        a.dim = op.bottom_dim;
+        a.L = op.bottom_L;
+        a.smoother = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+        e = launch_bottom<double>(op.nent, a, (const BottomArgs<double> *)tbl, p->stream, op.lds);
+        break;
+      }
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_run_cycle(gmg_plan *p) {
+  Batch *b = p->batch;
+  if (!(p->cfg.flags & GMG_USE_GRAPH) || p->profile) return batch_enqueue_cycle(p);
+  if (!b->graph) {
+    hipError_t e;
+    if (!p->capture_stream) {
+      e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    hipStream_t keep = p->stream;
+    p->stream = p->capture_stream;
+    e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      p->stream = keep;
+      return e;
+    }
+    hipError_t ee = batch_enqueue_cycle(p);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->capture_stream, &g);
+    p->stream = keep;
+    if (ee != hipSuccess) return ee;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+  }
+  return hipGraphLaunch(b->graph, p->stream);
+}
+
+gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int *levels,
+                       void *workspace, size_t *ws_bytes, void *stream, gmg_plan **out) {
+  if (!dims || !levels) return GMG_ERR_INVALID_ARG;
+  gmg_config c = *cfg;
+  c.dim = dims[0];
+  c.levels = levels[0];
+  gmg_status st = validate_cfg(&c);
+  if (st != GMG_OK) return st;
+  if (c.precision != GMG_FP64) return GMG_ERR_UNSUPPORTED;  // batch: FP64 cycles
+  if (c.nu1 < 1 || c.nu2 < 1) return GMG_ERR_UNSUPPORTED;
+  for (int q = 0; q < n; ++q) {
+    if (dims[q] != 2 && dims[q] != 3) return GMG_ERR_INVALID_ARG;
+    if (levels[q] < 2 || levels[q] > (dims[q] == 3 ? 10 : kMaxLevels)) return GMG_ERR_INVALID_ARG;
+  }
+  gmg_plan tmp;
+  init_plan_shape(tmp, &c);
+  Batch tb;
+  const size_t total = batch_build(&tmp, &tb, n, dims, levels, nullptr);
+  if (!workspace) {
+    *ws_bytes = total;
+    return GMG_OK;
+  }
+  if (!out) return GMG_ERR_INVALID_ARG;
+  if (*ws_bytes < total) return GMG_ERR_WORKSPACE;
+  if (((uintptr_t)workspace) % kAlign) return GMG_ERR_WORKSPACE;
+  gmg_plan *p = new gmg_plan();
+  init_plan_shape(*p, &c);
+  p->nproblems = n;
+  p->stream = (hipStream_t)stream;
+  p->ws = (char *)workspace;
+  p->ws_bytes = total;
+  p->batch = new Batch();
+  batch_build(p, p->batch, n, dims, levels, p->ws);
+  p->prof.resize(PC_COUNT);
+  for (int i = 0; i < PC_COUNT; ++i) p->prof[i].name = kProfNames[i];
+  Batch *b = p->batch;
+  if (hipHostMalloc((void **)&b->pinned, b->host_tbl.size() + 64, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&b->hstates, sizeof(SolveState) * n, hipHostMallocDefault) !=
+          hipSuccess) {
+    if (b->pinned) (void)hipHostFree(b->pinned);
+    delete b;
+    delete p;
+    return GMG_ERR_HIP;
+  }
+  *out = p;
+  return GMG_OK;
 }
 
 }  // namespace
@@ -607,9 +1313,9 @@ gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, cons
                      void *workspace, size_t *ws_bytes, void *stream, gmg_plan **out) {
   if (!ws_bytes) return GMG_ERR_INVALID_ARG;
   if (nproblems < 1) return GMG_ERR_INVALID_ARG;
-  if (nproblems > 1) return GMG_ERR_UNSUPPORTED;  // batch plans: not in this build yet
-  gmg_config c = cfg ? *cfg : gmg_config{};
   if (!cfg) return GMG_ERR_INVALID_ARG;
+  if (nproblems > 1) return batch_setup(cfg, nproblems, dims, levels, workspace, ws_bytes, stream, out);
+  gmg_config c = *cfg;
   if (dims) c.dim = dims[0];
   if (levels) c.levels = levels[0];
   gmg_status st = validate_cfg(&c);
@@ -663,6 +1369,16 @@ gmg_status gmg_destroy(gmg_plan *p) {
   }
   for (auto e : p->evpool) (void)hipEventDestroy(e);
   if (p->hstate) (void)hipHostFree(p->hstate);
+  for (auto &row : p->coarse_graph)
+    for (auto &g : row)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->batch) {
+    if (p->batch->graph) (void)hipGraphExecDestroy(p->batch->graph);
+    if (p->batch->pinned) (void)hipHostFree(p->batch->pinned);
+    if (p->batch->hstates) (void)hipHostFree(p->batch->hstates);
+    delete p->batch;
+  }
   delete p;
   return GMG_OK;
 }
@@ -670,12 +1386,24 @@ gmg_status gmg_destroy(gmg_plan *p) {
 size_t gmg_plan_workspace_bytes(const gmg_plan *p) { return p ? p->ws_bytes : 0; }
 
 int gmg_level_side(const gmg_plan *p, int problem, int level) {
+  if (p && p->batch) {
+    if (problem < 0 || problem >= p->nproblems) return -1;
+    const BProblem &pr = p->batch->pb[problem];
+    if (level < 0 || level >= pr.L) return -1;
+    return pr.m[level];
+  }
   if (!p || problem != 0 || level < 0 || level >= p->L) return -1;
   return p->m[level];
 }
 
 gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f) {
-  if (!p || !u || !f) return GMG_ERR_INVALID_ARG;
+  if (!p || !u || !f || p->batch) return GMG_ERR_INVALID_ARG;
+  if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) {
+    if (p->cfg.precision == GMG_FP64)
+      HIPCHK(tune_plan<double>(p, u, f, nullptr));
+    else
+      HIPCHK(tune_plan<float>(p, nullptr, p->s.f[0], nullptr));
+  }
   if (p->cfg.precision == GMG_FP64) {
     // u -> w0 (pre) ... w0 + P u1 -> u (post): u is never read and written by one pass
     HIPCHK(enqueue_vcycle<double>(p, u, f, u, nullptr, nullptr));
@@ -714,9 +1442,15 @@ static gmg_status read_state(gmg_plan *p) {
 
 gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int maxit,
                      const double *res0_opt, int *iters, double *relres) {
-  if (!p || !u || !f) return GMG_ERR_INVALID_ARG;
+  if (!p || !u || !f || p->batch) return GMG_ERR_INVALID_ARG;
   if (!(rtol > 0.0) || maxit < 1) return GMG_ERR_INVALID_ARG;
   if (res0_opt && !(*res0_opt >= 0.0)) return GMG_ERR_INVALID_ARG;
+  if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) {
+    if (p->cfg.precision == GMG_FP64)
+      HIPCHK(tune_plan<double>(p, u, f, p->partials));
+    else
+      HIPCHK(tune_plan<float>(p, nullptr, p->s.f[0], nullptr));
+  }
   const double r0 = res0_opt ? *res0_opt : -1.0;
   HIPCHK(launch_state_init(p->state, maxit, rtol, r0, p->stream));
   const int *act = &p->state->active;
@@ -784,15 +1518,53 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
 
 gmg_status gmg_batch_solve(gmg_plan *p, double *const *u, const double *const *f, double rtol,
                            int maxit, int *iters, double *relres, gmg_status *st) {
-  (void)u;
-  (void)f;
-  (void)rtol;
-  (void)maxit;
-  (void)iters;
-  (void)relres;
-  (void)st;
-  if (!p) return GMG_ERR_INVALID_ARG;
-  return GMG_ERR_UNSUPPORTED;
+  if (!p || !u || !f) return GMG_ERR_INVALID_ARG;
+  if (!p->batch) return GMG_ERR_INVALID_ARG;
+  if (!(rtol > 0.0) || maxit < 1) return GMG_ERR_INVALID_ARG;
+  Batch *b = p->batch;
+  const int n = p->nproblems;
+  for (int q = 0; q < n; ++q)
+    if (!u[q] || !f[q]) return GMG_ERR_INVALID_ARG;
+  // the caller's arrays go into the level-0 entries of the launch tables
+  for (const auto &pt : b->patches) {
+    void *v = pt.which == 0 ? (void *)u[pt.prob] : (void *)f[pt.prob];
+    std::memcpy(b->host_tbl.data() + pt.off, &v, sizeof(void *));
+  }
+  std::memcpy(b->pinned, b->host_tbl.data(), b->host_tbl.size());
+  HIPCHK(hipMemcpyAsync(b->dev_tbl, b->pinned, b->host_tbl.size(), hipMemcpyHostToDevice,
+                        p->stream));
+  HIPCHK(launch_state_init_batch(b->states, n, maxit, rtol, p->stream));
+  int enq = 0, batch = 2;
+  for (;;) {
+    for (int k = 0; k < batch; ++k, ++enq) HIPCHK(batch_run_cycle(p));
+    HIPCHK(hipMemcpyAsync(b->hstates, b->states, sizeof(SolveState) * n, hipMemcpyDeviceToHost,
+                          p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    int need = 0, active = 0;
+    for (int q = 0; q < n; ++q) {
+      const SolveState &s = b->hstates[q];
+      if (!s.active) continue;
+      ++active;
+      need = std::max(need, estimate_cycles(s, s.iter - 1));
+    }
+    if (!active || enq >= maxit + 1) break;
+    batch = std::max(1, std::min(need, maxit + 1 - enq));
+  }
+  gmg_status worst = GMG_OK;
+  for (int q = 0; q < n; ++q) {
+    const SolveState &s = b->hstates[q];
+    const gmg_status sq = map_status(s.status);
+    if (iters) iters[q] = s.iter;
+    if (relres) relres[q] = s.res0 > 0.0 ? s.res / s.res0 : 0.0;
+    if (st) st[q] = sq;
+    if (sq < 0 && (worst >= 0 || sq < worst)) worst = sq;
+    if (sq == GMG_NOT_CONVERGED && worst == GMG_OK) worst = sq;
+  }
+  if (p->profile) {
+    gmg_status hs = harvest(p);
+    if (hs != GMG_OK) return hs;
+  }
+  return worst;
 }
 
 int gmg_tile_variant_count(int dim, gmg_smoother smoother, int stages) {
@@ -801,30 +1573,29 @@ int gmg_tile_variant_count(int dim, gmg_smoother smoother, int stages) {
 }
 
 gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, int tz) {
-  if (!p || level < 0 || level >= p->L || stages < 1 || stages > 4 || tz < 0)
+  if (!p || p->batch || level < 0 || level >= p->L || stages < 1 || stages > 4 || tz < 0)
     return GMG_ERR_INVALID_ARG;
   const int wj = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
   const int nv = pass_variant_count(p->dim, stages, wj);
   if (variant < 0 || variant >= nv) return GMG_ERR_INVALID_ARG;
-  p->var[level][stages] = variant;
-  if (tz > 0) {
-    p->tz[level][stages] = std::min(tz, p->m[level]);
-  } else {
-    const PassTile t = pass_variant(p->dim, stages, wj, variant);
-    const PassGeom g0 = pass_geometry(p->dim, p->m[level], stages, t, p->m[level]);
-    const int xy = g0.ntx * g0.nty;
-    const int ntz = std::max(1, (3 * 256 + xy - 1) / xy);
-    p->tz[level][stages] = std::max((p->m[level] + ntz - 1) / ntz, std::min(p->m[level], 16));
+  const int sweeps = wj ? stages : stages / 2;
+  if (sweeps < 1 || sweeps > p->smax_cap) return GMG_ERR_INVALID_ARG;
+  const PassTile t = pass_variant(p->dim, stages, wj, variant);
+  const int tzv = tz > 0 ? std::min(tz, p->m[level]) : auto_tz(p->dim, p->m[level], stages, t);
+  if (pass_geometry(p->dim, p->m[level], stages, t, tzv).nblocks > kMaxPartials)
+    return GMG_ERR_INVALID_ARG;
+  for (int role = 0; role < 2; ++role) {
+    PassChoice &c = p->ch[level][role];
+    c.var[stages] = variant;
+    c.tz[stages] = tzv;
+    c.smax = sweeps;
   }
-  const PassGeom g = pass_geometry(p->dim, p->m[level], stages,
-                                   pass_variant(p->dim, stages, wj, variant), p->tz[level][stages]);
-  if (g.nblocks > kMaxPartials) return GMG_ERR_INVALID_ARG;
   return GMG_OK;
 }
 
 // ------------------------------------------------------------------ primitives
 static gmg_status check_level(gmg_plan *p, int level, gmg_dtype dt) {
-  if (!p || level < 0 || level >= p->L) return GMG_ERR_INVALID_ARG;
+  if (!p || p->batch || level < 0 || level >= p->L) return GMG_ERR_INVALID_ARG;
   if (dt != GMG_F64 && dt != GMG_F32) return GMG_ERR_INVALID_ARG;
   return GMG_OK;
 }
@@ -836,7 +1607,8 @@ static gmg_status op_smooth_t(gmg_plan *p, int level, int nsweeps, int backward,
                               const T *f, const T *ec, T *u_out, double *res_in_norm) {
   LevelSet<T> &S = levels_of<T>(p);
   T *tmp = level < (int)S.t.size() ? S.t[level] : nullptr;
-  const int K = nsweeps == 0 ? 0 : (nsweeps + p->smax - 1) / p->smax;
+  const int smax = p->ch[level][ec ? 1 : 0].smax;
+  const int K = nsweeps == 0 ? 0 : (nsweeps + smax - 1) / smax;
   if (K >= 2 && !tmp) return GMG_ERR_UNSUPPORTED;  // plan made without chained-pass scratch
   int nparts = 0;
   HIPCHK(smooth_chain<T>(p, level, nsweeps, backward != 0, u_in, ec, f, u_out, tmp,
@@ -921,6 +1693,12 @@ gmg_status gmg_profile_get(gmg_plan *p, int idx, gmg_kernel_stat *out) {
   out->launches = p->prof[idx].launches;
   out->total_ms = p->prof[idx].ms;
   out->alg_bytes = p->prof[idx].bytes;
+  return GMG_OK;
+}
+
+gmg_status gmg_profile_set_mask(gmg_plan *p, unsigned mask) {
+  if (!p) return GMG_ERR_INVALID_ARG;
+  p->prof_mask = mask;
   return GMG_OK;
 }
 

@@ -108,20 +108,26 @@ int pass_variant_count(int dim, int stages, int wj);
 PassTile pass_variant(int dim, int stages, int wj, int v);
 PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz);
 
+// Launchers.  Batch mode: tbl != NULL points to nent device-resident argument
+// entries (one problem each, all with the same level size); the grid gets a
+// y-dimension of nent and every workgroup reads its entry.
 template <typename T>
 hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<T> a,
-                          hipStream_t s);
+                          hipStream_t s, const PassArgs<T> *tbl = nullptr, int nent = 1);
 template <typename T>
 hipError_t launch_wj_pass(int dim, int sweeps, int flags, int variant, PassArgs<T> a,
-                          hipStream_t s);
+                          hipStream_t s, const PassArgs<T> *tbl = nullptr, int nent = 1);
 template <typename T>
-hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s);
+hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s,
+                           const RestrictArgs<T> *tbl = nullptr, int nent = 1);
 template <typename T>
 hipError_t launch_residual(int dim, ResidArgs<T> a, hipStream_t s);
 int residual_blocks(int dim, int m);
+// bottom: tbl != NULL gives one entry (problem) per workgroup; a.L must then
+// be the largest entry's level count (it sizes the LDS)
 template <typename T>
-hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const T *const *f_list,
-                         T *const *u_list, hipStream_t s);
+hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const BottomArgs<T> *tbl, hipStream_t s,
+                         size_t lds_bytes = 0);
 size_t bottom_lds_bytes(int dim, int L, int smoother, size_t elem);
 hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s);
 int ir_blocks(int dim, int m);
@@ -132,6 +138,14 @@ hipError_t launch_prolong_add(int dim, int m, int mc, const T *in, const T *ec, 
 hipError_t launch_axpy_f32(double *x, const float *e, size_t n, const int *active, hipStream_t s);
 
 hipError_t launch_finalize(const double *partials, int n, SolveState *st, hipStream_t s);
+
+struct FinEntry {
+  const double *partials;
+  int n;
+  SolveState *st;
+};
+hipError_t launch_finalize_batch(const FinEntry *tbl, int n, hipStream_t s);
+hipError_t launch_state_init_batch(SolveState *st, int n, int maxit, double rtol, hipStream_t s);
 hipError_t launch_state_init(SolveState *st, int maxit, double rtol, double res0, hipStream_t s);
 hipError_t launch_reduce_norm(const double *partials, int n, double *out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, const int *active, hipStream_t s);

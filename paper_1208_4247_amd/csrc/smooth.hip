@@ -102,11 +102,105 @@ __device__ __forceinline__ void block_sum_store(double acc, double *out) {
 }
 
 // ------------------------------------------------------------------------
+// Per-slot geometry shared by the passes.  A slot is a pair of adjacent x
+// columns (xb, xb+1), xb even, in row y of the extended tile.
+// ------------------------------------------------------------------------
+struct SlotGeo {
+  int off;       // y*m + xb (3D) / xb (2D): offset inside a plane
+  int q;         // slot index inside the tile (LDS position)
+  int par;       // (y + DIM) & 1: element e has colour (e + par + z) & 1
+  int ok;        // bit0 / bit1: element 0 / 1 inside the domain (x and y); bit2 live
+  int outp;      // slot belongs to the output tile
+  int y;         // row (3D) or 0
+  int xb;
+};
+
+// xy-interpolated coarse correction at one coarse plane for both elements of
+// a slot: e0 (x even: fine node odd, halfway between coarse xb/2-1 and xb/2)
+// and e1 (x odd: fine node even, on coarse column xb/2).  2D: the coarse
+// "plane" is a coarse row.
+template <typename T, int DIM>
+__device__ __forceinline__ void coarse_xy(const T *__restrict__ ec, int mc, int cz, int y, int xb,
+                                          T &v0, T &v1) {
+  v0 = T(0);
+  v1 = T(0);
+  if (cz < 0 || cz >= mc) return;
+  const int cl = (xb >> 1) - 1, cr = xb >> 1;
+  const bool okl = cl >= 0 && cl < mc, okr = cr >= 0 && cr < mc;
+  if (DIM == 2) {
+    const T *row = ec + (size_t)cz * mc;
+    const T el = okl ? row[cl] : T(0), er = okr ? row[cr] : T(0);
+    v0 = T(0.5) * (el + er);
+    v1 = er;
+    return;
+  }
+  // rows: y odd -> coarse row (y-1)/2 (weight 1); y even -> y/2-1, y/2 (1/2)
+  int r0, r1;
+  T w;
+  if (y & 1) {
+    r0 = (y - 1) >> 1;
+    r1 = -1;
+    w = T(1);
+  } else {
+    r0 = (y >> 1) - 1;
+    r1 = y >> 1;
+    w = T(0.5);
+  }
+  const T *pl = ec + (size_t)cz * mc * mc;
+  T el = T(0), er = T(0);
+  if (r0 >= 0 && r0 < mc) {
+    if (okl) el += w * pl[(size_t)r0 * mc + cl];
+    if (okr) er += w * pl[(size_t)r0 * mc + cr];
+  }
+  if (r1 >= 0 && r1 < mc) {
+    if (okl) el += w * pl[(size_t)r1 * mc + cl];
+    if (okr) er += w * pl[(size_t)r1 * mc + cr];
+  }
+  v0 = T(0.5) * (el + er);
+  v1 = er;
+}
+
+template <int DIM, int S_HALO, int EXP, int EY, int NT, int NS>
+__device__ __forceinline__ void slot_setup(SlotGeo (&g)[NS], int X0, int Y0, int m) {
+  constexpr int PL = EXP * EY;
+  constexpr int HP = (S_HALO + 1) / 2;
+  constexpr int H = 2 * HP;
+  constexpr int TXP = EXP - 2 * HP;
+  constexpr int TY = DIM == 3 ? EY - 2 * H : 1;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int q = threadIdx.x + NT * i;
+    const bool live = q < PL;
+    const int p = q % EXP, r = q / EXP;
+    const int xb = X0 - H + 2 * p;
+    const int y = DIM == 3 ? Y0 - H + r : 0;
+    const bool yin = DIM == 2 || (y >= 0 && y < m);
+    g[i].q = live ? q : PL - 1;
+    g[i].xb = xb;
+    g[i].y = y;
+    g[i].off = (DIM == 3 ? y * m : 0) + xb;
+    g[i].par = (y + DIM) & 1;
+    g[i].ok = ((live && yin && xb >= 0 && xb < m) ? 1 : 0) |
+              ((live && yin && xb + 1 >= 0 && xb + 1 < m) ? 2 : 0) | (live ? 4 : 0);
+    g[i].outp = live && yin && p >= HP && p < HP + TXP &&
+                (DIM == 2 || (r >= H && r < H + TY)) && xb < m;
+  }
+}
+
+// ------------------------------------------------------------------------
 // Red-black Gauss-Seidel pass: S half-sweeps, colour of stage s is
 // (C1 + s - 1) mod 2 with C1 = 0 (red first) or 1 (black first).
+//
+// Step t: stage 0 holds the start value of plane t (prefetched during step
+// t-1), stage s computes plane t-s of colour c_s from stage s-1's planes
+// t-s-1 .. t-s+1 (registers) and its in-plane neighbours (LDS, written at
+// step t-1).  Plane t-S leaves the pipeline: colour c_S from stage S, the
+// other colour from stage S-1.
 // ------------------------------------------------------------------------
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
-__global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
+__global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<T> *tbl) {
+  // batch mode: one table entry (problem) per blockIdx.y
+  const PassArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
   if (a.active && *a.active == 0) return;
   constexpr int NS = (EXP * EY + NT - 1) / NT;  // slots per thread
   constexpr int HP = S / 2;                     // halo in pairs
@@ -131,32 +225,20 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
   const int Y0 = ty * TY;
   const int Z0 = tzc * a.tz;
   const int Z1 = min(Z0 + a.tz, m);
-  const size_t rowS = (size_t)m;
-  const size_t planeS = DIM == 3 ? (size_t)m * m : (size_t)m;
+  const int planeS = DIM == 3 ? m * m : m;
   const T h2 = T(a.h2);
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
+  const T *__restrict__ fg = a.f;
+  const T *__restrict__ ug = a.u_in;
 
-  int q[NS], xb[NS], yy[NS], lq[NS], rq[NS], uq[NS], dq[NS];
-  bool live[NS], yin[NS], outp[NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    q[i] = threadIdx.x + NT * i;
-    live[i] = q[i] < PL;
-    const int p = q[i] % EXP, r = q[i] / EXP;
-    xb[i] = X0 - S + 2 * p;
-    yy[i] = DIM == 3 ? Y0 - S + r : 0;
-    yin[i] = DIM == 2 || (yy[i] >= 0 && yy[i] < m);
-    outp[i] = live[i] && yin[i] && p >= HP && p < HP + TXP &&
-              (DIM == 2 || (r >= S && r < S + TY)) && xb[i] < m;
-    const int rr = min(r, EY - 1);
-    lq[i] = rr * EXP + max(p - 1, 0);
-    rq[i] = rr * EXP + min(p + 1, EXP - 1);
-    uq[i] = max(rr - 1, 0) * EXP + p;
-    dq[i] = min(rr + 1, EY - 1) * EXP + p;
-  }
+  SlotGeo g[NS];
+  slot_setup<DIM, S, EXP, EY, NT, NS>(g, X0, Y0, m);
 
   T W[S][NS][3];  // stage windows: [0] newest plane, [1] previous, [2] two back
   T WB[NORM ? NS : 1][3];
+  T pu0[NS], pu1[NS];  // start value of the plane being entered (both elements)
+  T cl0[PRO ? NS : 1], cl1[PRO ? NS : 1], ch0[PRO ? NS : 1], ch1[PRO ? NS : 1];
+  T cn0[PRO ? NS : 1], cn1[PRO ? NS : 1];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -165,30 +247,88 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
   for (int i = 0; i < (NORM ? NS : 1); ++i) WB[i][0] = WB[i][1] = WB[i][2] = T(0);
   double acc = 0.0;
 
-  for (int t = Z0 - S; t < Z1 + S; ++t) {
-    const bool tin = t >= 0 && t < m;
-    // ---- stage 0: start value on plane t
+  const int t0 = Z0 - S, t1 = Z1 + S;
+  auto load_u = [&](int t, T *v0, T *v1) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      T v0 = T(0), v1 = T(0);
-      const int e0 = (C0 + yy[i] + t + DIM) & 1;  // element holding colour C0
-      if (live[i] && tin && yin[i]) {
-        const size_t base = (size_t)t * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
-        const int x0 = xb[i];
-        if (!ZERO) {
-          if (x0 >= 0 && x0 < m) v0 = a.u_in[base + x0];
-          if (x0 + 1 >= 0 && x0 + 1 < m) v1 = a.u_in[base + x0 + 1];
+      v0[i] = T(0);
+      v1[i] = T(0);
+      if (!ZERO && t >= 0 && t < m) {
+        const int o = t * planeS + g[i].off;
+        if (g[i].ok & 1) v0[i] = ug[o];
+        if (g[i].ok & 2) v1[i] = ug[o + 1];
+      }
+    }
+  };
+  load_u(t0, pu0, pu1);
+  if (PRO) {
+    // state at the start of step t0: even t0 needs coarse planes t0/2-1 (lo)
+    // and t0/2 (hi); odd t0 needs plane (t0-1)/2 (hi)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      cl0[i] = cl1[i] = cn0[i] = cn1[i] = T(0);
+      if (t0 & 1) {
+        coarse_xy<T, DIM>(a.e_c, a.mc, (t0 - 1) >> 1, g[i].y, g[i].xb, ch0[i], ch1[i]);
+      } else {
+        coarse_xy<T, DIM>(a.e_c, a.mc, (t0 >> 1) - 1, g[i].y, g[i].xb, cl0[i], cl1[i]);
+        coarse_xy<T, DIM>(a.e_c, a.mc, t0 >> 1, g[i].y, g[i].xb, ch0[i], ch1[i]);
+      }
+    }
+  }
+
+  for (int t = t0; t < t1; ++t) {
+    // ---- issue the loads of this step: next plane's start value, the
+    // right-hand side of every stage, the next coarse plane
+    T nu0[NS], nu1[NS];
+    load_u(t + 1, nu0, nu1);
+    T fs[S][NS];
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+      const int zs = t - s;
+      const int cs = (C1 + s - 1) & 1;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int es = (cs + g[i].par + zs) & 1;
+        fs[s - 1][i] = (zs >= 0 && zs < m && ((g[i].ok >> es) & 1))
+                           ? fg[zs * planeS + g[i].off + es]
+                           : T(0);
+      }
+    }
+    T fb[NORM ? NS : 1];  // NORM: f of the colour-C0 element of plane t-1
+    if (NORM) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const int zr = t - 1;
+        const int e0 = (C0 + g[i].par + zr) & 1;
+        fb[i] = (zr >= Z0 && zr < Z1 && g[i].outp && ((g[i].ok >> e0) & 1))
+                    ? fg[zr * planeS + g[i].off + e0]
+                    : T(0);
+      }
+    }
+    if (PRO) {
+      if (t & 1) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+          coarse_xy<T, DIM>(a.e_c, a.mc, (t + 1) >> 1, g[i].y, g[i].xb, cn0[i], cn1[i]);
+      }
+    }
+    // ---- stage 0: start value on plane t (colour C0 into the window)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e0 = (C0 + g[i].par + t) & 1;
+      T v0 = pu0[i], v1 = pu1[i];
+      if (PRO) {
+        T c0, c1;
+        if (t & 1) {  // fine node t+1 even: on a coarse plane
+          c0 = ch0[i];
+          c1 = ch1[i];
+        } else {      // between coarse planes t/2-1 and t/2
+          c0 = T(0.5) * (cl0[i] + ch0[i]);
+          c1 = T(0.5) * (cl1[i] + ch1[i]);
         }
-        if (PRO) {
-          const int xe = x0 + e0;
-          if (xe >= 0 && xe < m) {
-            const T c = DIM == 3 ? interp<T, 3>(a.e_c, a.mc, xe, yy[i], t)
-                                 : interp<T, 2>(a.e_c, a.mc, xe, t, 0);
-            if (e0)
-              v1 += c;
-            else
-              v0 += c;
-          }
+        if (t >= 0 && t < m) {
+          if (g[i].ok & 1) v0 += c0;
+          if (g[i].ok & 2) v1 += c1;
         }
       }
       W[0][i][2] = W[0][i][1];
@@ -204,32 +344,33 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
     if (NORM) {
       const int zr = t - 1;
       if (zr >= Z0 && zr < Z1) {
-        const T *L0 = lds;            // colour C0 values of plane t-1
-        const T *LB = lds + S * PL;   // colour C1 values of plane t-1
+        const T *L0 = lds;           // colour C0 values of plane t-1
+        const T *LB = lds + S * PL;  // colour C1 values of plane t-1
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-          if (!outp[i]) continue;
-          const int e0 = (C0 + yy[i] + zr + DIM) & 1;
-          const size_t base = (size_t)zr * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
+          if (!g[i].outp) continue;
+          const int e0 = (C0 + g[i].par + zr) & 1;
+          const int qc = g[i].q;
+          const int lq = max(qc - 1, 0), rq = min(qc + 1, PL - 1);
+          const int uq = max(qc - EXP, 0), dq = min(qc + EXP, PL - 1);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {  // c = 0: the C0 element, 1: the C1 element
+          for (int c = 0; c < 2; ++c) {  // 0: the colour-C0 element, 1: the other
             const int e = c == 0 ? e0 : 1 - e0;
-            const int x = xb[i] + e;
-            if (x >= m) continue;
+            if (!((g[i].ok >> e) & 1)) continue;
             const T self = c == 0 ? W[0][i][1] : WB[i][1];
             const T own = c == 0 ? WB[i][1] : W[0][i][1];
             const T *Ln = c == 0 ? LB : L0;
-            const T side = e ? Ln[rq[i]] : Ln[lq[i]];
-            T nb = e ? own : side;
-            nb += e ? side : own;
+            const T side = e ? Ln[rq] : Ln[lq];
+            T nb = own + side;
             if (DIM == 3) {
-              nb += Ln[uq[i]];
-              nb += Ln[dq[i]];
+              nb += Ln[uq];
+              nb += Ln[dq];
             }
             nb += c == 0 ? WB[i][2] : W[0][i][2];
             nb += c == 0 ? WB[i][0] : W[0][i][0];
-            const double r = double(a.f[base + x]) -
-                             (double(T(2 * DIM) * self) - double(nb)) * a.inv_h2;
+            // colour-C1 element's f is stage 1's right-hand side
+            const T fv = c == 0 ? fb[i] : fs[0][i];
+            const double r = double(fv) - (double(T(2 * DIM) * self) - double(nb)) * a.inv_h2;
             acc += r * r;
           }
         }
@@ -240,28 +381,22 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int zs = t - s;
-      const bool zin = zs >= 0 && zs < m;
       const int cs = (C1 + s - 1) & 1;
       const T *L = lds + (s - 1) * PL;
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        const int es = (cs + yy[i] + zs + DIM) & 1;
-        const T own = W[s - 1][i][1];
-        const T side = es ? L[rq[i]] : L[lq[i]];
-        T nb = es ? own : side;  // x - 1
-        nb += es ? side : own;   // x + 1
+        const int es = (cs + g[i].par + zs) & 1;
+        const int qc = g[i].q;
+        const int sq = es ? min(qc + 1, PL - 1) : max(qc - 1, 0);
+        T nb = W[s - 1][i][1] + L[sq];  // x-1 and x+1 (one is the own pair)
         if (DIM == 3) {
-          nb += L[uq[i]];        // y - 1
-          nb += L[dq[i]];        // y + 1
+          nb += L[max(qc - EXP, 0)];     // y - 1
+          nb += L[min(qc + EXP, PL - 1)];  // y + 1
         }
-        nb += W[s - 1][i][2];    // marching axis - 1
-        nb += W[s - 1][i][0];    // marching axis + 1
-        const int x = xb[i] + es;
-        T v = T(0);
-        if (live[i] && zin && yin[i] && x >= 0 && x < m) {
-          const size_t idx = (size_t)zs * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0) + x;
-          v = fma(h2, a.f[idx], nb) * inv2d;
-        }
+        nb += W[s - 1][i][2];  // marching axis - 1
+        nb += W[s - 1][i][0];  // marching axis + 1
+        const bool in = zs >= 0 && zs < m && ((g[i].ok >> es) & 1);
+        const T v = in ? fma(h2, fs[s - 1][i], nb) * inv2d : T(0);
         if (s < S) {
           W[s][i][2] = W[s][i][1];
           W[s][i][1] = W[s][i][0];
@@ -277,24 +412,39 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
       constexpr int CS = (C1 + S - 1) & 1;
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        if (!outp[i]) continue;
-        const int es = (CS + yy[i] + zo + DIM) & 1;
+        if (!g[i].outp) continue;
+        const int es = (CS + g[i].par + zo) & 1;
         const T o_new = newS[i], o_old = W[S - 1][i][1];
-        const size_t base = (size_t)zo * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
-        const int x0 = xb[i];
-        a.u_out[base + x0] = es ? o_old : o_new;
-        if (x0 + 1 < m) a.u_out[base + x0 + 1] = es ? o_new : o_old;
+        const int o = zo * planeS + g[i].off;
+        a.u_out[o] = es ? o_old : o_new;
+        if (g[i].ok & 2) a.u_out[o + 1] = es ? o_new : o_old;
       }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      if (!live[i]) continue;
+      if (!(g[i].ok & 4)) continue;
 #pragma unroll
-      for (int s = 0; s < S; ++s) lds[s * PL + q[i]] = W[s][i][0];
-      if (NORM) lds[S * PL + q[i]] = WB[i][0];
+      for (int s = 0; s < S; ++s) lds[s * PL + g[i].q] = W[s][i][0];
+      if (NORM) lds[S * PL + g[i].q] = WB[i][0];
     }
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      pu0[i] = nu0[i];
+      pu1[i] = nu1[i];
+    }
+    if (PRO) {
+      if (t & 1) {  // next step is even: shift the coarse planes
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          cl0[i] = ch0[i];
+          cl1[i] = ch1[i];
+          ch0[i] = cn0[i];
+          ch1[i] = cn1[i];
+        }
+      }
+    }
   }
   if (NORM) block_sum_store<NT>(acc, a.partials);
 }
@@ -304,7 +454,9 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> a) {
 // every pair from the previous stage's values.
 // ------------------------------------------------------------------------
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
-__global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> a) {
+__global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<T> *tbl) {
+  // batch mode: one table entry (problem) per blockIdx.y
+  const PassArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
   if (a.active && *a.active == 0) return;
   constexpr int NS = (EXP * EY + NT - 1) / NT;
   constexpr int HP = (S + 1) / 2;  // halo in pairs (>= S points)
@@ -490,8 +642,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> a) {
 // ------------------------------------------------------------------------
 // Each entry: pairs per extended row, extended rows, threads.  Output tile:
 // TX = 2*(EXP - 2*halo_pairs), TY = EY - 2*halo (3D).
-#define GMG_RB3_S2(X) X(3, 2, 66, 30, 512) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 256)
-#define GMG_RB3_S4(X) X(3, 4, 68, 30, 512) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
+#define GMG_RB3_S2(X) X(3, 2, 66, 30, 1024) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 512)
+#define GMG_RB3_S4(X) X(3, 4, 68, 30, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
 #define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 #define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
 #define GMG_WJ3_S1(X) X(3, 1, 66, 18, 256) X(3, 1, 34, 18, 128)
@@ -558,7 +710,7 @@ PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz) {
 
 namespace {
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
-hipError_t run_rb(PassArgs<T> a, hipStream_t st) {
+hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
   const size_t lds = sizeof(T) * EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0));
   auto k = k_rb_pass<T, DIM, S, EXP, EY, NT, FL>;
   static bool attr = false;
@@ -568,12 +720,12 @@ hipError_t run_rb(PassArgs<T> a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(NT), lds, st, a);
+  hipLaunchKernelGGL(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
   return hipGetLastError();
 }
 
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
-hipError_t run_wj(PassArgs<T> a, hipStream_t st) {
+hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
   const size_t lds = sizeof(T) * EXP * EY * 2 * S;
   auto k = k_wj_pass<T, DIM, S, EXP, EY, NT, FL>;
   static bool attr = false;
@@ -583,28 +735,28 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(NT), lds, st, a);
+  hipLaunchKernelGGL(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
   return hipGetLastError();
 }
 
 // The fused-flag combinations a cycle uses.
 #define GMG_FLAG_SWITCH(RUN, T, D, S, E, Y, N)                                            \
   switch (flags) {                                                                     \
-    case 0: return RUN<T, D, S, E, Y, N, 0>(a, st);                                    \
-    case F_ZERO_IN: return RUN<T, D, S, E, Y, N, F_ZERO_IN>(a, st);                    \
-    case F_PROLONG: return RUN<T, D, S, E, Y, N, F_PROLONG>(a, st);                    \
-    case F_NORM_IN: return RUN<T, D, S, E, Y, N, F_NORM_IN>(a, st);                    \
-    case F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_BLACK_FIRST>(a, st);            \
-    case F_ZERO_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_ZERO_IN | F_BLACK_FIRST>(a, st); \
-    case F_PROLONG | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST>(a, st); \
-    case F_NORM_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_NORM_IN | F_BLACK_FIRST>(a, st); \
+    case 0: return RUN<T, D, S, E, Y, N, 0>(a, st, tbl, nent);                                    \
+    case F_ZERO_IN: return RUN<T, D, S, E, Y, N, F_ZERO_IN>(a, st, tbl, nent);                    \
+    case F_PROLONG: return RUN<T, D, S, E, Y, N, F_PROLONG>(a, st, tbl, nent);                    \
+    case F_NORM_IN: return RUN<T, D, S, E, Y, N, F_NORM_IN>(a, st, tbl, nent);                    \
+    case F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_BLACK_FIRST>(a, st, tbl, nent);            \
+    case F_ZERO_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_ZERO_IN | F_BLACK_FIRST>(a, st, tbl, nent); \
+    case F_PROLONG | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST>(a, st, tbl, nent); \
+    case F_NORM_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_NORM_IN | F_BLACK_FIRST>(a, st, tbl, nent); \
     default: return hipErrorInvalidValue;                                              \
   }
 }  // namespace
 
 template <typename T>
 hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<T> a,
-                          hipStream_t st) {
+                          hipStream_t st, const PassArgs<T> *tbl, int nent) {
   const PassTile t = pass_variant(dim, stages, 0, variant);
   if (t.nt == 0) return hipErrorInvalidValue;
 #define GMG_TRY(D, S, E, Y, N)                                       \
@@ -618,7 +770,7 @@ hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<
 
 template <typename T>
 hipError_t launch_wj_pass(int dim, int sweeps, int flags, int variant, PassArgs<T> a,
-                          hipStream_t st) {
+                          hipStream_t st, const PassArgs<T> *tbl, int nent) {
   const PassTile t = pass_variant(dim, sweeps, 1, variant);
   if (t.nt == 0) return hipErrorInvalidValue;
   flags &= ~F_BLACK_FIRST;
@@ -631,9 +783,13 @@ hipError_t launch_wj_pass(int dim, int sweeps, int flags, int variant, PassArgs<
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_rb_pass<double>(int, int, int, int, PassArgs<double>, hipStream_t);
-template hipError_t launch_rb_pass<float>(int, int, int, int, PassArgs<float>, hipStream_t);
-template hipError_t launch_wj_pass<double>(int, int, int, int, PassArgs<double>, hipStream_t);
-template hipError_t launch_wj_pass<float>(int, int, int, int, PassArgs<float>, hipStream_t);
+template hipError_t launch_rb_pass<double>(int, int, int, int, PassArgs<double>, hipStream_t,
+                                           const PassArgs<double> *, int);
+template hipError_t launch_rb_pass<float>(int, int, int, int, PassArgs<float>, hipStream_t,
+                                          const PassArgs<float> *, int);
+template hipError_t launch_wj_pass<double>(int, int, int, int, PassArgs<double>, hipStream_t,
+                                           const PassArgs<double> *, int);
+template hipError_t launch_wj_pass<float>(int, int, int, int, PassArgs<float>, hipStream_t,
+                                          const PassArgs<float> *, int);
 
 }  // namespace gmg

@@ -30,11 +30,15 @@ __device__ __forceinline__ T ld0(const T *__restrict__ p, int m, int x, int y, i
 // ------------------------------------------------------------------------
 // Residual + full weighting: the residual is formed in LDS one fine plane at
 // a time and reduced to coarse points without ever being stored.
-// Workgroup: a CX x CY block of coarse columns (3D), marching over coarse z.
+// Workgroup: a CX x CY block of coarse columns (3D; CX x 1 in 2D) marching
+// over a chunk of coarse planes (rows in 2D).  Fine u planes sit in a
+// three-plane LDS ring; the next u plane and the next f plane are loaded into
+// registers one step ahead, so global latency overlaps the LDS work.
 // ------------------------------------------------------------------------
 template <typename T, int DIM, int CX, int CY, int NT>
-__global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> a, int ncx, int ncy, int czc,
-                                                 int nblocks) {
+__global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const RestrictArgs<T> *tbl,
+                                                 int ncx, int ncy, int czc, int nblocks) {
+  const RestrictArgs<T> a = tbl ? tbl[blockIdx.y] : arg;  // batch: one entry per blockIdx.y
   if (a.active && *a.active == 0) return;
   const int m = a.m, mc = a.mc;
   const int bid = xcd_remap_t(blockIdx.x, nblocks);
@@ -42,81 +46,111 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> a, int ncx, int
   const int rest = bid / ncx;
   const int by = DIM == 3 ? rest % ncy : 0;
   const int bz = DIM == 3 ? rest / ncy : rest;
-  // coarse ranges
   const int A0 = bx * CX;
   const int B0 = DIM == 3 ? by * CY : 0;
-  const int C0 = bz * czc;  // coarse planes (3D) / rows (2D) of this block
+  const int C0 = bz * czc;
   const int C1 = min(C0 + czc, mc);
-  // fine residual region (storage): x in [2A0, 2A0 + 2CX], y likewise (3D)
   constexpr int RX = 2 * CX + 1;
   constexpr int RY = DIM == 3 ? 2 * CY + 1 : 1;
   constexpr int UX = RX + 2;
   constexpr int UY = DIM == 3 ? RY + 2 : 1;
-  __shared__ T su[3][UY * UX];  // fine u planes z-1, z, z+1 (ring)
+  constexpr int NU = (UX * UY + NT - 1) / NT;
+  constexpr int NR = (RX * RY + NT - 1) / NT;
+  __shared__ T su[3][UY * UX];  // fine u planes, ring indexed by (z + 3) % 3
   __shared__ T sr[RY * RX];     // fine residual of the current plane
   const T inv_h2 = T(a.inv_h2);
   const T two_d = T(2 * DIM);
-  const int xF0 = 2 * A0 - 1;           // u region origin (fine storage)
-  const int yF0 = DIM == 3 ? 2 * B0 - 1 : 0;
-  const size_t planeS = DIM == 3 ? (size_t)m * m : (size_t)m;
+  const int planeS = DIM == 3 ? m * m : m;
+  const T *__restrict__ ug = a.u;
+  const T *__restrict__ fg = a.f;
 
-  // coarse point owned by this thread (one per thread in the restriction step)
+  // u-tile element q -> plane offset (or -1 outside the domain)
+  int uo[NU];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int q = threadIdx.x + NT * k;
+    const int ux = q % UX, uy = q / UX;
+    const int x = 2 * A0 - 1 + ux, y = DIM == 3 ? 2 * B0 - 1 + uy : 0;
+    const bool in = q < UX * UY && x >= 0 && x < m && y >= 0 && y < m;
+    uo[k] = in ? (DIM == 3 ? y * m + x : x) : -1;
+  }
+  int ro[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const int q = threadIdx.x + NT * k;
+    const int rx = q % RX, ry = q / RX;
+    const int x = 2 * A0 + rx, y = DIM == 3 ? 2 * B0 + ry : 0;
+    const bool in = q < RX * RY && x < m && y < m;
+    ro[k] = in ? (DIM == 3 ? y * m + x : x) : -1;
+  }
+  auto load_u = [&](int z, T *v) {
+#pragma unroll
+    for (int k = 0; k < NU; ++k) v[k] = (z >= 0 && z < m && uo[k] >= 0) ? ug[z * planeS + uo[k]] : T(0);
+  };
+  auto load_f = [&](int z, T *v) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = (z >= 0 && z < m && ro[k] >= 0) ? fg[z * planeS + ro[k]] : T(0);
+  };
+  auto store_u = [&](int z, const T *v) {
+    T *dst = su[(z + 3) % 3];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      const int q = threadIdx.x + NT * k;
+      if (q < UX * UY) dst[q] = v[k];
+    }
+  };
+
   const int cxl = threadIdx.x % CX;
   const int cyl = DIM == 3 ? (threadIdx.x / CX) % CY : 0;
   const bool cown = threadIdx.x < CX * (DIM == 3 ? CY : 1);
   const int cx = A0 + cxl, cy = B0 + cyl;
-  T acc_cur = T(0), acc_next = T(0);
+  const bool cvalid = cown && cx < mc && (DIM == 2 || cy < mc);
+  T acc = T(0);
 
-  // fine planes needed: 2*C0 .. 2*C1 (storage), u planes one more each side
-  const int zf_begin = 2 * C0, zf_end = 2 * C1;  // inclusive range of r planes
-  auto load_u_plane = [&](int slot, int zf) {
-    for (int q = threadIdx.x; q < UY * UX; q += NT) {
-      const int ux = q % UX, uy = q / UX;
-      const int x = xF0 + ux, y = DIM == 3 ? yF0 + uy : zf;
-      T v = T(0);
-      if (DIM == 3)
-        v = ld0(a.u, m, x, y, zf, 3);
-      else
-        v = ld0(a.u, m, x, zf, 0, 2);
-      su[slot][q] = v;
-    }
-  };
-  // ring: slot of fine plane z is (z + 3) % 3 (z may be -1)
-  load_u_plane((zf_begin - 1 + 3) % 3, zf_begin - 1);
-  load_u_plane((zf_begin + 3) % 3, zf_begin);
-  for (int zf = zf_begin; zf <= zf_end; ++zf) {
-    load_u_plane((zf + 1 + 3) % 3, zf + 1);
-    __syncthreads();
+  const int zf0 = 2 * C0, zf1 = 2 * C1;  // fine residual planes zf0 .. zf1
+  {
+    T v[NU];
+    load_u(zf0 - 1, v);
+    store_u(zf0 - 1, v);
+    load_u(zf0, v);
+    store_u(zf0, v);
+    load_u(zf0 + 1, v);
+    store_u(zf0 + 1, v);
+  }
+  T pf[NR];
+  load_f(zf0, pf);
+  __syncthreads();
+  for (int zf = zf0; zf <= zf1; ++zf) {
+    T nu[NU], nf[NR];
+    load_u(zf + 2, nu);
+    load_f(zf + 1, nf);
     const T *um = su[(zf - 1 + 3) % 3];
     const T *u0 = su[(zf + 3) % 3];
     const T *up = su[(zf + 1 + 3) % 3];
-    for (int q = threadIdx.x; q < RY * RX; q += NT) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int q = threadIdx.x + NT * k;
+      if (q >= RX * RY) continue;
       const int rx = q % RX, ry = q / RX;
-      const int x = 2 * A0 + rx, y = DIM == 3 ? 2 * B0 + ry : zf;
       T r = T(0);
-      if (x < m && y < m && zf < m) {
+      if (ro[k] >= 0 && zf < m) {
         const int c = (ry + (DIM == 3 ? 1 : 0)) * UX + rx + 1;  // centre in the u tile
         T nb = u0[c - 1] + u0[c + 1];
         if (DIM == 3) {
           nb += u0[c - UX];
           nb += u0[c + UX];
-          nb += um[c];
-          nb += up[c];
-        } else {
-          nb += um[c];
-          nb += up[c];
         }
-        const T fv = DIM == 3 ? a.f[(size_t)zf * planeS + (size_t)y * m + x]
-                              : a.f[(size_t)zf * m + x];
-        r = fv - (two_d * u0[c] - nb) * inv_h2;
+        nb += um[c];
+        nb += up[c];
+        r = pf[k] - (two_d * u0[c] - nb) * inv_h2;
       }
       sr[q] = r;
     }
     __syncthreads();
-    // weight of this fine plane for coarse planes: zf = 2c+1 -> 1/2 for c;
-    // zf = 2c+2 -> 1/4 for c and c+1.  In 2D the "plane" is a fine row.
-    if (cown && cx < mc && (DIM == 2 || cy < mc)) {
-      const int lx = 2 * cxl + 1;  // fine centre column in the r tile
+    // fine plane zf = 2c+1 weighs 1/2 for coarse plane c; zf = 2c+2 weighs
+    // 1/4 for coarse planes c and c+1
+    if (cvalid) {
+      const int lx = 2 * cxl + 1;
       T sxy;
       if (DIM == 3) {
         const int ly = 2 * cyl + 1;
@@ -129,20 +163,22 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> a, int ncx, int
         sxy = T(0.25) * sr[lx - 1] + T(0.5) * sr[lx] + T(0.25) * sr[lx + 1];
       }
       if (zf & 1) {
-        acc_cur += T(0.5) * sxy;
+        acc += T(0.5) * sxy;
       } else {
-        const int c = zf / 2 - 1;  // coarse plane completed by this fine plane
+        const int c = zf / 2 - 1;
         if (c >= C0) {
-          acc_cur += T(0.25) * sxy;
+          acc += T(0.25) * sxy;
           const size_t o = DIM == 3 ? ((size_t)c * mc + cy) * mc + cx : (size_t)c * mc + cx;
-          a.fc[o] = acc_cur;
+          a.fc[o] = acc;
         }
-        acc_cur = T(0.25) * sxy;  // contribution to coarse plane c+1
+        acc = T(0.25) * sxy;
       }
     }
+    store_u(zf + 2, nu);  // the ring slot of plane zf-1, read before the barrier
+#pragma unroll
+    for (int k = 0; k < NR; ++k) pf[k] = nf[k];
     __syncthreads();
   }
-  (void)acc_next;
 }
 
 // ------------------------------------------------------------------------
@@ -290,6 +326,49 @@ __global__ void __launch_bounds__(64) k_finalize(const double *partials, int n, 
   }
 }
 
+// batch: one workgroup per table entry
+__global__ void __launch_bounds__(64) k_finalize_batch(const FinEntry *tbl) {
+  const FinEntry e = tbl[blockIdx.x];
+  SolveState *st = e.st;
+  if (st->active == 0) return;
+  const double tot = sum_partials(e.partials, e.n);
+  if (threadIdx.x == 0) {
+    const double res = sqrt(tot);
+    if (st->res0 < 0.0) st->res0 = res;
+    st->res = res;
+    const double res0 = st->res0;
+    if (!isfinite(res)) {
+      st->status = -3;
+      st->active = 0;
+    } else if (!(res > st->rtol * res0)) {
+      st->status = 0;
+      st->active = 0;
+    } else if (res > 1e3 * res0 && st->iter > 0) {
+      st->status = -4;
+      st->active = 0;
+    } else if (st->iter >= st->maxit) {
+      st->status = 1;
+      st->active = 0;
+    } else {
+      st->iter += 1;
+    }
+  }
+}
+
+__global__ void k_state_init_batch(SolveState *st, int n, int maxit, double rtol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    st[i].active = 1;
+    st[i].iter = 0;
+    st[i].maxit = maxit;
+    st[i].status = 0;
+    st[i].rtol = rtol;
+    st[i].res0 = -1.0;
+    st[i].res = 0.0;
+    st[i].pad = 0.0;
+  }
+}
+
 __global__ void k_reduce_norm(const double *partials, int n, double *out) {
   const double tot = sum_partials(partials, n);
   if (threadIdx.x == 0) *out = sqrt(tot);
@@ -377,25 +456,34 @@ __global__ void __launch_bounds__(256) k_axpy_f32(double *x, const float *__rest
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
-namespace {
-constexpr int kRX3 = 32, kRY3 = 8, kRX2 = 64;
-}
-
 template <typename T>
-hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s) {
+hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s, const RestrictArgs<T> *tbl,
+                           int nent) {
+  // tile and chunk by size: small coarse grids get small tiles and short
+  // chunks (many short-lived workgroups), large ones long chunks
+  const int mc = a.mc;
   if (dim == 3) {
-    const int ncx = (a.mc + kRX3 - 1) / kRX3, ncy = (a.mc + kRY3 - 1) / kRY3;
-    const int czc = a.mc < 16 ? a.mc : 16;
-    const int ncz = (a.mc + czc - 1) / czc;
-    const int nb = ncx * ncy * ncz;
-    hipLaunchKernelGGL((k_restrict<T, 3, kRX3, kRY3, 256>), dim3(nb), dim3(256), 0, s, a, ncx,
-                       ncy, czc, nb);
+    if (mc >= 64) {
+      const int ncx = (mc + 31) / 32, ncy = (mc + 7) / 8;
+      const int czc = mc >= 256 ? 8 : 4;
+      const int ncz = (mc + czc - 1) / czc;
+      const int nb = ncx * ncy * ncz;
+      hipLaunchKernelGGL((k_restrict<T, 3, 32, 8, 256>), dim3(nb, nent), dim3(256), 0, s, a, tbl, ncx,
+                         ncy, czc, nb);
+    } else {
+      const int ncx = (mc + 15) / 16, ncy = (mc + 7) / 8;
+      const int czc = mc >= 16 ? 2 : 1;
+      const int ncz = (mc + czc - 1) / czc;
+      const int nb = ncx * ncy * ncz;
+      hipLaunchKernelGGL((k_restrict<T, 3, 16, 8, 128>), dim3(nb, nent), dim3(128), 0, s, a, tbl, ncx,
+                         ncy, czc, nb);
+    }
   } else {
-    const int ncx = (a.mc + kRX2 - 1) / kRX2;
-    const int czc = a.mc < 32 ? a.mc : 32;
-    const int ncz = (a.mc + czc - 1) / czc;
+    const int ncx = (mc + 63) / 64;
+    const int czc = mc >= 512 ? 16 : (mc >= 128 ? 8 : 2);
+    const int ncz = (mc + czc - 1) / czc;
     const int nb = ncx * ncz;
-    hipLaunchKernelGGL((k_restrict<T, 2, kRX2, 1, 128>), dim3(nb), dim3(128), 0, s, a, ncx, 1,
+    hipLaunchKernelGGL((k_restrict<T, 2, 64, 1, 128>), dim3(nb, nent), dim3(128), 0, s, a, tbl, ncx, 1,
                        czc, nb);
   }
   return hipGetLastError();
@@ -422,6 +510,17 @@ hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s) {
 
 hipError_t launch_finalize(const double *partials, int n, SolveState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, n, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const FinEntry *tbl, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_batch, dim3(n), dim3(64), 0, s, tbl);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init_batch(SolveState *st, int n, int maxit, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init_batch, dim3((n + 255) / 256), dim3(256), 0, s, st, n, maxit, rtol);
   return hipGetLastError();
 }
 
@@ -479,8 +578,10 @@ template hipError_t launch_prolong_add<double>(int, int, int, const double *, co
                                                double *, const int *, hipStream_t);
 template hipError_t launch_prolong_add<float>(int, int, int, const float *, const float *, float *,
                                               const int *, hipStream_t);
-template hipError_t launch_restrict<double>(int, RestrictArgs<double>, hipStream_t);
-template hipError_t launch_restrict<float>(int, RestrictArgs<float>, hipStream_t);
+template hipError_t launch_restrict<double>(int, RestrictArgs<double>, hipStream_t,
+                                            const RestrictArgs<double> *, int);
+template hipError_t launch_restrict<float>(int, RestrictArgs<float>, hipStream_t,
+                                           const RestrictArgs<float> *, int);
 template hipError_t launch_residual<double>(int, ResidArgs<double>, hipStream_t);
 template hipError_t launch_residual<float>(int, ResidArgs<float>, hipStream_t);
 

@@ -1,0 +1,98 @@
+"""Per-kernel timings of the hot path on one GPU (the methodology of the
+paper's matrix-free matvec tables, Sec. 5.2 Tables 3-4, applied to every
+kernel of the cycle): each fused pass, tile shape and z-chunk is timed with
+device events over repeated launches and reported as microseconds and
+algorithmic HBM GB/s.
+
+    python -m paper_1208_4247_amd.microbench --dim 3 --m 255
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+import torch
+
+from .solver import Plan
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps  # microseconds
+
+
+def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=None):
+    L = (m + 1).bit_length() - 1
+    plan = Plan(dim, L, smoother=smoother, nu1=2, nu2=2)
+    n = m ** dim
+    mc = (m - 1) // 2
+    es = torch.finfo(dtype).bits // 8
+    g = torch.Generator(device="cuda").manual_seed(0)
+    f = torch.rand((m,) * dim, dtype=dtype, device="cuda", generator=g)
+    u = torch.rand((m,) * dim, dtype=dtype, device="cuda", generator=g) * 1e-3
+    o = torch.empty_like(u)
+    e = torch.rand((mc,) * dim, dtype=dtype, device="cuda", generator=g) * 1e-3
+    fc = torch.empty((mc,) * dim, dtype=dtype, device="cuda")
+    rows = []
+    stage_counts = (2, 4) if smoother == "rbgs" else (1, 2)
+    for st in stage_counts:
+        nsw = st // 2 if smoother == "rbgs" else st
+        for v in range(plan.tile_variants(st)):
+            for tz in tzs:
+                plan.set_tile(0, st, v, tz)
+                for kind in ("plain", "zero", "prolong", "prolong_bwd"):
+                    if kind == "plain":
+                        fn = lambda: plan.op_smooth(0, nsw, False, u, f, None, o)
+                        nb = 3 * n * es
+                    elif kind == "zero":
+                        fn = lambda: plan.op_smooth(0, nsw, False, None, f, None, o)
+                        nb = 2 * n * es
+                    elif kind == "prolong":
+                        fn = lambda: plan.op_smooth(0, nsw, False, u, f, e, o)
+                        nb = 3 * n * es + mc ** dim * es
+                    else:
+                        fn = lambda: plan.op_smooth(0, nsw, True, u, f, e, o)
+                        nb = 3 * n * es + mc ** dim * es
+                    us = _time(fn, reps)
+                    rows.append(dict(kernel="%s_pass" % smoother, stages=st, variant=v, tz=tz,
+                                     kind=kind, us=us, gbs=nb / (us * 1e-6) / 1e9))
+    us = _time(lambda: plan.op_restrict_residual(0, u, f, fc), reps)
+    rows.append(dict(kernel="resid_restrict", us=us,
+                     gbs=(2 * n + mc ** dim) * es / (us * 1e-6) / 1e9))
+    us = _time(lambda: plan.op_residual(0, u, f, o, want_norm=False), reps)
+    rows.append(dict(kernel="residual", us=us, gbs=3 * n * es / (us * 1e-6) / 1e9))
+    for r in rows:
+        print(json.dumps(r), flush=True)
+    if out:
+        with open(out, "a") as fh:
+            for r in rows:
+                fh.write(json.dumps(dict(r, dim=dim, m=m)) + "\n")
+    plan.close()
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dim", type=int, default=3)
+    ap.add_argument("--m", type=int, nargs="+", default=[255])
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--smoother", default="rbgs")
+    ap.add_argument("--tz", type=int, nargs="+", default=[0])
+    ap.add_argument("--fp32", action="store_true")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    for m in a.m:
+        print("# dim %d m %d" % (a.dim, m), flush=True)
+        run(a.dim, m, a.reps, torch.float32 if a.fp32 else torch.float64, a.smoother, a.tz, a.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,5 +127,76 @@ class Plan:
             out[st.name.decode()] = dict(launches=st.launches, ms=st.total_ms, bytes=st.alg_bytes)
         return out
 
+    PROFILE_CLASSES = ["smooth_pre_l0", "smooth_post_l0", "resid_restrict_l0", "smooth_pre_coarse",
+                       "smooth_post_coarse", "resid_restrict_coarse", "bottom", "finalize",
+                       "ir_step", "misc"]
+
+    def profile_only(self, names):
+        mask = 0
+        for n in names:
+            mask |= 1 << self.PROFILE_CLASSES.index(n)
+        capi.check(capi.lib().gmg_profile_set_mask(self._plan, mask), "gmg_profile_set_mask")
+
+    def profile_reset(self):
+        capi.check(capi.lib().gmg_profile_reset(self._plan), "gmg_profile_reset")
+
+
+class BatchPlan:
+    """Many independent problems of uneven sizes solved together: every
+    kernel launch covers all problems with a level of that size."""
+
+    def __init__(self, problems, smoother: str = "rbgs", nu1: int = 2, nu2: int = 2,
+                 omega: float = 0.0, flags: int = 0):
+        L = capi.lib()
+        dims = [int(d) for d, _ in problems]
+        levels = [int(lv) for _, lv in problems]
+        cfg = capi.config_default(dims[0], levels[0])
+        cfg.smoother = {"rbgs": capi.GMG_SMOOTH_RBGS, "wj": capi.GMG_SMOOTH_WJ}[smoother]
+        cfg.nu1, cfg.nu2 = int(nu1), int(nu2)
+        cfg.omega = float(omega)
+        cfg.flags = int(flags)
+        self.cfg = cfg
+        self.n = len(problems)
+        self.problems = list(zip(dims, levels))
+        s, nbytes = capi.workspace_bytes(cfg, self.n, dims, levels)
+        capi.check(s, "gmg_setup(batch size query)")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        da = (ctypes.c_int * self.n)(*dims)
+        la = (ctypes.c_int * self.n)(*levels)
+        n = ctypes.c_size_t(nbytes)
+        plan = ctypes.c_void_p()
+        s = L.gmg_setup(ctypes.byref(cfg), self.n, da, la, _ptr(self.workspace), ctypes.byref(n),
+                        _stream(), ctypes.byref(plan))
+        capi.check(s, "gmg_setup(batch)")
+        self._plan = plan
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            capi.lib().gmg_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, us, fs, rtol: float = 1e-10, maxit: int = 100):
+        n = self.n
+        ua = (ctypes.c_void_p * n)(*[t.data_ptr() for t in us])
+        fa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in fs])
+        for t in list(us) + list(fs):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
+                raise ValueError("expected contiguous float64 device tensors")
+        it = (ctypes.c_int * n)()
+        rel = (ctypes.c_double * n)()
+        st = (ctypes.c_int * n)()
+        s = capi.lib().gmg_batch_solve(self._plan, ua, fa, float(rtol), int(maxit), it, rel, st)
+        capi.check(s, "gmg_batch_solve")
+        return s, list(it), list(rel), list(st)
+
+    def profile(self):
+        return Plan.profile(self)
+
     def profile_reset(self):
         capi.check(capi.lib().gmg_profile_reset(self._plan), "gmg_profile_reset")

@@ -74,16 +74,22 @@ def test_wj_omega_range(capi):
 
 
 def test_workspace_size_model(capi):
-    """Workspace ~ coarse u, w, f (3 * N0 / (2^d - 1)) + one level-0
-    ping-pong array (N0) + small fixed state, the paper's memory model
-    (Sec. 4 remark on space complexity) plus the pre-smoothed copy."""
+    """Workspace against the paper's memory model (Sec. 4, remark on the space
+    complexity of the V-cycle: u_l, f_l on every level and r_l below the
+    coarsest): here the caller's u, f are level 0, the residual is never
+    stored, and the workspace holds the coarse u, w (pre-smoothed), f
+    (3 * N0 / (2^d - 1)) plus the level-0 pre-smoothed copy w0 (N0); with
+    nu >= 2 every level also carries one scratch array for chained passes
+    (+N0 + N0 / (2^d - 1))."""
     for d, L in [(2, 10), (3, 8)]:
-        c = capi.config_default(d, L)
-        s, n = capi.workspace_bytes(c)
-        assert s == 0
-        N0 = ((1 << L) - 1) ** d
-        model = 8 * (N0 + 3 * N0 / (2 ** d - 1))
-        assert 0.9 * model < n < 1.1 * model + (1 << 20), (n, model)
+        for nu, arrays0, arrays_c in [(1, 1, 3), (2, 2, 4)]:
+            c = capi.config_default(d, L)
+            c.nu1 = c.nu2 = nu
+            s, n = capi.workspace_bytes(c)
+            assert s == 0
+            N0 = ((1 << L) - 1) ** d
+            model = 8 * (arrays0 * N0 + arrays_c * N0 / (2 ** d - 1))
+            assert 0.9 * model < n < 1.05 * model + (1 << 20), (d, nu, n, model)
 
 
 def test_setup_null_checks(capi):
