@@ -79,6 +79,9 @@ typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
 #define GMG_POST_FORWARD 0x8u       /* post-smooth red->black (textbook order)
                                        instead of Algorithm 1's backward sweep */
 #define GMG_NO_TEMPORAL_BLOCKING 0x10u /* one fused sweep per pass at most     */
+#define GMG_NO_FUSED_COARSE 0x20u   /* small coarse levels through the general
+                                       passes instead of the fused LDS-tile
+                                       kernels (same results, for testing)    */
 
 typedef struct {
   int dim;                 /* 2 or 3                                            */

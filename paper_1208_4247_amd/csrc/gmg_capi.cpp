@@ -96,7 +96,7 @@ struct BProblem {
 
 // One launch of the batched cycle; its argument entries live in a device
 // table (byte offset tbl_off in the table region).
-enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3 };
+enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3, BO_SMALL_DOWN = 4, BO_SMALL_UP = 5 };
 struct BOp {
   int kind = BO_PASS;
   int dim = 3, stages = 0, flags = 0, variant = 0, wj = 0, nent = 0;
@@ -358,7 +358,8 @@ hipError_t smooth_chain(gmg_plan *p, int level, int nsweeps, bool backward, cons
 
 template <typename T>
 hipError_t restrict_level(gmg_plan *p, int level, const T *u, const T *f, T *fc,
-                          const int *active, int cls) {
+                          const int *active, int cls, const double *fin_partials = nullptr,
+                          int fin_n = 0) {
   const int m = p->m[level];
   if (!u) {  // zero iterate: the residual is f itself
     u = nullptr;
@@ -372,6 +373,9 @@ hipError_t restrict_level(gmg_plan *p, int level, const T *u, const T *f, T *fc,
   a.mc = p->m[level + 1];
   const double h = 1.0 / double(m + 1);
   a.inv_h2 = 1.0 / (h * h);
+  a.fin_partials = fin_partials;
+  a.fin_n = fin_n;
+  a.fin_state = fin_partials ? p->state : nullptr;
   ProfScope ps(p, cls, (double)npts(p->dim, m) * sizeof(T) * 2 + (double)npts(p->dim, a.mc) * sizeof(T));
   return launch_restrict<T>(p->dim, a, p->stream);
 }
@@ -387,6 +391,12 @@ LevelSet<float> &levels_of<float>(gmg_plan *p) {
   return p->s;
 }
 
+// Small coarse levels go through the fused LDS-tile kernels (red-black only).
+bool use_small(const gmg_plan *p, int dim, int m, int nu, size_t elem) {
+  return p->cfg.smoother == GMG_SMOOTH_RBGS && !(p->cfg.flags & GMG_NO_FUSED_COARSE) && nu >= 1 &&
+         small_level_ok(dim, m, nu, elem);
+}
+
 // Levels 1..B-1 of the descent, the bottom kernel and levels B-1..1 of the
 // ascent: everything of a cycle that touches only workspace arrays.
 template <typename T>
@@ -397,6 +407,24 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
   const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
   hipError_t e;
   for (int l = 1; l < B; ++l) {
+    const int m = p->m[l];
+    const double h = 1.0 / double(m + 1);
+    if (use_small(p, p->dim, m, nu1, sizeof(T))) {
+      SmallArgs<T> a{};
+      a.f = S.f[l];
+      a.w = S.w[l];
+      a.fc = S.f[l + 1];
+      a.active = active;
+      a.m = m;
+      a.mc = p->m[l + 1];
+      a.nsweeps = nu1;
+      a.h2 = h * h;
+      a.inv_h2 = 1.0 / (h * h);
+      ProfScope ps(p, PC_PRE_C, (double)npts(p->dim, m) * sizeof(T) * 2);
+      e = launch_small<T>(p->dim, true, a, p->stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     e = smooth_chain<T>(p, l, nu1, false, nullptr, nullptr, S.f[l], S.w[l], S.t[l], nullptr,
                         active, PC_PRE_C, nullptr);
     if (e != hipSuccess) return e;
@@ -420,6 +448,26 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
     if (e != hipSuccess) return e;
   }
   for (int l = B - 1; l >= 1; --l) {
+    const int m = p->m[l];
+    if (use_small(p, p->dim, m, nu2, sizeof(T))) {
+      const double h = 1.0 / double(m + 1);
+      SmallArgs<T> a{};
+      a.f = S.f[l];
+      a.w = S.w[l];
+      a.ec = S.u[l + 1];
+      a.u = S.u[l];
+      a.active = active;
+      a.m = m;
+      a.mc = p->m[l + 1];
+      a.nsweeps = nu2;
+      a.black_first = bwd ? 1 : 0;
+      a.h2 = h * h;
+      a.inv_h2 = 1.0 / (h * h);
+      ProfScope ps(p, PC_POST_C, (double)npts(p->dim, m) * sizeof(T) * 3);
+      e = launch_small<T>(p->dim, false, a, p->stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     e = smooth_chain<T>(p, l, nu2, bwd, S.w[l], S.u[l + 1], S.f[l], S.u[l], S.t[l], nullptr,
                         active, PC_POST_C, nullptr);
     if (e != hipSuccess) return e;
@@ -505,15 +553,11 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
   e = smooth_chain<T>(p, 0, nu1, false, u0_in, nullptr, f0, S.w[0], S.t[0], norm_partials, active,
                       PC_PRE0, &nparts);
   if (e != hipSuccess) return e;
-  if (norm_partials) {
-    ProfScope ps(p, PC_FIN, 0.0);
-    e = launch_finalize(norm_partials, nparts, p->state, p->stream);
-    if (e != hipSuccess) return e;
-  }
   // (nu1 == 0: the chain copied the start value into w0, so the post-pass
   // below never reads the array it writes)
   const T *w0 = S.w[0];
-  e = restrict_level<T>(p, 0, w0, f0, S.f[1], active, PC_RES0);
+  // the stop test runs in workgroup 0 of the level-0 restriction
+  e = restrict_level<T>(p, 0, w0, f0, S.f[1], active, PC_RES0, norm_partials, nparts);
   if (e != hipSuccess) return e;
   e = run_coarse<T>(p, active);
   if (e != hipSuccess) return e;
@@ -1071,10 +1115,42 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
         for (int q : tops) bb.push(FinEntry{b->pb[q].partials, b->pb[q].npart, b->pb[q].st});
         b->ops.push_back(op);
       }
-      build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C);
+      const bool small = use_small(p, dim, m, nu1, sizeof(double));
+      if (small && !coarse.empty()) {
+        BOp op;
+        op.kind = BO_SMALL_DOWN;
+        op.dim = dim;
+        op.nent = (int)coarse.size();
+        op.cls = PC_PRE_C;
+        bb.align_tbl();
+        op.tbl_off = b->host_tbl.size();
+        const double h = 1.0 / double(m + 1);
+        const int ct = small_tile_coarse(dim);
+        const int ntile = (m + 2 * ct - 1) / (2 * ct);
+        for (const ChainEnt &ce : coarse) {
+          BProblem &pr = b->pb[ce.q];
+          SmallArgs<double> a{};
+          a.f = pr.f[ce.level];
+          a.w = pr.w[ce.level];
+          a.fc = pr.f[ce.level + 1];
+          a.active = &pr.st->active;
+          a.m = m;
+          a.mc = (m - 1) / 2;
+          a.nsweeps = nu1;
+          a.ntile = ntile;
+          a.nblocks = dim == 3 ? ntile * ntile * ntile : ntile * ntile;
+          a.h2 = h * h;
+          a.inv_h2 = 1.0 / (h * h);
+          bb.push(a);
+          op.bytes += (double)npts(dim, m) * 16.0;
+        }
+        b->ops.push_back(op);
+      } else {
+        build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C);
+      }
       // residual + restriction for every entry of this size
       std::vector<ChainEnt> all = top;
-      all.insert(all.end(), coarse.begin(), coarse.end());
+      if (!small) all.insert(all.end(), coarse.begin(), coarse.end());
       if (!all.empty()) {
         BOp op;
         op.kind = BO_RESTRICT;
@@ -1147,7 +1223,45 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
         ents.push_back({q, l, pr.w[l], pr.u[l + 1], l == 0 ? nullptr : pr.f[l],
                         l == 0 ? nullptr : pr.u[l], pr.t[l], false, l == 0, l == 0, nullptr});
       }
-      build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, ents, PC_POST_C);
+      if (use_small(p, dim, m, nu2, sizeof(double))) {
+        std::vector<ChainEnt> top, coarse;
+        for (const ChainEnt &ce : ents) (ce.level == 0 ? top : coarse).push_back(ce);
+        build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, top, PC_POST_C);
+        if (!coarse.empty()) {
+          BOp op;
+          op.kind = BO_SMALL_UP;
+          op.dim = dim;
+          op.nent = (int)coarse.size();
+          op.cls = PC_POST_C;
+          bb.align_tbl();
+          op.tbl_off = b->host_tbl.size();
+          const double h = 1.0 / double(m + 1);
+          const int ct = small_tile_coarse(dim);
+          const int ntile = (m + 2 * ct - 1) / (2 * ct);
+          for (const ChainEnt &ce : coarse) {
+            BProblem &pr = b->pb[ce.q];
+            SmallArgs<double> a{};
+            a.f = pr.f[ce.level];
+            a.w = pr.w[ce.level];
+            a.ec = pr.u[ce.level + 1];
+            a.u = pr.u[ce.level];
+            a.active = &pr.st->active;
+            a.m = m;
+            a.mc = (m - 1) / 2;
+            a.nsweeps = nu2;
+            a.black_first = bwd ? 1 : 0;
+            a.ntile = ntile;
+            a.nblocks = dim == 3 ? ntile * ntile * ntile : ntile * ntile;
+            a.h2 = h * h;
+            a.inv_h2 = 1.0 / (h * h);
+            bb.push(a);
+            op.bytes += (double)npts(dim, m) * 24.0;
+          }
+          b->ops.push_back(op);
+        }
+      } else {
+        build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, ents, PC_POST_C);
+      }
     }
   }
   bb.align_tbl();
@@ -1174,7 +1288,7 @@ hipError_t batch_enqueue_cycle(gmg_plan *p) {
         break;
       }
       case BO_RESTRICT: {
-        RestrictArgs<double> a;
+        RestrictArgs<double> a{};
         std::memcpy(&a, host, sizeof(a));
         e = launch_restrict<double>(op.dim, a, p->stream, (const RestrictArgs<double> *)tbl,
                                     op.nent);
@@ -1183,6 +1297,14 @@ hipError_t batch_enqueue_cycle(gmg_plan *p) {
       case BO_FIN:
         e = launch_finalize_batch((const FinEntry *)tbl, op.nent, p->stream);
         break;
+      case BO_SMALL_DOWN:
+      case BO_SMALL_UP: {
+        SmallArgs<double> a;
+        std::memcpy(&a, host, sizeof(a));
+        e = launch_small<double>(op.dim, op.kind == BO_SMALL_DOWN, a, p->stream,
+                                 (const SmallArgs<double> *)tbl, op.nent);
+        break;
+      }
       case BO_BOTTOM: {
         BottomArgs<double> a{};
         a.dim = op.bottom_dim;

@@ -51,6 +51,12 @@ struct RestrictArgs {
   const int *active;
   int m, mc;
   double inv_h2;
+  // optional stop test of the solve loop, done by workgroup 0 before its
+  // share of the restriction (fin_state NULL: none).  The other workgroups
+  // may still restrict in the cycle that converges; nothing reads that.
+  const double *fin_partials;
+  int fin_n;
+  SolveState *fin_state;
 };
 
 template <typename T>
@@ -76,6 +82,22 @@ struct BottomArgs {
   int smoother;         // 0 RBGS, 1 WJ
   int post_forward;     // post-smoothing in forward order
   double omega;
+};
+
+// Fused LDS-tile kernels for small coarse levels (descent: zero start,
+// nsweeps forward sweeps, w = result, fc = FW(f - A w); ascent: u = nsweeps
+// sweeps from w + P ec).  ntile/nblocks are filled by the launcher (batch
+// entries must carry the same values).
+template <typename T>
+struct SmallArgs {
+  const T *f;
+  T *w;
+  T *fc;
+  const T *ec;
+  T *u;
+  const int *active;
+  int m, mc, nsweeps, black_first, ntile, nblocks;
+  double h2, inv_h2;
 };
 
 // Outer step of iterative refinement (FP64 residual around FP32 cycles).
@@ -130,6 +152,12 @@ hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const BottomArgs<T> *tb
                          size_t lds_bytes = 0);
 size_t bottom_lds_bytes(int dim, int L, int smoother, size_t elem);
 hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s);
+bool small_level_ok(int dim, int m, int nsweeps, size_t elem);
+size_t small_lds_bytes(int dim, int nsweeps, bool down, size_t elem);
+int small_tile_coarse(int dim);
+template <typename T>
+hipError_t launch_small(int dim, bool down, SmallArgs<T> a, hipStream_t s,
+                        const SmallArgs<T> *tbl = nullptr, int nent = 1);
 int ir_blocks(int dim, int m);
 
 template <typename T>

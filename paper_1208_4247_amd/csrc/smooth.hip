@@ -42,48 +42,24 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return xcd * per + min(xcd, rem) + loc;
 }
 
-// Per-axis linear interpolation from the coarse grid to fine storage index x:
-// fine node x+1 even -> coarse storage (x-1)/2 with weight 1; odd -> coarse
-// storage x/2-1 and x/2 with weight 1/2 each.
-template <typename T>
-__device__ __forceinline__ int lin_axis(int x, int *c, T *w) {
-  if (x & 1) {  // node x+1 even
-    c[0] = (x - 1) >> 1;
-    w[0] = T(1);
-    return 1;
-  }
-  c[0] = (x >> 1) - 1;
-  c[1] = x >> 1;
-  w[0] = T(0.5);
-  w[1] = T(0.5);
-  return 2;
-}
-
-// (P e)(x, y, z): tensor-product linear interpolation, zero coarse boundary.
+// (P e)(x, y, z): linear interpolation from the coarse grid, zero coarse
+// boundary, in the canonical order of the library (average along x, then y,
+// then z).  Per axis, fine storage index v odd (fine node even) lies on
+// coarse storage (v-1)/2; v even lies halfway between v/2-1 and v/2.
 template <typename T, int DIM>
 __device__ __forceinline__ T interp(const T *__restrict__ ec, int mc, int x, int y, int z) {
-  int cx[2], cy[2], cz[2];
-  T wx[2], wy[2], wz[2];
-  const int nx = lin_axis<T>(x, cx, wx);
-  const int ny = lin_axis<T>(y, cy, wy);
-  T s = T(0);
-  if (DIM == 2) {
-    for (int b = 0; b < ny; ++b)
-      for (int a = 0; a < nx; ++a) {
-        const int i = cx[a], j = cy[b];
-        if (i >= 0 && i < mc && j >= 0 && j < mc) s += wx[a] * wy[b] * ec[(size_t)j * mc + i];
-      }
-  } else {
-    const int nz = lin_axis<T>(z, cz, wz);
-    for (int c = 0; c < nz; ++c)
-      for (int b = 0; b < ny; ++b)
-        for (int a = 0; a < nx; ++a) {
-          const int i = cx[a], j = cy[b], k = cz[c];
-          if (i >= 0 && i < mc && j >= 0 && j < mc && k >= 0 && k < mc)
-            s += wx[a] * wy[b] * wz[c] * ec[((size_t)k * mc + j) * mc + i];
-        }
-  }
-  return s;
+  auto cv = [&](int a, int b, int c) -> T {
+    if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) return T(0);
+    return ec[DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a];
+  };
+  auto xs = [&](int b, int c) {
+    return (x & 1) ? cv((x - 1) >> 1, b, c) : T(0.5) * (cv((x >> 1) - 1, b, c) + cv(x >> 1, b, c));
+  };
+  auto ys = [&](int c) {
+    return (y & 1) ? xs((y - 1) >> 1, c) : T(0.5) * (xs((y >> 1) - 1, c) + xs(y >> 1, c));
+  };
+  if (DIM == 2) return ys(0);
+  return (z & 1) ? ys((z - 1) >> 1) : T(0.5) * (ys((z >> 1) - 1) + ys(z >> 1));
 }
 
 template <int NT>
@@ -134,30 +110,34 @@ __device__ __forceinline__ void coarse_xy(const T *__restrict__ ec, int mc, int 
     v1 = er;
     return;
   }
-  // rows: y odd -> coarse row (y-1)/2 (weight 1); y even -> y/2-1, y/2 (1/2)
+  // rows: y odd -> coarse row (y-1)/2; y even -> average of y/2-1 and y/2
   int r0, r1;
-  T w;
   if (y & 1) {
     r0 = (y - 1) >> 1;
     r1 = -1;
-    w = T(1);
   } else {
     r0 = (y >> 1) - 1;
     r1 = y >> 1;
-    w = T(0.5);
   }
+  // canonical order shared by every prolongation in the library: average
+  // along x first, then y, then z
   const T *pl = ec + (size_t)cz * mc * mc;
-  T el = T(0), er = T(0);
-  if (r0 >= 0 && r0 < mc) {
-    if (okl) el += w * pl[(size_t)r0 * mc + cl];
-    if (okr) er += w * pl[(size_t)r0 * mc + cr];
+  auto row = [&](int r, T &x0, T &x1) {
+    const T el = okl ? pl[(size_t)r * mc + cl] : T(0);
+    const T er = okr ? pl[(size_t)r * mc + cr] : T(0);
+    x0 = T(0.5) * (el + er);
+    x1 = er;
+  };
+  T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
+  if (r0 >= 0 && r0 < mc) row(r0, a0, a1);
+  if (r1 < 0) {  // y odd: on a coarse row
+    v0 = a0;
+    v1 = a1;
+    return;
   }
-  if (r1 >= 0 && r1 < mc) {
-    if (okl) el += w * pl[(size_t)r1 * mc + cl];
-    if (okr) er += w * pl[(size_t)r1 * mc + cr];
-  }
-  v0 = T(0.5) * (el + er);
-  v1 = er;
+  if (r1 < mc) row(r1, b0, b1);
+  v0 = T(0.5) * (a0 + b0);
+  v1 = T(0.5) * (a1 + b1);
 }
 
 template <int DIM, int S_HALO, int EXP, int EY, int NT, int NS>

@@ -28,6 +28,40 @@ __device__ __forceinline__ T ld0(const T *__restrict__ p, int m, int x, int y, i
 }
 
 // ------------------------------------------------------------------------
+// Fixed-order reduction of per-block partial sums (the first 64 threads) and
+// the stop test of the solve loop (Algorithm 3's while condition).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double sum_partials(const double *p, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) s += p[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  return s;
+}
+
+__device__ __forceinline__ void update_state(SolveState *st, double tot) {
+  const double res = sqrt(tot);
+  if (st->res0 < 0.0) st->res0 = res;
+  st->res = res;
+  const double res0 = st->res0;
+  if (!isfinite(res)) {
+    st->status = -3;
+    st->active = 0;
+  } else if (!(res > st->rtol * res0)) {
+    st->status = 0;
+    st->active = 0;
+  } else if (res > 1e3 * res0 && st->iter > 0) {
+    st->status = -4;
+    st->active = 0;
+  } else if (st->iter >= st->maxit) {
+    st->status = 1;
+    st->active = 0;
+  } else {
+    st->iter += 1;  // admit one more cycle
+  }
+}
+
+// ------------------------------------------------------------------------
 // Residual + full weighting: the residual is formed in LDS one fine plane at
 // a time and reduced to coarse points without ever being stored.
 // Workgroup: a CX x CY block of coarse columns (3D; CX x 1 in 2D) marching
@@ -40,6 +74,10 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
                                                  int ncx, int ncy, int czc, int nblocks) {
   const RestrictArgs<T> a = tbl ? tbl[blockIdx.y] : arg;  // batch: one entry per blockIdx.y
   if (a.active && *a.active == 0) return;
+  if (a.fin_state && blockIdx.x == 0 && threadIdx.x < 64) {
+    const double tot = sum_partials(a.fin_partials, a.fin_n);
+    if (threadIdx.x == 0) update_state(a.fin_state, tot);
+  }
   const int m = a.m, mc = a.mc;
   const int bid = xcd_remap_t(blockIdx.x, nblocks);
   const int bx = bid % ncx;
@@ -288,42 +326,10 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
 
 int ir_blocks(int dim, int m) { return residual_blocks(dim, m); }
 
-// ------------------------------------------------------------------------
-// Fixed-order reduction of per-block partial sums; updates the solve state
-// (Algorithm 3's while test).
-// ------------------------------------------------------------------------
-__device__ __forceinline__ double sum_partials(const double *p, int n) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 64) s += p[i];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-  return s;
-}
-
 __global__ void __launch_bounds__(64) k_finalize(const double *partials, int n, SolveState *st) {
   if (st->active == 0) return;
   const double tot = sum_partials(partials, n);
-  if (threadIdx.x == 0) {
-    const double res = sqrt(tot);
-    if (st->res0 < 0.0) st->res0 = res;
-    st->res = res;
-    const double res0 = st->res0;
-    if (!isfinite(res)) {
-      st->status = -3;
-      st->active = 0;
-    } else if (!(res > st->rtol * res0)) {
-      st->status = 0;
-      st->active = 0;
-    } else if (res > 1e3 * res0 && st->iter > 0) {
-      st->status = -4;
-      st->active = 0;
-    } else if (st->iter >= st->maxit) {
-      st->status = 1;
-      st->active = 0;
-    } else {
-      st->iter += 1;  // admit one more cycle
-    }
-  }
+  if (threadIdx.x == 0) update_state(st, tot);
 }
 
 // batch: one workgroup per table entry
@@ -332,27 +338,7 @@ __global__ void __launch_bounds__(64) k_finalize_batch(const FinEntry *tbl) {
   SolveState *st = e.st;
   if (st->active == 0) return;
   const double tot = sum_partials(e.partials, e.n);
-  if (threadIdx.x == 0) {
-    const double res = sqrt(tot);
-    if (st->res0 < 0.0) st->res0 = res;
-    st->res = res;
-    const double res0 = st->res0;
-    if (!isfinite(res)) {
-      st->status = -3;
-      st->active = 0;
-    } else if (!(res > st->rtol * res0)) {
-      st->status = 0;
-      st->active = 0;
-    } else if (res > 1e3 * res0 && st->iter > 0) {
-      st->status = -4;
-      st->active = 0;
-    } else if (st->iter >= st->maxit) {
-      st->status = 1;
-      st->active = 0;
-    } else {
-      st->iter += 1;
-    }
-  }
+  if (threadIdx.x == 0) update_state(st, tot);
 }
 
 __global__ void k_state_init_batch(SolveState *st, int n, int maxit, double rtol) {
@@ -417,30 +403,22 @@ __global__ void __launch_bounds__(256) k_prolong_add(const T *in, const T *__res
     const size_t rest = p / m;
     const int y = (int)(rest % m);
     const int z = DIM == 3 ? (int)(rest / m) : 0;
-    auto axis = [](int v, int *c, T *w) -> int {
-      if (v & 1) {
-        c[0] = (v - 1) >> 1;
-        w[0] = T(1);
-        return 1;
-      }
-      c[0] = (v >> 1) - 1;
-      c[1] = v >> 1;
-      w[0] = w[1] = T(0.5);
-      return 2;
+    // canonical order: average along x, then y, then z (zero coarse boundary)
+    auto cv = [&](int a, int b, int c) -> T {
+      if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) return T(0);
+      return ec[DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a];
     };
-    int cx[2], cy[2], cz[2] = {0, 0};
-    T wx[2], wy[2], wz[2] = {T(1), T(1)};
-    const int nx = axis(x, cx, wx), ny = axis(y, cy, wy);
-    const int nz = DIM == 3 ? axis(z, cz, wz) : 1;
-    T s = T(0);
-    for (int k = 0; k < nz; ++k)
-      for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-          const int a = cx[i], b = cy[j], c = cz[k];
-          if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) continue;
-          const size_t o = DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a;
-          s += (DIM == 3 ? wx[i] * wy[j] * wz[k] : wx[i] * wy[j]) * ec[o];
-        }
+    auto xs = [&](int b, int c) {
+      return (x & 1) ? cv((x - 1) >> 1, b, c) : T(0.5) * (cv((x >> 1) - 1, b, c) + cv(x >> 1, b, c));
+    };
+    auto ys = [&](int c) {
+      return (y & 1) ? xs((y - 1) >> 1, c) : T(0.5) * (xs((y >> 1) - 1, c) + xs(y >> 1, c));
+    };
+    T s;
+    if (DIM == 3)
+      s = (z & 1) ? ys((z - 1) >> 1) : T(0.5) * (ys((z >> 1) - 1) + ys(z >> 1));
+    else
+      s = ys(0);
     out[p] = (in ? in[p] : T(0)) + s;
   }
 }

@@ -275,3 +275,26 @@ def test_run_to_run_bitwise():
         plan.solve(ud, f, rtol=1e-10)
         outs.append(host(ud))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dim,m", [(3, 31), (3, 127), (2, 255), (2, 1023)])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 1), (1, 2)])
+@pytest.mark.parametrize("post_forward", [False, True])
+def test_fused_coarse_kernels_bitwise(dim, m, nu, post_forward):
+    """The LDS-tile kernels of the small coarse levels give the same bits as
+    the general passes + restriction on those levels."""
+    from paper_1208_4247_amd import capi
+
+    f = dev(wl.rhs_uniform(dim, m, seed=65))
+    u0 = dev(wl.rhs_uniform(dim, m, seed=66) * 1e-3)
+    base = capi.GMG_POST_FORWARD if post_forward else 0
+    outs = []
+    for flags in (base, base | capi.GMG_NO_FUSED_COARSE):
+        plan = Plan(dim, levels_of(m), nu1=nu[0], nu2=nu[1], flags=flags)
+        ud = u0.clone()
+        plan.vcycle(ud, f)
+        outs.append(host(ud))
+    assert np.array_equal(outs[0], outs[1])
+    want = oracle.vcycle(host(u0), host(f), nu[0], nu[1]) if not post_forward else None
+    if want is not None:
+        assert maxrel(outs[0], want) <= 1e-12
