@@ -180,7 +180,7 @@ __device__ __forceinline__ int bl_offset(int dim, int L, int l) {
 }
 
 template <typename T, int DIM>
-__device__ void bottom_body(const BottomArgs<T> &a, const T *fin, T *uout, T *sm) {
+__device__ void bottom_body(const BottomArgs<T> &a, const GMG_GLOBAL T *fin, GMG_GLOBAL T *uout, T *sm) {
   const int L = a.L;
   const int total = bl_offset(DIM, L, L) + bl_make(DIM, L, 0).size;
   T *R = sm + bl_offset(DIM, L, L);  // residual / Jacobi scratch, size of level 0
@@ -231,9 +231,9 @@ __device__ void bottom_body(const BottomArgs<T> &a, const T *fin, T *uout, T *sm
 template <typename T>
 __global__ void __launch_bounds__(1024) k_bottom(BottomArgs<T> arg, const BottomArgs<T> *tbl) {
   const BottomArgs<T> a = tbl ? tbl[blockIdx.x] : arg;  // batch: one problem per workgroup
-  if (a.active && *a.active == 0) return;
-  const T *fin = a.f;
-  T *uout = a.u;
+  if (a.active && *gbl(a.active) == 0) return;
+  const GMG_GLOBAL T *fin = gbl(a.f);
+  GMG_GLOBAL T *uout = gbl(a.u);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
   if (a.dim == 3)

@@ -7,6 +7,20 @@
 
 namespace gmg {
 
+// Global-memory views of device pointers.  Accesses through them compile to
+// global_* instructions; accesses through generic pointers compile to flat_*
+// ones, which also count on the LDS wait counter, so every LDS wait would
+// also wait for the HBM loads in flight.
+#define GMG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GMG_GLOBAL T *gbl(T *p) {
+  return (GMG_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const GMG_GLOBAL T *gbl(const T *p) {
+  return (const GMG_GLOBAL T *)p;
+}
+
 // Flags of a fused smoothing pass.
 enum PassFlags : int {
   F_ZERO_IN = 1,     // start value is zero: u_in is not read

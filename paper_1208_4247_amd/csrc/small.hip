@@ -119,7 +119,7 @@ __device__ __forceinline__ void box_coord(int i, int &lx, int &ly, int &lz) {
 template <typename T, int DIM, int CT, int NSW, int NT>
 __global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const SmallArgs<T> *tbl) {
   const SmallArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
-  if (a.active && *a.active == 0) return;
+  if (a.active && *gbl(a.active) == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int S = 2 * NSW;
   constexpr int H = S + 1;  // local index of the first core point
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const Small
       const int i = threadIdx.x + NT * k;
       int lx, ly, lz;
       box_coord<DIM, E>(i, lx, ly, lz);
-      fv[k] = (i < N && in_dom<DIM>(b, lx, ly, lz, m)) ? a.f[gidx<DIM>(b, lx, ly, lz, m)] : T(0);
+      fv[k] = (i < N && in_dom<DIM>(b, lx, ly, lz, m)) ? gbl(a.f)[gidx<DIM>(b, lx, ly, lz, m)] : T(0);
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const Small
   lds_sweeps<T, DIM>(b, u, f, S, 0, m, h2);
   // pre-smoothed values on the core (fine points 2*A0 .. 2*A0 + 2CT - 1)
   box_for<DIM>(E, H, H + 2 * CT, [&](int i, int lx, int ly, int lz) {
-    if (in_dom<DIM>(b, lx, ly, lz, m)) a.w[gidx<DIM>(b, lx, ly, lz, m)] = u[i];
+    if (in_dom<DIM>(b, lx, ly, lz, m)) gbl(a.w)[gidx<DIM>(b, lx, ly, lz, m)] = u[i];
   });
   // residual on the core and one point past it (f is overwritten in place:
   // each point reads only its own f and the neighbours' u)
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const Small
     const T v = DIM == 3 ? T(0.25) * pl(i - E * E) + T(0.5) * pl(i) + T(0.25) * pl(i + E * E)
                          : pl(i);
     const size_t o = DIM == 3 ? ((size_t)cz * mc + cy) * mc + cx : (size_t)cy * mc + cx;
-    a.fc[o] = v;
+    gbl(a.fc)[o] = v;
   }
 }
 
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const Small
 template <typename T, int DIM, int CT, int NSW, int NT>
 __global__ void __launch_bounds__(NT) k_small_up(SmallArgs<T> arg, const SmallArgs<T> *tbl) {
   const SmallArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
-  if (a.active && *a.active == 0) return;
+  if (a.active && *gbl(a.active) == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int S = 2 * NSW;
   constexpr int H = S;
@@ -218,16 +218,16 @@ __global__ void __launch_bounds__(NT) k_small_up(SmallArgs<T> arg, const SmallAr
       T v = T(0), fl = T(0);
       if (i < N && in_dom<DIM>(b, lx, ly, lz, m)) {
         const size_t g = gidx<DIM>(b, lx, ly, lz, m);
-        fl = a.f[g];
+        fl = gbl(a.f)[g];
         // u = w + P e in the canonical order (x, then y, then z averaging)
         const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = DIM == 3 ? b.o[2] + lz : 0;
         auto cv = [&](int cx, int cy, int cz) -> T {
           if (cx < 0 || cx >= mc || cy < 0 || cy >= mc) return T(0);
           if (DIM == 3) {
             if (cz < 0 || cz >= mc) return T(0);
-            return a.ec[((size_t)cz * mc + cy) * mc + cx];
+            return gbl(a.ec)[((size_t)cz * mc + cy) * mc + cx];
           }
-          return a.ec[(size_t)cy * mc + cx];
+          return gbl(a.ec)[(size_t)cy * mc + cx];
         };
         auto xs = [&](int cy, int cz) {
           return (gx & 1) ? cv((gx - 1) >> 1, cy, cz)
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(NT) k_small_up(SmallArgs<T> arg, const SmallAr
           pe = (gz & 1) ? ys((gz - 1) >> 1) : T(0.5) * (ys((gz >> 1) - 1) + ys(gz >> 1));
         else
           pe = ys(0);
-        v = a.w[g] + pe;
+        v = gbl(a.w)[g] + pe;
       }
       uv[k] = v;
       fv[k] = fl;
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(NT) k_small_up(SmallArgs<T> arg, const SmallAr
   __syncthreads();
   lds_sweeps<T, DIM>(b, u, f, S, a.black_first ? 1 : 0, m, h2);
   box_for<DIM>(E, H, H + 2 * CT, [&](int i, int lx, int ly, int lz) {
-    if (in_dom<DIM>(b, lx, ly, lz, m)) a.u[gidx<DIM>(b, lx, ly, lz, m)] = u[i];
+    if (in_dom<DIM>(b, lx, ly, lz, m)) gbl(a.u)[gidx<DIM>(b, lx, ly, lz, m)] = u[i];
   });
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 // then z).  Per axis, fine storage index v odd (fine node even) lies on
 // coarse storage (v-1)/2; v even lies halfway between v/2-1 and v/2.
 template <typename T, int DIM>
-__device__ __forceinline__ T interp(const T *__restrict__ ec, int mc, int x, int y, int z) {
+__device__ __forceinline__ T interp(const GMG_GLOBAL T *__restrict__ ec, int mc, int x, int y, int z) {
   auto cv = [&](int a, int b, int c) -> T {
     if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) return T(0);
     return ec[DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a];
@@ -63,7 +63,7 @@ __device__ __forceinline__ T interp(const T *__restrict__ ec, int mc, int x, int
 }
 
 template <int NT>
-__device__ __forceinline__ void block_sum_store(double acc, double *out) {
+__device__ __forceinline__ void block_sum_store(double acc, GMG_GLOBAL double *out) {
   __shared__ double red[NT / 64];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
@@ -90,55 +90,6 @@ struct SlotGeo {
   int y;         // row (3D) or 0
   int xb;
 };
-
-// xy-interpolated coarse correction at one coarse plane for both elements of
-// a slot: e0 (x even: fine node odd, halfway between coarse xb/2-1 and xb/2)
-// and e1 (x odd: fine node even, on coarse column xb/2).  2D: the coarse
-// "plane" is a coarse row.
-template <typename T, int DIM>
-__device__ __forceinline__ void coarse_xy(const T *__restrict__ ec, int mc, int cz, int y, int xb,
-                                          T &v0, T &v1) {
-  v0 = T(0);
-  v1 = T(0);
-  if (cz < 0 || cz >= mc) return;
-  const int cl = (xb >> 1) - 1, cr = xb >> 1;
-  const bool okl = cl >= 0 && cl < mc, okr = cr >= 0 && cr < mc;
-  if (DIM == 2) {
-    const T *row = ec + (size_t)cz * mc;
-    const T el = okl ? row[cl] : T(0), er = okr ? row[cr] : T(0);
-    v0 = T(0.5) * (el + er);
-    v1 = er;
-    return;
-  }
-  // rows: y odd -> coarse row (y-1)/2; y even -> average of y/2-1 and y/2
-  int r0, r1;
-  if (y & 1) {
-    r0 = (y - 1) >> 1;
-    r1 = -1;
-  } else {
-    r0 = (y >> 1) - 1;
-    r1 = y >> 1;
-  }
-  // canonical order shared by every prolongation in the library: average
-  // along x first, then y, then z
-  const T *pl = ec + (size_t)cz * mc * mc;
-  auto row = [&](int r, T &x0, T &x1) {
-    const T el = okl ? pl[(size_t)r * mc + cl] : T(0);
-    const T er = okr ? pl[(size_t)r * mc + cr] : T(0);
-    x0 = T(0.5) * (el + er);
-    x1 = er;
-  };
-  T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
-  if (r0 >= 0 && r0 < mc) row(r0, a0, a1);
-  if (r1 < 0) {  // y odd: on a coarse row
-    v0 = a0;
-    v1 = a1;
-    return;
-  }
-  if (r1 < mc) row(r1, b0, b1);
-  v0 = T(0.5) * (a0 + b0);
-  v1 = T(0.5) * (a1 + b1);
-}
 
 template <int DIM, int S_HALO, int EXP, int EY, int NT, int NS>
 __device__ __forceinline__ void slot_setup(SlotGeo (&g)[NS], int X0, int Y0, int m) {
@@ -181,7 +132,7 @@ template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<T> *tbl) {
   // batch mode: one table entry (problem) per blockIdx.y
   const PassArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
-  if (a.active && *a.active == 0) return;
+  if (a.active && *gbl(a.active) == 0) return;
   constexpr int NS = (EXP * EY + NT - 1) / NT;  // slots per thread
   constexpr int HP = S / 2;                     // halo in pairs
   constexpr int TXP = EXP - 2 * HP;             // output pairs per row
@@ -192,8 +143,16 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr int C1 = (FL & F_BLACK_FIRST) ? 1 : 0;
   constexpr int C0 = 1 - C1;  // colour the first stage reads
   constexpr int PL = EXP * EY;
+  // PRO: the coarse correction's footprint under the tile, one coarse plane
+  // at a time, staged in LDS (two planes in a ring).  Column j <-> coarse x
+  // index CX0 + j, row k <-> coarse y index CY0 + k; zero outside the grid.
+  constexpr int NCX = EXP + 1;
+  constexpr int NCY = DIM == 3 ? EY / 2 + 1 : 1;
+  constexpr int CPL = NCX * NCY;
+  constexpr int NCP = PRO ? (CPL + NT - 1) / NT : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *lds = reinterpret_cast<T *>(smem_raw);  // [S (+1)][PL]
+  T *lds = reinterpret_cast<T *>(smem_raw);  // [S (+1)][PL], then PRO: [2][CPL]
+  T *cring = lds + (S + (NORM ? 1 : 0)) * PL;
 
   const int m = a.m;
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -208,8 +167,9 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   const int planeS = DIM == 3 ? m * m : m;
   const T h2 = T(a.h2);
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
-  const T *__restrict__ fg = a.f;
-  const T *__restrict__ ug = a.u_in;
+  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
+  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u_in);
+  GMG_GLOBAL T *__restrict__ uo = gbl(a.u_out);
 
   SlotGeo g[NS];
   slot_setup<DIM, S, EXP, EY, NT, NS>(g, X0, Y0, m);
@@ -217,8 +177,6 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   T W[S][NS][3];  // stage windows: [0] newest plane, [1] previous, [2] two back
   T WB[NORM ? NS : 1][3];
   T pu0[NS], pu1[NS];  // start value of the plane being entered (both elements)
-  T cl0[PRO ? NS : 1], cl1[PRO ? NS : 1], ch0[PRO ? NS : 1], ch1[PRO ? NS : 1];
-  T cn0[PRO ? NS : 1], cn1[PRO ? NS : 1];
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -241,19 +199,71 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     }
   };
   load_u(t0, pu0, pu1);
+  // PRO geometry: tile origin (X0 - S, Y0 - S) is even in both axes, so pair
+  // p reads coarse columns p (left) and p + 1 (right); an odd row r of the
+  // extended tile lies on coarse row (r + 1) / 2, an even one halfway between
+  // rows r / 2 and r / 2 + 1.
+  const int CX0 = ((X0 - S) >> 1) - 1;
+  const int CY0 = DIM == 3 ? ((Y0 - S) >> 1) - 1 : 0;
+  int cb[PRO ? NS : 1];
+  bool c2[PRO ? NS : 1];
   if (PRO) {
-    // state at the start of step t0: even t0 needs coarse planes t0/2-1 (lo)
-    // and t0/2 (hi); odd t0 needs plane (t0-1)/2 (hi)
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      cl0[i] = cl1[i] = cn0[i] = cn1[i] = T(0);
-      if (t0 & 1) {
-        coarse_xy<T, DIM>(a.e_c, a.mc, (t0 - 1) >> 1, g[i].y, g[i].xb, ch0[i], ch1[i]);
-      } else {
-        coarse_xy<T, DIM>(a.e_c, a.mc, (t0 >> 1) - 1, g[i].y, g[i].xb, cl0[i], cl1[i]);
-        coarse_xy<T, DIM>(a.e_c, a.mc, t0 >> 1, g[i].y, g[i].xb, ch0[i], ch1[i]);
-      }
+      const int p = (g[i].xb - (X0 - S)) >> 1;
+      const int r = DIM == 3 ? min(g[i].y - (Y0 - S), EY - 1) : 0;
+      c2[i] = DIM == 3 && !(r & 1);
+      cb[i] = (DIM == 3 ? ((r & 1) ? (r + 1) >> 1 : r >> 1) * NCX : 0) + p;
     }
+  }
+  const GMG_GLOBAL T *__restrict__ ecg = gbl(a.e_c);
+  const int mc = a.mc;
+  auto load_c = [&](int cz, T *v) {
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) {
+      const int j = threadIdx.x + NT * k;
+      const int cx = CX0 + j % NCX, cy = CY0 + j / NCX;
+      v[k] = (j < CPL && cz >= 0 && cz < mc && cx >= 0 && cx < mc && (DIM == 2 || cy < mc) &&
+              cy >= 0)
+                 ? ecg[(DIM == 3 ? ((size_t)cz * mc + cy) * mc : (size_t)cz * mc) + cx]
+                 : T(0);
+    }
+  };
+  auto store_c = [&](int cz, const T *v) {
+    T *dst = cring + (cz & 1) * CPL;
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) {
+      const int j = threadIdx.x + NT * k;
+      if (j < CPL) dst[j] = v[k];
+    }
+  };
+  // xy-interpolated correction of both elements of slot i from one staged
+  // coarse plane, in the library's canonical order (x, then y)
+  auto cxy = [&](int cz, int i, T &v0, T &v1) {
+    const T *P = cring + (cz & 1) * CPL + cb[i];
+    const T el = P[0], er = P[1];
+    v0 = T(0.5) * (el + er);
+    v1 = er;
+    if (c2[i]) {
+      const T fl = P[NCX], fr = P[NCX + 1];
+      v0 = T(0.5) * (v0 + T(0.5) * (fl + fr));
+      v1 = T(0.5) * (v1 + fr);
+    }
+  };
+  if (PRO) {
+    // the coarse planes step t0 reads: (t0 - 1) / 2 for odd t0, t0 / 2 - 1
+    // and t0 / 2 for even t0
+    T cv[NCP];
+    if (t0 & 1) {
+      load_c((t0 - 1) >> 1, cv);
+      store_c((t0 - 1) >> 1, cv);
+    } else {
+      load_c((t0 >> 1) - 1, cv);
+      store_c((t0 >> 1) - 1, cv);
+      load_c(t0 >> 1, cv);
+      store_c(t0 >> 1, cv);
+    }
+    __syncthreads();
   }
 
   for (int t = t0; t < t1; ++t) {
@@ -285,13 +295,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
                     : T(0);
       }
     }
-    if (PRO) {
-      if (t & 1) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i)
-          coarse_xy<T, DIM>(a.e_c, a.mc, (t + 1) >> 1, g[i].y, g[i].xb, cn0[i], cn1[i]);
-      }
-    }
+    T cnext[NCP];  // PRO, odd t: coarse plane (t + 1) / 2, staged at the end of the step
+    if (PRO && (t & 1)) load_c((t + 1) >> 1, cnext);
     // ---- stage 0: start value on plane t (colour C0 into the window)
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
@@ -299,12 +304,14 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
       T v0 = pu0[i], v1 = pu1[i];
       if (PRO) {
         T c0, c1;
-        if (t & 1) {  // fine node t+1 even: on a coarse plane
-          c0 = ch0[i];
-          c1 = ch1[i];
+        if (t & 1) {  // fine node t+1 even: on coarse plane (t-1)/2
+          cxy((t - 1) >> 1, i, c0, c1);
         } else {      // between coarse planes t/2-1 and t/2
-          c0 = T(0.5) * (cl0[i] + ch0[i]);
-          c1 = T(0.5) * (cl1[i] + ch1[i]);
+          T l0, l1, h0, h1;
+          cxy((t >> 1) - 1, i, l0, l1);
+          cxy(t >> 1, i, h0, h1);
+          c0 = T(0.5) * (l0 + h0);
+          c1 = T(0.5) * (l1 + h1);
         }
         if (t >= 0 && t < m) {
           if (g[i].ok & 1) v0 += c0;
@@ -396,8 +403,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         const int es = (CS + g[i].par + zo) & 1;
         const T o_new = newS[i], o_old = W[S - 1][i][1];
         const int o = zo * planeS + g[i].off;
-        a.u_out[o] = es ? o_old : o_new;
-        if (g[i].ok & 2) a.u_out[o + 1] = es ? o_new : o_old;
+        uo[o] = es ? o_old : o_new;
+        if (g[i].ok & 2) uo[o + 1] = es ? o_new : o_old;
       }
     }
     __syncthreads();
@@ -408,25 +415,15 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
       for (int s = 0; s < S; ++s) lds[s * PL + g[i].q] = W[s][i][0];
       if (NORM) lds[S * PL + g[i].q] = WB[i][0];
     }
+    if (PRO && (t & 1)) store_c((t + 1) >> 1, cnext);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       pu0[i] = nu0[i];
       pu1[i] = nu1[i];
     }
-    if (PRO) {
-      if (t & 1) {  // next step is even: shift the coarse planes
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          cl0[i] = ch0[i];
-          cl1[i] = ch1[i];
-          ch0[i] = cn0[i];
-          ch1[i] = cn1[i];
-        }
-      }
-    }
   }
-  if (NORM) block_sum_store<NT>(acc, a.partials);
+  if (NORM) block_sum_store<NT>(acc, gbl(a.partials));
 }
 
 // ------------------------------------------------------------------------
@@ -437,7 +434,7 @@ template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<T> *tbl) {
   // batch mode: one table entry (problem) per blockIdx.y
   const PassArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
-  if (a.active && *a.active == 0) return;
+  if (a.active && *gbl(a.active) == 0) return;
   constexpr int NS = (EXP * EY + NT - 1) / NT;
   constexpr int HP = (S + 1) / 2;  // halo in pairs (>= S points)
   constexpr int H = 2 * HP;
@@ -466,6 +463,10 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const T om = T(a.omega);
   const T om1 = T(1.0 - a.omega);
+  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
+  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u_in);
+  const GMG_GLOBAL T *__restrict__ ecg = gbl(a.e_c);
+  GMG_GLOBAL T *__restrict__ uo = gbl(a.u_out);
 
   int q[NS], xb[NS], yy[NS], lq[NS], rq[NS], uq[NS], dq[NS];
   bool live[NS], yin[NS], outp[NS];
@@ -506,10 +507,10 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
         for (int e = 0; e < 2; ++e) {
           const int x = xb[i] + e;
           if (x < 0 || x >= m) continue;
-          if (!ZERO) v[e] = a.u_in[base + x];
+          if (!ZERO) v[e] = ug[base + x];
           if (PRO)
-            v[e] += DIM == 3 ? interp<T, 3>(a.e_c, a.mc, x, yy[i], t)
-                             : interp<T, 2>(a.e_c, a.mc, x, t, 0);
+            v[e] += DIM == 3 ? interp<T, 3>(ecg, a.mc, x, yy[i], t)
+                             : interp<T, 2>(ecg, a.mc, x, t, 0);
         }
       }
 #pragma unroll
@@ -542,7 +543,7 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
             }
             nb += W[0][i][e][2];
             nb += W[0][i][e][0];
-            const double r = double(a.f[base + x]) -
+            const double r = double(fg[base + x]) -
                              (double(T(2 * DIM) * W[0][i][e][1]) - double(nb)) * a.inv_h2;
             acc += r * r;
           }
@@ -576,7 +577,7 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
           const int x = xb[i] + e;
           T v = T(0);
           if (live[i] && zin && yin[i] && x >= 0 && x < m)
-            v = om1 * W[s - 1][i][e][1] + om * (fma(h2, a.f[base + x], nb) * inv2d);
+            v = om1 * W[s - 1][i][e][1] + om * (fma(h2, fg[base + x], nb) * inv2d);
           nv[e] = v;
         }
 #pragma unroll
@@ -598,8 +599,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
         if (!outp[i]) continue;
         const size_t base = (size_t)zo * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
         const int x0 = xb[i];
-        a.u_out[base + x0] = newS[i][0];
-        if (x0 + 1 < m) a.u_out[base + x0 + 1] = newS[i][1];
+        uo[base + x0] = newS[i][0];
+        if (x0 + 1 < m) uo[base + x0 + 1] = newS[i][1];
       }
     }
     __syncthreads();
@@ -614,7 +615,7 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
     }
     __syncthreads();
   }
-  if (NORM) block_sum_store<NT>(acc, a.partials);
+  if (NORM) block_sum_store<NT>(acc, gbl(a.partials));
 }
 
 // ------------------------------------------------------------------------
@@ -691,7 +692,8 @@ PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz) {
 namespace {
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
-  const size_t lds = sizeof(T) * EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0));
+  const size_t cpl = (FL & F_PROLONG) ? 2 * (size_t)(EXP + 1) * (DIM == 3 ? EY / 2 + 1 : 1) : 0;
+  const size_t lds = sizeof(T) * (EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0)) + cpl);
   auto k = k_rb_pass<T, DIM, S, EXP, EY, NT, FL>;
   static bool attr = false;
   if (!attr) {

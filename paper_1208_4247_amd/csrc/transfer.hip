@@ -18,7 +18,7 @@ __device__ __forceinline__ int xcd_remap_t(int bid, int n) {
 }
 
 template <typename T>
-__device__ __forceinline__ T ld0(const T *__restrict__ p, int m, int x, int y, int z, int dim) {
+__device__ __forceinline__ T ld0(const GMG_GLOBAL T *__restrict__ p, int m, int x, int y, int z, int dim) {
   if (x < 0 || y < 0 || x >= m || y >= m) return T(0);
   if (dim == 3) {
     if (z < 0 || z >= m) return T(0);
@@ -99,8 +99,9 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
   const T inv_h2 = T(a.inv_h2);
   const T two_d = T(2 * DIM);
   const int planeS = DIM == 3 ? m * m : m;
-  const T *__restrict__ ug = a.u;
-  const T *__restrict__ fg = a.f;
+  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u);
+  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
+  GMG_GLOBAL T *__restrict__ fcg = gbl(a.fc);
 
   // u-tile element q -> plane offset (or -1 outside the domain)
   int uo[NU];
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
         if (c >= C0) {
           acc += T(0.25) * sxy;
           const size_t o = DIM == 3 ? ((size_t)c * mc + cy) * mc + cx : (size_t)c * mc + cx;
-          a.fc[o] = acc;
+          fcg[o] = acc;
         }
         acc = T(0.25) * sxy;
       }
@@ -229,6 +230,8 @@ __global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a) {
   const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
   double acc = 0.0;
   const T inv_h2 = T(a.inv_h2);
+  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u);
+  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
   for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
     const int x = (int)(p % m);
     const size_t rest = p / m;
@@ -237,20 +240,20 @@ __global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a) {
     T nb;
     T c;
     if (DIM == 3) {
-      c = a.u[p];
-      nb = ld0(a.u, m, x - 1, y, z, 3) + ld0(a.u, m, x + 1, y, z, 3);
-      nb += ld0(a.u, m, x, y - 1, z, 3);
-      nb += ld0(a.u, m, x, y + 1, z, 3);
-      nb += ld0(a.u, m, x, y, z - 1, 3);
-      nb += ld0(a.u, m, x, y, z + 1, 3);
+      c = ug[p];
+      nb = ld0(ug, m, x - 1, y, z, 3) + ld0(ug, m, x + 1, y, z, 3);
+      nb += ld0(ug, m, x, y - 1, z, 3);
+      nb += ld0(ug, m, x, y + 1, z, 3);
+      nb += ld0(ug, m, x, y, z - 1, 3);
+      nb += ld0(ug, m, x, y, z + 1, 3);
     } else {
-      c = a.u[p];
-      nb = ld0(a.u, m, x - 1, y, 0, 2) + ld0(a.u, m, x + 1, y, 0, 2);
-      nb += ld0(a.u, m, x, y - 1, 0, 2);
-      nb += ld0(a.u, m, x, y + 1, 0, 2);
+      c = ug[p];
+      nb = ld0(ug, m, x - 1, y, 0, 2) + ld0(ug, m, x + 1, y, 0, 2);
+      nb += ld0(ug, m, x, y - 1, 0, 2);
+      nb += ld0(ug, m, x, y + 1, 0, 2);
     }
-    const T r = a.f[p] - (T(2 * DIM) * c - nb) * inv_h2;
-    if (a.r) a.r[p] = r;
+    const T r = fg[p] - (T(2 * DIM) * c - nb) * inv_h2;
+    if (a.r) gbl(a.r)[p] = r;
     acc += double(r) * double(r);
   }
   if (a.partials) {
@@ -262,7 +265,7 @@ __global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a) {
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int w = 0; w < NT / 64; ++w) s += red[w];
-      a.partials[blockIdx.x] = s;
+      gbl(a.partials)[blockIdx.x] = s;
     }
   }
 }
@@ -286,6 +289,9 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
   const int m = a.m;
   const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
   double acc = 0.0;
+  const GMG_GLOBAL double *__restrict__ xg = gbl(a.x);
+  const GMG_GLOBAL float *__restrict__ eg = gbl(a.e);
+  const GMG_GLOBAL double *__restrict__ fg = gbl(a.f);
   for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
     const int x = (int)(p % m);
     const size_t rest = p / m;
@@ -295,8 +301,8 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
       if (i < 0 || j < 0 || i >= m || j >= m) return 0.0;
       if (DIM == 3 && (k < 0 || k >= m)) return 0.0;
       const size_t o = DIM == 3 ? ((size_t)k * m + j) * m + i : (size_t)j * m + i;
-      double v = a.x[o];
-      if (a.e) v += double(a.e[o]);
+      double v = xg[o];
+      if (eg) v += double(eg[o]);
       return v;
     };
     const double c = val(x, y, z);
@@ -307,9 +313,9 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
       nb += val(x, y, z - 1);
       nb += val(x, y, z + 1);
     }
-    const double r = a.f[p] - (double(2 * DIM) * c - nb) * a.inv_h2;
-    if (a.e) a.x_out[p] = c;
-    a.r32[p] = float(r);
+    const double r = fg[p] - (double(2 * DIM) * c - nb) * a.inv_h2;
+    if (eg) gbl(a.x_out)[p] = c;
+    gbl(a.r32)[p] = float(r);
     acc += r * r;
   }
   __shared__ double red[NT / 64];
@@ -320,7 +326,7 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < NT / 64; ++w) s += red[w];
-    a.partials[blockIdx.x] = s;
+    gbl(a.partials)[blockIdx.x] = s;
   }
 }
 

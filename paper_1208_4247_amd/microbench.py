@@ -79,8 +79,24 @@ def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=Non
     return rows
 
 
+def copy_calibration(mib, reps=20):
+    """A plain device copy of known size (torch's copy kernel): the yardstick
+    that converts the HBM byte counters of a profiler into bytes, and the
+    practical streaming ceiling of the device."""
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    us = _time(lambda: dst.copy_(src), reps)
+    row = dict(kernel="copy", bytes_read=n * 8, bytes_written=n * 8, us=us,
+               gbs=2 * n * 8 / (us * 1e-6) / 1e9)
+    print(json.dumps(row), flush=True)
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only time a plain copy of this many MiB")
     ap.add_argument("--dim", type=int, default=3)
     ap.add_argument("--m", type=int, nargs="+", default=[255])
     ap.add_argument("--reps", type=int, default=20)
@@ -89,6 +105,9 @@ def main():
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
+    if a.copy_mib:
+        copy_calibration(a.copy_mib, a.reps)
+        return
     for m in a.m:
         print("# dim %d m %d" % (a.dim, m), flush=True)
         run(a.dim, m, a.reps, torch.float32 if a.fp32 else torch.float64, a.smoother, a.tz, a.out)
