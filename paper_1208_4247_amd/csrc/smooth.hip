@@ -124,16 +124,85 @@ __device__ __forceinline__ void slot_setup(SlotGeo (&g)[NS], int X0, int Y0, int
 //
 // Step t: stage 0 holds the start value of plane t (prefetched during step
 // t-1), stage s computes plane t-s of colour c_s from stage s-1's planes
-// t-s-1 .. t-s+1 (registers) and its in-plane neighbours (LDS, written at
+// t-s-1 .. t-s+1 (registers) and its in-plane neighbours (LDS, published at
 // step t-1).  Plane t-S leaves the pipeline: colour c_S from stage S, the
 // other colour from stage S-1.
+//
+// Memory access: every HBM access goes through a buffer resource of one
+// plane (zero records for a plane outside the grid) and a per-element byte
+// offset that is out of range for elements outside the grid or (stores)
+// outside the output tile, so loads of the zero boundary return 0 and
+// stores outside the tile are dropped, without branches.  Steps come in
+// pairs (t even, t odd), which makes every colour and parity decision a
+// compile-time choice between the two elements of a pair, and the LDS planes
+// are double-buffered by step parity, so one barrier per step suffices.
 // ------------------------------------------------------------------------
+constexpr int kOOB = 0x7ffffff0;  // byte offset beyond any plane resource
+
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, int z, int m,
+                                                             int plane) {
+  // raw buffer over plane z (no records when z is outside 0..m-1)
+  const bool in = z >= 0 && z < m;
+  const T *p = base + (in ? (size_t)z * plane : 0);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0,
+                                           in ? plane * (int)sizeof(T) : 0, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+typedef unsigned int gmg_u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct PairOf {
+  T lo, hi;
+};
+
+// two adjacent elements in one load (16 bytes for FP64, 8 for FP32)
+template <typename T>
+__device__ __forceinline__ PairOf<T> bload2(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(PairOf<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(PairOf<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gmg_u32x2, v), r, off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
+// Argument block of this workgroup: the kernel argument, or (batch mode) the
+// table entry of problem blockIdx.y, read through the scalar cache.
+template <typename A>
+__device__ __forceinline__ A entry_of(const A &arg, const A *tbl) {
+  if (!tbl) return arg;
+  A r;
+  __builtin_memcpy(&r, (const __attribute__((address_space(4))) A *)tbl + blockIdx.y, sizeof(A));
+  return r;
+}
+
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<T> *tbl) {
-  // batch mode: one table entry (problem) per blockIdx.y
-  const PassArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
+  const PassArgs<T> a = entry_of(arg, tbl);
   if (a.active && *gbl(a.active) == 0) return;
-  constexpr int NS = (EXP * EY + NT - 1) / NT;  // slots per thread
+  constexpr int PL = EXP * EY;
+  constexpr int NS = (PL + NT - 1) / NT;        // slots per thread
+  constexpr bool TAIL = NS * NT > PL;           // the last slot index has dead lanes
   constexpr int HP = S / 2;                     // halo in pairs
   constexpr int TXP = EXP - 2 * HP;             // output pairs per row
   constexpr int TY = DIM == 3 ? EY - 2 * S : 1;
@@ -142,7 +211,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr bool NORM = (FL & F_NORM_IN) != 0;
   constexpr int C1 = (FL & F_BLACK_FIRST) ? 1 : 0;
   constexpr int C0 = 1 - C1;  // colour the first stage reads
-  constexpr int PL = EXP * EY;
+  constexpr int NB = S + (NORM ? 1 : 0);  // LDS planes per buffer
   // PRO: the coarse correction's footprint under the tile, one coarse plane
   // at a time, staged in LDS (two planes in a ring).  Column j <-> coarse x
   // index CX0 + j, row k <-> coarse y index CY0 + k; zero outside the grid.
@@ -151,8 +220,9 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr int CPL = NCX * NCY;
   constexpr int NCP = PRO ? (CPL + NT - 1) / NT : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *lds = reinterpret_cast<T *>(smem_raw);  // [S (+1)][PL], then PRO: [2][CPL]
-  T *cring = lds + (S + (NORM ? 1 : 0)) * PL;
+  // [2 (step parity)][NB][PL], then PRO: [2][CPL]
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  T *cring = lds + 2 * NB * PL;
 
   const int m = a.m;
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -167,16 +237,68 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   const int planeS = DIM == 3 ? m * m : m;
   const T h2 = T(a.h2);
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
-  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
-  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u_in);
-  GMG_GLOBAL T *__restrict__ uo = gbl(a.u_out);
 
-  SlotGeo g[NS];
-  slot_setup<DIM, S, EXP, EY, NT, NS>(g, X0, Y0, m);
+  // ---- per-slot geometry.  "P" is the element whose index equals the row
+  // parity par = (y + DIM) & 1, "Q" the other one; an element e of plane z
+  // has colour (e + par + z) & 1.
+  // Loads take both elements of a pair at once from byte offset o2 (kOOB
+  // when neither is inside the grid); the pair at the end of a row (xb =
+  // m - 1, m odd) loads elements (xb - 1, xb) instead, so element 0 is then
+  // the high half.  hP / hQ: element P / Q is the high half of the load.
+  int o2[NS];
+  bool hP[NS], hQ[NS];
+  int sP[NS], sQ[NS];    // store offsets, kOOB outside the grid or the output tile
+  bool nP[NS], nQ[NS];   // NORM: element inside the grid and the output tile
+  bool kP[NS], kQ[NS];   // element inside the grid
+  int lq[NS], lP[NS], lQ[NS], lu[NS], ld[NS];  // LDS: self, x-side of P / Q, y-1, y+1
+  bool live[NS];
+  int cb[PRO ? NS : 1];
+  bool c2[PRO ? NS : 1];
+  bool pone[PRO ? NS : 1];  // element P is element 1 of the pair
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int q = threadIdx.x + NT * i;
+    live[i] = q < PL;
+    const int qc = live[i] ? q : PL - 1;
+    const int p = qc % EXP, r = qc / EXP;
+    const int xb = X0 - S + 2 * p;
+    const int y = DIM == 3 ? Y0 - S + r : 0;
+    const bool yin = DIM == 2 || (y >= 0 && y < m);
+    const int par = (y + DIM) & 1;
+    const int off = (DIM == 3 ? y * m : 0) + xb;
+    const bool in0 = live[i] && yin && xb >= 0 && xb < m;
+    const bool in1 = live[i] && yin && xb + 1 >= 0 && xb + 1 < m;
+    const bool outp = live[i] && yin && p >= HP && p < HP + TXP &&
+                      (DIM == 2 || (r >= S && r < S + TY)) && xb < m;
+    const int o0 = in0 ? off * (int)sizeof(T) : kOOB;
+    const int o1 = in1 ? (off + 1) * (int)sizeof(T) : kOOB;
+    const bool half = in0 && !in1;
+    o2[i] = in0 ? (off - (half ? 1 : 0)) * (int)sizeof(T) : kOOB;
+    hP[i] = par ? true : half;
+    hQ[i] = par ? half : true;
+    kP[i] = par ? in1 : in0;
+    kQ[i] = par ? in0 : in1;
+    sP[i] = outp ? (par ? o1 : o0) : kOOB;
+    sQ[i] = outp ? (par ? o0 : o1) : kOOB;
+    nP[i] = outp && kP[i];
+    nQ[i] = outp && kQ[i];
+    lq[i] = qc;
+    const int left = max(qc - 1, 0), right = min(qc + 1, PL - 1);
+    lP[i] = par ? right : left;  // element 1 updates from the pair to its right
+    lQ[i] = par ? left : right;
+    lu[i] = max(qc - EXP, 0);
+    ld[i] = min(qc + EXP, PL - 1);
+    if (PRO) {
+      pone[i] = par != 0;
+      const int rr = DIM == 3 ? r : 0;
+      c2[i] = DIM == 3 && !(rr & 1);
+      cb[i] = (DIM == 3 ? ((rr & 1) ? (rr + 1) >> 1 : rr >> 1) * NCX : 0) + p;
+    }
+  }
 
   T W[S][NS][3];  // stage windows: [0] newest plane, [1] previous, [2] two back
   T WB[NORM ? NS : 1][3];
-  T pu0[NS], pu1[NS];  // start value of the plane being entered (both elements)
+  T pu0[NS], pu1[NS];  // start value of the plane being entered (elements P, Q)
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -185,60 +307,58 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   for (int i = 0; i < (NORM ? NS : 1); ++i) WB[i][0] = WB[i][1] = WB[i][2] = T(0);
   double acc = 0.0;
 
-  const int t0 = Z0 - S, t1 = Z1 + S;
+  // steps in pairs from an even start; the extra leading or trailing step
+  // only touches planes outside the exact region
+  const int t0 = (Z0 - S) & ~1, t1 = Z1 + S;
   auto load_u = [&](int t, T *v0, T *v1) {
+    if (ZERO) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) v0[i] = v1[i] = T(0);
+      return;
+    }
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.u_in, t, m, planeS);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      v0[i] = T(0);
-      v1[i] = T(0);
-      if (!ZERO && t >= 0 && t < m) {
-        const int o = t * planeS + g[i].off;
-        if (g[i].ok & 1) v0[i] = ug[o];
-        if (g[i].ok & 2) v1[i] = ug[o + 1];
-      }
+      const PairOf<T> v = bload2<T>(r, o2[i]);
+      v0[i] = kP[i] ? (hP[i] ? v.hi : v.lo) : T(0);
+      v1[i] = kQ[i] ? (hQ[i] ? v.hi : v.lo) : T(0);
     }
   };
   load_u(t0, pu0, pu1);
+
   // PRO geometry: tile origin (X0 - S, Y0 - S) is even in both axes, so pair
   // p reads coarse columns p (left) and p + 1 (right); an odd row r of the
   // extended tile lies on coarse row (r + 1) / 2, an even one halfway between
   // rows r / 2 and r / 2 + 1.
   const int CX0 = ((X0 - S) >> 1) - 1;
   const int CY0 = DIM == 3 ? ((Y0 - S) >> 1) - 1 : 0;
-  int cb[PRO ? NS : 1];
-  bool c2[PRO ? NS : 1];
-  if (PRO) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      const int p = (g[i].xb - (X0 - S)) >> 1;
-      const int r = DIM == 3 ? min(g[i].y - (Y0 - S), EY - 1) : 0;
-      c2[i] = DIM == 3 && !(r & 1);
-      cb[i] = (DIM == 3 ? ((r & 1) ? (r + 1) >> 1 : r >> 1) * NCX : 0) + p;
-    }
-  }
-  const GMG_GLOBAL T *__restrict__ ecg = gbl(a.e_c);
   const int mc = a.mc;
-  auto load_c = [&](int cz, T *v) {
+  const int cplane = DIM == 3 ? mc * mc : mc;
+  int coff[NCP];
+  if (PRO) {
 #pragma unroll
     for (int k = 0; k < NCP; ++k) {
       const int j = threadIdx.x + NT * k;
       const int cx = CX0 + j % NCX, cy = CY0 + j / NCX;
-      v[k] = (j < CPL && cz >= 0 && cz < mc && cx >= 0 && cx < mc && (DIM == 2 || cy < mc) &&
-              cy >= 0)
-                 ? ecg[(DIM == 3 ? ((size_t)cz * mc + cy) * mc : (size_t)cz * mc) + cx]
-                 : T(0);
+      const bool ok = j < CPL && cx >= 0 && cx < mc && (DIM == 2 || (cy >= 0 && cy < mc));
+      coff[k] = ok ? ((DIM == 3 ? cy * mc : 0) + cx) * (int)sizeof(T) : kOOB;
     }
+  }
+  auto load_c = [&](int cz, T *v) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.e_c, cz, mc, cplane);
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) v[k] = bload<T>(r, coff[k]);
   };
   auto store_c = [&](int cz, const T *v) {
     T *dst = cring + (cz & 1) * CPL;
 #pragma unroll
     for (int k = 0; k < NCP; ++k) {
       const int j = threadIdx.x + NT * k;
-      if (j < CPL) dst[j] = v[k];
+      if (NCP * NT == CPL || j < CPL) dst[j] = v[k];
     }
   };
-  // xy-interpolated correction of both elements of slot i from one staged
-  // coarse plane, in the library's canonical order (x, then y)
+  // xy-interpolated correction of the two elements of slot i (element 0 /
+  // element 1 of the pair) from one staged coarse plane, canonical order
   auto cxy = [&](int cz, int i, T &v0, T &v1) {
     const T *P = cring + (cz & 1) * CPL + cb[i];
     const T el = P[0], er = P[1];
@@ -251,115 +371,101 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     }
   };
   if (PRO) {
-    // the coarse planes step t0 reads: (t0 - 1) / 2 for odd t0, t0 / 2 - 1
-    // and t0 / 2 for even t0
+    // coarse planes t0 / 2 - 1 and t0 / 2 (t0 is even)
     T cv[NCP];
-    if (t0 & 1) {
-      load_c((t0 - 1) >> 1, cv);
-      store_c((t0 - 1) >> 1, cv);
-    } else {
-      load_c((t0 >> 1) - 1, cv);
-      store_c((t0 >> 1) - 1, cv);
-      load_c(t0 >> 1, cv);
-      store_c(t0 >> 1, cv);
-    }
+    load_c((t0 >> 1) - 1, cv);
+    store_c((t0 >> 1) - 1, cv);
+    load_c(t0 >> 1, cv);
+    store_c(t0 >> 1, cv);
     __syncthreads();
   }
 
-  for (int t = t0; t < t1; ++t) {
-    // ---- issue the loads of this step: next plane's start value, the
-    // right-hand side of every stage, the next coarse plane
-    T nu0[NS], nu1[NS];
-    load_u(t + 1, nu0, nu1);
-    T fs[S][NS];
-#pragma unroll
-    for (int s = 1; s <= S; ++s) {
-      const int zs = t - s;
-      const int cs = (C1 + s - 1) & 1;
-#pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        const int es = (cs + g[i].par + zs) & 1;
-        fs[s - 1][i] = (zs >= 0 && zs < m && ((g[i].ok >> es) & 1))
-                           ? fg[zs * planeS + g[i].off + es]
-                           : T(0);
-      }
-    }
-    T fb[NORM ? NS : 1];  // NORM: f of the colour-C0 element of plane t-1
-    if (NORM) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        const int zr = t - 1;
-        const int e0 = (C0 + g[i].par + zr) & 1;
-        fb[i] = (zr >= Z0 && zr < Z1 && g[i].outp && ((g[i].ok >> e0) & 1))
-                    ? fg[zr * planeS + g[i].off + e0]
-                    : T(0);
-      }
-    }
-    T cnext[NCP];  // PRO, odd t: coarse plane (t + 1) / 2, staged at the end of the step
-    if (PRO && (t & 1)) load_c((t + 1) >> 1, cnext);
-    // ---- stage 0: start value on plane t (colour C0 into the window)
+  // right-hand side window: fP[j] / fQ[j] hold elements P / Q of f on plane
+  // t - j (j = 0 .. S) during step t; stage s reads plane t - s.  Plane t + 1
+  // is loaded during step t (one step of latency hidden), with the next
+  // plane's start value and (odd steps) the next coarse plane.
+  auto load_f = [&](int z, T *vP, T *vQ) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.f, z, m, planeS);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      const int e0 = (C0 + g[i].par + t) & 1;
-      T v0 = pu0[i], v1 = pu1[i];
+      const PairOf<T> v = bload2<T>(r, o2[i]);
+      vP[i] = hP[i] ? v.hi : v.lo;
+      vQ[i] = hQ[i] ? v.hi : v.lo;
+    }
+  };
+  T fP[S + 1][NS], fQ[S + 1][NS];
+#pragma unroll
+  for (int j = 0; j <= S; ++j) load_f(t0 - j, fP[j], fQ[j]);
+  T cnext[NCP];  // PRO: coarse plane (t + 1) / 2 for the odd step t, loaded at step t - 1
+  if (PRO) load_c((t0 + 2) >> 1, cnext);
+
+  auto step = [&](int t, auto tp_tag) {
+    constexpr int TP = decltype(tp_tag)::value;  // t & 1
+    auto isP = [](int s) { return (((C1 + s - 1) + TP - s) & 1) == 0; };
+    constexpr bool B0P = ((C0 + TP - 1) & 1) == 0;  // colour-C0 element of plane t-1 is P
+    const int zr = t - 1;
+    const bool rin = NORM && zr >= Z0 && zr < Z1;
+    T nu0[NS], nu1[NS];
+    load_u(t + 1, nu0, nu1);
+    T fnP[NS], fnQ[NS];
+    load_f(t + 1, fnP, fnQ);
+    T cnn[NCP];
+    if (PRO && TP == 1) load_c((t + 3) >> 1, cnn);
+
+    // ---- stage 0: start value on plane t (colour C0 into the window)
+    constexpr bool S0P = ((C0 + TP) & 1) == 0;  // colour-C0 element of plane t is P
+    const bool tin = t >= 0 && t < m;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      T vP = pu0[i], vQ = pu1[i];
       if (PRO) {
         T c0, c1;
-        if (t & 1) {  // fine node t+1 even: on coarse plane (t-1)/2
+        if (TP == 1) {  // fine node t+1 even: on coarse plane (t-1)/2
           cxy((t - 1) >> 1, i, c0, c1);
-        } else {      // between coarse planes t/2-1 and t/2
+        } else {        // between coarse planes t/2-1 and t/2
           T l0, l1, h0, h1;
           cxy((t >> 1) - 1, i, l0, l1);
           cxy(t >> 1, i, h0, h1);
           c0 = T(0.5) * (l0 + h0);
           c1 = T(0.5) * (l1 + h1);
         }
-        if (t >= 0 && t < m) {
-          if (g[i].ok & 1) v0 += c0;
-          if (g[i].ok & 2) v1 += c1;
-        }
+        const T cP = pone[i] ? c1 : c0, cQ = pone[i] ? c0 : c1;
+        vP = (tin && kP[i]) ? vP + cP : vP;
+        vQ = (tin && kQ[i]) ? vQ + cQ : vQ;
       }
       W[0][i][2] = W[0][i][1];
       W[0][i][1] = W[0][i][0];
-      W[0][i][0] = e0 ? v1 : v0;
+      W[0][i][0] = S0P ? vP : vQ;
       if (NORM) {
         WB[i][2] = WB[i][1];
         WB[i][1] = WB[i][0];
-        WB[i][0] = e0 ? v0 : v1;
+        WB[i][0] = S0P ? vQ : vP;
       }
     }
+    const T *Lprev = lds + (1 - TP) * NB * PL;  // planes published at step t-1
     // ---- residual of the start value on plane t-1 (convergence test)
-    if (NORM) {
-      const int zr = t - 1;
-      if (zr >= Z0 && zr < Z1) {
-        const T *L0 = lds;           // colour C0 values of plane t-1
-        const T *LB = lds + S * PL;  // colour C1 values of plane t-1
+    if (NORM && rin) {
+      const T *L0 = Lprev;           // colour C0 values of plane t-1
+      const T *LB = Lprev + S * PL;  // colour C1 values of plane t-1
 #pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          if (!g[i].outp) continue;
-          const int e0 = (C0 + g[i].par + zr) & 1;
-          const int qc = g[i].q;
-          const int lq = max(qc - 1, 0), rq = min(qc + 1, PL - 1);
-          const int uq = max(qc - EXP, 0), dq = min(qc + EXP, PL - 1);
+      for (int i = 0; i < NS; ++i) {
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {  // 0: the colour-C0 element, 1: the other
-            const int e = c == 0 ? e0 : 1 - e0;
-            if (!((g[i].ok >> e) & 1)) continue;
-            const T self = c == 0 ? W[0][i][1] : WB[i][1];
-            const T own = c == 0 ? WB[i][1] : W[0][i][1];
-            const T *Ln = c == 0 ? LB : L0;
-            const T side = e ? Ln[rq] : Ln[lq];
-            T nb = own + side;
-            if (DIM == 3) {
-              nb += Ln[uq];
-              nb += Ln[dq];
-            }
-            nb += c == 0 ? WB[i][2] : W[0][i][2];
-            nb += c == 0 ? WB[i][0] : W[0][i][0];
-            // colour-C1 element's f is stage 1's right-hand side
-            const T fv = c == 0 ? fb[i] : fs[0][i];
-            const double r = double(fv) - (double(T(2 * DIM) * self) - double(nb)) * a.inv_h2;
-            acc += r * r;
+        for (int c = 0; c < 2; ++c) {  // 0: the colour-C0 element, 1: the other
+          const bool eP = (c == 0) == B0P;
+          const T self = c == 0 ? W[0][i][1] : WB[i][1];
+          const T own = c == 0 ? WB[i][1] : W[0][i][1];
+          const T *Ln = c == 0 ? LB : L0;
+          T nb = own + Ln[eP ? lP[i] : lQ[i]];
+          if (DIM == 3) {
+            nb += Ln[lu[i]];
+            nb += Ln[ld[i]];
           }
+          nb += c == 0 ? WB[i][2] : W[0][i][2];
+          nb += c == 0 ? WB[i][0] : W[0][i][0];
+          const T fv = eP ? fP[1][i] : fQ[1][i];
+          const double r = double(fv) - (double(T(2 * DIM) * self) - double(nb)) * a.inv_h2;
+          const bool use = eP ? nP[i] : nQ[i];
+          acc += use ? r * r : 0.0;
         }
       }
     }
@@ -368,22 +474,19 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int zs = t - s;
-      const int cs = (C1 + s - 1) & 1;
-      const T *L = lds + (s - 1) * PL;
+      const bool zin = zs >= 0 && zs < m;
+      const T *L = Lprev + (s - 1) * PL;
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        const int es = (cs + g[i].par + zs) & 1;
-        const int qc = g[i].q;
-        const int sq = es ? min(qc + 1, PL - 1) : max(qc - 1, 0);
-        T nb = W[s - 1][i][1] + L[sq];  // x-1 and x+1 (one is the own pair)
+        T nb = W[s - 1][i][1] + L[isP(s) ? lP[i] : lQ[i]];  // x-1 and x+1 (one is the own pair)
         if (DIM == 3) {
-          nb += L[max(qc - EXP, 0)];     // y - 1
-          nb += L[min(qc + EXP, PL - 1)];  // y + 1
+          nb += L[lu[i]];  // y - 1
+          nb += L[ld[i]];  // y + 1
         }
         nb += W[s - 1][i][2];  // marching axis - 1
         nb += W[s - 1][i][0];  // marching axis + 1
-        const bool in = zs >= 0 && zs < m && ((g[i].ok >> es) & 1);
-        const T v = in ? fma(h2, fs[s - 1][i], nb) * inv2d : T(0);
+        const bool in = zin && (isP(s) ? kP[i] : kQ[i]);
+        const T v = in ? fma(h2, isP(s) ? fP[s][i] : fQ[s][i], nb) * inv2d : T(0);
         if (s < S) {
           W[s][i][2] = W[s][i][1];
           W[s][i][1] = W[s][i][0];
@@ -396,32 +499,45 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     // ---- output plane t-S: last stage's colour from newS, the other from S-1
     const int zo = t - S;
     if (zo >= Z0 && zo < Z1) {
-      constexpr int CS = (C1 + S - 1) & 1;
+      const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.u_out, zo, m, planeS);
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        if (!g[i].outp) continue;
-        const int es = (CS + g[i].par + zo) & 1;
         const T o_new = newS[i], o_old = W[S - 1][i][1];
-        const int o = zo * planeS + g[i].off;
-        uo[o] = es ? o_old : o_new;
-        if (g[i].ok & 2) uo[o + 1] = es ? o_new : o_old;
+        bstore<T>(r, isP(S) ? sP[i] : sQ[i], o_new);
+        bstore<T>(r, isP(S) ? sQ[i] : sP[i], o_old);
       }
     }
-    __syncthreads();
+    // ---- publish the newest plane of every stage for step t+1
+    T *Lnow = lds + TP * NB * PL;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      if (!(g[i].ok & 4)) continue;
+      if (TAIL && i == NS - 1 && !live[i]) continue;
 #pragma unroll
-      for (int s = 0; s < S; ++s) lds[s * PL + g[i].q] = W[s][i][0];
-      if (NORM) lds[S * PL + g[i].q] = WB[i][0];
+      for (int s = 0; s < S; ++s) Lnow[s * PL + lq[i]] = W[s][i][0];
+      if (NORM) Lnow[S * PL + lq[i]] = WB[i][0];
     }
-    if (PRO && (t & 1)) store_c((t + 1) >> 1, cnext);
+    if (PRO && TP == 1) store_c((t + 1) >> 1, cnext);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       pu0[i] = nu0[i];
       pu1[i] = nu1[i];
+#pragma unroll
+      for (int j = S; j >= 1; --j) {
+        fP[j][i] = fP[j - 1][i];
+        fQ[j][i] = fQ[j - 1][i];
+      }
+      fP[0][i] = fnP[i];
+      fQ[0][i] = fnQ[i];
     }
+    if (PRO && TP == 1) {
+#pragma unroll
+      for (int k = 0; k < NCP; ++k) cnext[k] = cnn[k];
+    }
+  };
+  for (int t = t0; t < t1; t += 2) {
+    step(t, IntC<0>());
+    step(t + 1, IntC<1>());
   }
   if (NORM) block_sum_store<NT>(acc, gbl(a.partials));
 }
@@ -623,8 +739,9 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
 // ------------------------------------------------------------------------
 // Each entry: pairs per extended row, extended rows, threads.  Output tile:
 // TX = 2*(EXP - 2*halo_pairs), TY = EY - 2*halo (3D).
-#define GMG_RB3_S2(X) X(3, 2, 66, 30, 1024) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 512)
-#define GMG_RB3_S4(X) X(3, 4, 68, 30, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
+#define GMG_RB3_S2(X) \
+  X(3, 2, 66, 30, 1024) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 512) X(3, 2, 34, 30, 1024)
+#define GMG_RB3_S4(X) X(3, 4, 36, 28, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
 #define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 #define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
 #define GMG_WJ3_S1(X) X(3, 1, 66, 18, 256) X(3, 1, 34, 18, 128)
@@ -693,7 +810,8 @@ namespace {
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
   const size_t cpl = (FL & F_PROLONG) ? 2 * (size_t)(EXP + 1) * (DIM == 3 ? EY / 2 + 1 : 1) : 0;
-  const size_t lds = sizeof(T) * (EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0)) + cpl);
+  // two step-parity buffers of S (+1 with the norm) planes, then the coarse ring
+  const size_t lds = sizeof(T) * (2 * EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0)) + cpl);
   auto k = k_rb_pass<T, DIM, S, EXP, EY, NT, FL>;
   static bool attr = false;
   if (!attr) {

@@ -29,7 +29,8 @@ def _time(fn, reps):
     return a.elapsed_time(b) * 1e3 / reps  # microseconds
 
 
-def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=None):
+def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=None, stages=None,
+        variants=None, kinds=("plain", "zero", "prolong", "prolong_bwd"), transfers=True):
     L = (m + 1).bit_length() - 1
     plan = Plan(dim, L, smoother=smoother, nu1=2, nu2=2)
     n = m ** dim
@@ -42,13 +43,15 @@ def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=Non
     e = torch.rand((mc,) * dim, dtype=dtype, device="cuda", generator=g) * 1e-3
     fc = torch.empty((mc,) * dim, dtype=dtype, device="cuda")
     rows = []
-    stage_counts = (2, 4) if smoother == "rbgs" else (1, 2)
+    stage_counts = stages or ((2, 4) if smoother == "rbgs" else (1, 2))
     for st in stage_counts:
         nsw = st // 2 if smoother == "rbgs" else st
         for v in range(plan.tile_variants(st)):
+            if variants is not None and v not in variants:
+                continue
             for tz in tzs:
                 plan.set_tile(0, st, v, tz)
-                for kind in ("plain", "zero", "prolong", "prolong_bwd"):
+                for kind in kinds:
                     if kind == "plain":
                         fn = lambda: plan.op_smooth(0, nsw, False, u, f, None, o)
                         nb = 3 * n * es
@@ -64,11 +67,12 @@ def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=Non
                     us = _time(fn, reps)
                     rows.append(dict(kernel="%s_pass" % smoother, stages=st, variant=v, tz=tz,
                                      kind=kind, us=us, gbs=nb / (us * 1e-6) / 1e9))
-    us = _time(lambda: plan.op_restrict_residual(0, u, f, fc), reps)
-    rows.append(dict(kernel="resid_restrict", us=us,
-                     gbs=(2 * n + mc ** dim) * es / (us * 1e-6) / 1e9))
-    us = _time(lambda: plan.op_residual(0, u, f, o, want_norm=False), reps)
-    rows.append(dict(kernel="residual", us=us, gbs=3 * n * es / (us * 1e-6) / 1e9))
+    if transfers:
+        us = _time(lambda: plan.op_restrict_residual(0, u, f, fc), reps)
+        rows.append(dict(kernel="resid_restrict", us=us,
+                         gbs=(2 * n + mc ** dim) * es / (us * 1e-6) / 1e9))
+        us = _time(lambda: plan.op_residual(0, u, f, o, want_norm=False), reps)
+        rows.append(dict(kernel="residual", us=us, gbs=3 * n * es / (us * 1e-6) / 1e9))
     for r in rows:
         print(json.dumps(r), flush=True)
     if out:
@@ -104,13 +108,18 @@ def main():
     ap.add_argument("--tz", type=int, nargs="+", default=[0])
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--stages", type=int, nargs="+", default=None)
+    ap.add_argument("--variants", type=int, nargs="+", default=None)
+    ap.add_argument("--kinds", nargs="+", default=["plain", "zero", "prolong", "prolong_bwd"])
+    ap.add_argument("--no-transfers", action="store_true")
     a = ap.parse_args()
     if a.copy_mib:
         copy_calibration(a.copy_mib, a.reps)
         return
     for m in a.m:
         print("# dim %d m %d" % (a.dim, m), flush=True)
-        run(a.dim, m, a.reps, torch.float32 if a.fp32 else torch.float64, a.smoother, a.tz, a.out)
+        run(a.dim, m, a.reps, torch.float32 if a.fp32 else torch.float64, a.smoother, a.tz, a.out,
+            a.stages, a.variants, a.kinds, not a.no_transfers)
 
 
 if __name__ == "__main__":
