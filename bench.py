@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rb_pass_restrict_l0_poisson3d_255_traffic.md")
 
 WORKLOADS = {
     # name: (dim, levels, rhs builder, smoother, nu, precision, description)
@@ -77,6 +78,29 @@ def cpu_baseline(spec, f, budget_s=30.0):
     return dict(value=N / (t * 12), unit="unknowns/s", cores=oracle.num_threads(), kind="oracle",
                 sample="%d V-cycles of the same workload at %.3f s each, scaled to 12 cycles"
                 % (ncyc, t))
+
+
+def measured_traffic(workload, cls, tile):
+    """HBM bytes per launch of kernel class `cls` from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None
+    when the summary is for another workload, kernel source or tile."""
+    import hashlib
+
+    if workload != DEFAULT or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    line = [l for l in open(TRAFFIC_PROFILE) if l.startswith("traffic-json: ")]
+    if not line:
+        return None
+    rec = json.loads(line[-1][len("traffic-json: "):])
+    csrc = os.path.join(ROOT, "paper_1208_4247_amd", "csrc")
+    for name, key in (("smooth.hip", "smooth_hip_sha256"), ("transfer.hip", "transfer_hip_sha256")):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec.get(key):
+                return None
+    e = rec["entries"].get(cls)
+    if not e or tile is None or (e.get("stages"), e.get("variant"), e.get("tz")) != tuple(tile):
+        return None
+    return e["traffic_bytes"]
 
 
 def bench_batch(args):
@@ -184,6 +208,8 @@ def main():
     value = N / (t_total / args.steps)
     dom = max(smoothers, key=lambda k: prof[k]["ms"])
     pv = prof[dom]
+    tile = plan.get_tile(0, 0 if dom == "smooth_pre_l0" else 1)
+    traffic = measured_traffic(args.workload, dom, tile)
     achieved = pv["bytes"] / (pv["ms"] * 1e-3) / 1e9 if pv["ms"] > 0 else 0.0
     avg_us = 1e3 * pv["ms"] / max(pv["launches"], 1)
     bytes_per_launch = pv["bytes"] / max(pv["launches"], 1)
@@ -218,8 +244,10 @@ def main():
         "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
                    "cycle": "V(2,2) red-black GS", "rtol": 1e-10, "iters": iters[-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch,
+                     "tile": {"stages": tile[0], "variant": tile[1], "tz": tile[2]},
+                     "timer": "HIP events recorded by each dispatch of the kernel"},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, f_host)

@@ -168,6 +168,14 @@ int gmg_tile_variant_count(int dim, gmg_smoother smoother, int stages);
  * choice (tests check this bitwise); only speed does.  Host only. */
 gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, int tz);
 
+/* The tile choice in use (after autotuning, if any) for the first pass of
+ * the pre- (role 0) or post-smoothing (role 1) on level `level` of problem 0:
+ * its stage count, tile index and z-chunk (resolved, > 0).  Host only; any
+ * output pointer may be NULL.  GMG_ERR_INVALID_ARG for a bad level/role, a
+ * batch plan, or a role without sweeps. */
+gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages, int *variant,
+                             int *tz);
+
 /* ---------------------------------------------------------------------- */
 /* Operator primitives.  Each runs exactly the kernels the cycle runs for  */
 /* one step, on problem 0's level `level` (side m = gmg_level_side(p,0,l)).*/

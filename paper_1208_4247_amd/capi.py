@@ -40,7 +40,7 @@ EXPORTED = [
     "gmg_destroy", "gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
     "gmg_op_smooth", "gmg_op_restrict_residual", "gmg_op_residual", "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
-    "gmg_profile_set_mask",
+    "gmg_profile_set_mask", "gmg_plan_get_tile",
 ]
 
 
@@ -109,6 +109,8 @@ def lib():
     L.gmg_tile_variant_count.argtypes = [i, i, i]
     L.gmg_plan_set_tile.argtypes = [vp, i, i, i, i]
     L.gmg_profile_set_mask.argtypes = [vp, ctypes.c_uint]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.gmg_plan_get_tile.argtypes = [vp, i, i, ip, ip, ip]
     for name in EXPORTED:
         if name not in ("gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
                         "gmg_profile_count", "gmg_tile_variant_count"):

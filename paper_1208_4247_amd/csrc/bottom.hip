@@ -266,7 +266,7 @@ hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const BottomArgs<T> *tb
     attr = true;
   }
   const int nt = (a.dim == 3 && a.L <= 3) || (a.dim == 2 && a.L <= 4) ? 256 : 1024;
-  hipLaunchKernelGGL(k_bottom<T>, dim3(nproblems), dim3(nt), lds, s, a, tbl);
+  gmg_launch(k_bottom<T>, dim3(nproblems), dim3(nt), lds, s, a, tbl);
   return hipGetLastError();
 }
 

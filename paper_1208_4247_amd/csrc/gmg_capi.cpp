@@ -208,6 +208,17 @@ hipEvent_t get_event(gmg_plan *p) {
   return e;
 }
 
+}  // namespace
+
+DispatchEvents &gmg::next_dispatch_events() {
+  static thread_local DispatchEvents ev{nullptr, nullptr};
+  return ev;
+}
+
+namespace {
+
+// Times the one kernel launch inside its scope: the dispatch itself records
+// the start and end events (no marker packets around it).
 struct ProfScope {
   gmg_plan *p;
   int cls;
@@ -215,13 +226,22 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(gmg_plan *p_, int cls_, double bytes_) : p(p_), cls(cls_), bytes(bytes_) {
     if (!p->profile || !((p->prof_mask >> cls) & 1u)) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return;
     a = get_event(p);
     b = get_event(p);
-    if (a) (void)hipEventRecord(a, p->stream);
+    if (a && b) next_dispatch_events() = {a, b};
   }
   ~ProfScope() {
     if (!a || !b) return;
-    (void)hipEventRecord(b, p->stream);
+    DispatchEvents &ev = next_dispatch_events();
+    if (ev.start == a) {  // nothing was launched
+      ev.start = ev.stop = nullptr;
+      p->evpool.push_back(a);
+      p->evpool.push_back(b);
+      return;
+    }
     p->pending.push_back({cls, a, b, bytes});
   }
 };
@@ -1712,6 +1732,23 @@ gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, in
     c.tz[stages] = tzv;
     c.smax = sweeps;
   }
+  return GMG_OK;
+}
+
+gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages, int *variant,
+                             int *tz) {
+  if (!p || p->batch || level < 0 || level >= p->L || role < 0 || role > 1)
+    return GMG_ERR_INVALID_ARG;
+  const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;
+  if (nu < 1) return GMG_ERR_INVALID_ARG;
+  const PassChoice &c = p->ch[level][role];
+  const int st = stages_of(p, std::min(c.smax, nu));
+  const int wj = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+  const PassTile t = pass_variant(p->dim, st, wj, c.var[st]);
+  if (stages) *stages = st;
+  if (variant) *variant = c.var[st];
+  if (tz) *tz = c.tz[st] > 0 ? std::min(c.tz[st], p->m[level])
+                             : auto_tz(p->dim, p->m[level], st, t);
   return GMG_OK;
 }
 

@@ -2,6 +2,7 @@
 // orchestration of the multigrid library (not part of the public ABI).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -19,6 +20,27 @@ __device__ __forceinline__ GMG_GLOBAL T *gbl(T *p) {
 template <typename T>
 __device__ __forceinline__ const GMG_GLOBAL T *gbl(const T *p) {
   return (const GMG_GLOBAL T *)p;
+}
+
+// Event pair that the library's profiler wants the next kernel dispatch of
+// this host thread to record (start and end of that dispatch, the same
+// timestamps a kernel-trace profiler reports), or {NULL, NULL}.
+struct DispatchEvents {
+  hipEvent_t start, stop;
+};
+DispatchEvents &next_dispatch_events();
+
+// Every kernel launch of the library goes through here.
+template <typename F, typename... Args>
+inline void gmg_launch(F k, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  DispatchEvents &ev = next_dispatch_events();
+  if (ev.start) {
+    hipEvent_t a = ev.start, b = ev.stop;
+    ev.start = ev.stop = nullptr;
+    hipExtLaunchKernelGGL(k, grid, block, (uint32_t)lds, s, a, b, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(k, grid, block, lds, s, args...);
+  }
 }
 
 // Flags of a fused smoothing pass.

@@ -283,9 +283,9 @@ hipError_t run_small(bool down, SmallArgs<T> a, hipStream_t s, const SmallArgs<T
   }
   dim3 grid(a.nblocks, nent);
   if (down)
-    hipLaunchKernelGGL((k_small_down<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
+    gmg_launch((k_small_down<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
   else
-    hipLaunchKernelGGL((k_small_up<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
+    gmg_launch((k_small_up<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
   return hipGetLastError();
 }
 }  // namespace

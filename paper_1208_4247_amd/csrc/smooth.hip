@@ -820,7 +820,7 @@ hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
+  gmg_launch(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
   return hipGetLastError();
 }
 
@@ -835,7 +835,7 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
+  gmg_launch(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
   return hipGetLastError();
 }
 

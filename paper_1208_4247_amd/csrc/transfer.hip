@@ -452,14 +452,14 @@ hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s, const Rest
       const int czc = mc >= 256 ? 8 : 4;
       const int ncz = (mc + czc - 1) / czc;
       const int nb = ncx * ncy * ncz;
-      hipLaunchKernelGGL((k_restrict<T, 3, 32, 8, 256>), dim3(nb, nent), dim3(256), 0, s, a, tbl, ncx,
+      gmg_launch((k_restrict<T, 3, 32, 8, 256>), dim3(nb, nent), dim3(256), 0, s, a, tbl, ncx,
                          ncy, czc, nb);
     } else {
       const int ncx = (mc + 15) / 16, ncy = (mc + 7) / 8;
       const int czc = mc >= 16 ? 2 : 1;
       const int ncz = (mc + czc - 1) / czc;
       const int nb = ncx * ncy * ncz;
-      hipLaunchKernelGGL((k_restrict<T, 3, 16, 8, 128>), dim3(nb, nent), dim3(128), 0, s, a, tbl, ncx,
+      gmg_launch((k_restrict<T, 3, 16, 8, 128>), dim3(nb, nent), dim3(128), 0, s, a, tbl, ncx,
                          ncy, czc, nb);
     }
   } else {
@@ -467,7 +467,7 @@ hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s, const Rest
     const int czc = mc >= 512 ? 16 : (mc >= 128 ? 8 : 2);
     const int ncz = (mc + czc - 1) / czc;
     const int nb = ncx * ncz;
-    hipLaunchKernelGGL((k_restrict<T, 2, 64, 1, 128>), dim3(nb, nent), dim3(128), 0, s, a, tbl, ncx, 1,
+    gmg_launch((k_restrict<T, 2, 64, 1, 128>), dim3(nb, nent), dim3(128), 0, s, a, tbl, ncx, 1,
                        czc, nb);
   }
   return hipGetLastError();
@@ -477,44 +477,44 @@ template <typename T>
 hipError_t launch_residual(int dim, ResidArgs<T> a, hipStream_t s) {
   const int nb = a.nblocks > 0 ? a.nblocks : residual_blocks(dim, a.m);
   if (dim == 3)
-    hipLaunchKernelGGL((k_residual<T, 3, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_residual<T, 3, 256>), dim3(nb), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_residual<T, 2, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_residual<T, 2, 256>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s) {
   const int nb = a.nblocks > 0 ? a.nblocks : ir_blocks(dim, a.m);
   if (dim == 3)
-    hipLaunchKernelGGL((k_ir_step<3, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_ir_step<3, 256>), dim3(nb), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_ir_step<2, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_ir_step<2, 256>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double *partials, int n, SolveState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, n, st);
+  gmg_launch(k_finalize, dim3(1), dim3(64), 0, s, partials, n, st);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize_batch(const FinEntry *tbl, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize_batch, dim3(n), dim3(64), 0, s, tbl);
+  gmg_launch(k_finalize_batch, dim3(n), dim3(64), 0, s, tbl);
   return hipGetLastError();
 }
 
 hipError_t launch_state_init_batch(SolveState *st, int n, int maxit, double rtol, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_init_batch, dim3((n + 255) / 256), dim3(256), 0, s, st, n, maxit, rtol);
+  gmg_launch(k_state_init_batch, dim3((n + 255) / 256), dim3(256), 0, s, st, n, maxit, rtol);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_norm(const double *partials, int n, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(64), 0, s, partials, n, out);
+  gmg_launch(k_reduce_norm, dim3(1), dim3(64), 0, s, partials, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_state_init(SolveState *st, int maxit, double rtol, double res0, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, rtol, res0);
+  gmg_launch(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, rtol, res0);
   return hipGetLastError();
 }
 
@@ -524,7 +524,7 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, const int *acti
   size_t nb = (n2 + 255) / 256;
   if (nb > 8192) nb = 8192;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const double2 *)src,
+  gmg_launch(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const double2 *)src,
                      (double2 *)dst, n2, (const unsigned char *)src + n2 * 16,
                      (unsigned char *)dst + n2 * 16, tail, active);
   return hipGetLastError();
@@ -534,7 +534,7 @@ hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s) {
   size_t nb = (bytes + 255) / 256;
   if (nb > 8192) nb = 8192;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, (unsigned char *)dst,
+  gmg_launch(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, s, (unsigned char *)dst,
                      bytes);
   return hipGetLastError();
 }
@@ -544,9 +544,9 @@ hipError_t launch_prolong_add(int dim, int m, int mc, const T *in, const T *ec, 
                               const int *active, hipStream_t s) {
   const int nb = residual_blocks(dim, m);
   if (dim == 3)
-    hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+    gmg_launch((k_prolong_add<T, 3>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
   else
-    hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+    gmg_launch((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
   return hipGetLastError();
 }
 
@@ -554,7 +554,7 @@ hipError_t launch_axpy_f32(double *x, const float *e, size_t n, const int *activ
   size_t nb = (n + 255) / 256;
   if (nb > 8192) nb = 8192;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_axpy_f32, dim3((unsigned)nb), dim3(256), 0, s, x, e, n, active);
+  gmg_launch(k_axpy_f32, dim3((unsigned)nb), dim3(256), 0, s, x, e, n, active);
   return hipGetLastError();
 }
 

@@ -91,6 +91,15 @@ class Plan:
         capi.check(capi.lib().gmg_plan_set_tile(self._plan, int(level), int(stages), int(variant),
                                                 int(tz)), "gmg_plan_set_tile")
 
+    def get_tile(self, level, role):
+        """(stages, variant, tz) of the first pre- (role 0) or post-smoothing
+        (role 1) pass on `level` after autotuning."""
+        st, v, tz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        capi.check(capi.lib().gmg_plan_get_tile(self._plan, int(level), int(role), ctypes.byref(st),
+                                                ctypes.byref(v), ctypes.byref(tz)),
+                   "gmg_plan_get_tile")
+        return st.value, v.value, tz.value
+
     def tile_variants(self, stages: int) -> int:
         return capi.lib().gmg_tile_variant_count(self.dim, self.cfg.smoother, int(stages))
 
