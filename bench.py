@@ -25,20 +25,30 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rb_pass_restrict_l0_poisson3d_255_traffic.md")
 
 WORKLOADS = {
-    # name: (dim, levels, rhs builder, smoother, nu, precision, description)
+    # name: dim, levels, right-hand side, precision, sweeps nu1 = nu2, FP32
+    # cycles per refinement step (mixed)
     "poisson3d_255_sine_noise_fp64_v22": dict(dim=3, L=8, rhs="sine_noise", prec="fp64"),
     "poisson2d_127_sine_fp64_v22": dict(dim=2, L=7, rhs="sine", prec="fp64"),
     "poisson3d_511_uniform_fp64_v22": dict(dim=3, L=9, rhs="uniform", prec="fp64"),
     "poisson3d_511_uniform_mixed_v22": dict(dim=3, L=9, rhs="uniform", prec="mixed"),
+    "poisson3d_511_uniform_mixed2_v22": dict(dim=3, L=9, rhs="uniform", prec="mixed", inner=2),
+    "poisson3d_1023_sine_modes_fp64_v11": dict(dim=3, L=10, rhs="sine_modes", prec="fp64", nu=1),
+    "poisson3d_1023_sine_modes_mixed_v11": dict(dim=3, L=10, rhs="sine_modes", prec="mixed",
+                                                nu=1),
+    "poisson3d_1023_sine_modes_mixed2_v11": dict(dim=3, L=10, rhs="sine_modes", prec="mixed",
+                                                 nu=1, inner=2),
     "batch256_uneven_fp64_v22": dict(dim=0, L=0, rhs="batch", prec="fp64"),
 }
 DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
 
 
 def make_rhs(spec):
+    """Host right-hand side (None for recipes built on the device)."""
     from paper_1208_4247_amd import workloads as wl
 
     d, m = spec["dim"], (1 << spec["L"]) - 1
+    if spec["rhs"] == "sine_modes":
+        return None
     if spec["rhs"] == "sine_noise":
         return wl.rhs_sine_plus_noise(d, m, 2)
     if spec["rhs"] == "sine":
@@ -70,7 +80,7 @@ def cpu_baseline(spec, f, budget_s=30.0):
         return dict(value=N / t, unit="unknowns/s", cores=oracle.num_threads(), kind="oracle",
                     sample="full solve of the same workload (%d V-cycles to relres %.1e), %.2f s"
                     % (it, rel, t))
-    ncyc = max(1, int(budget_s / t_cycle))
+    ncyc = max(1, min(int(budget_s / t_cycle), 20))
     t0 = time.perf_counter()
     for _ in range(ncyc):
         u = oracle.vcycle(u, f)
@@ -135,6 +145,28 @@ def bench_batch(args):
         torch.cuda.synchronize()
         t_total += time.perf_counter() - t0
     value = N / (t_total / args.steps)
+    # the same 256 problems solved one after another by single-problem plans
+    # (one plan per distinct size, autotuned during a warm-up pass)
+    from paper_1208_4247_amd.solver import Plan
+
+    plans = {}
+    for d, m in sorted(set(probs)):
+        plans[(d, m)] = Plan(d, (m + 1).bit_length() - 1, flags=args.flags | capi.GMG_AUTOTUNE)
+    for q, (d, m) in enumerate(probs):
+        us[q].zero_()
+        plans[(d, m)].solve(us[q], fs[q], rtol=1e-10)
+    torch.cuda.synchronize()
+    seq = []
+    for _ in range(max(1, min(args.steps, 3))):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q, (d, m) in enumerate(probs):
+            plans[(d, m)].solve(us[q], fs[q], rtol=1e-10)
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - t0)
+    seq_ms = 1e3 * sum(seq) / len(seq)
     line = {
         "metric": "fine-grid unknowns/s to 1e-10 rel. residual (batch of 256 uneven problems)",
         "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
@@ -142,9 +174,45 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "batch256_uneven_fp64_v22", "problems": len(probs),
-                   "unknowns": N, "max_cycles": max(its), "min_cycles": min(its)},
+                   "unknowns": N, "max_cycles": max(its), "min_cycles": min(its),
+                   "sequential_single_solves_ms": seq_ms,
+                   "speedup_vs_sequential": seq_ms / (1e3 * t_total / args.steps)},
     }
     print(json.dumps(line), flush=True)
+
+
+def compare_fp64(args, spec, plan, u_mixed, f, mixed_ms):
+    """The plain FP64 solve of the same problem in the same process: its time
+    to 1e-10, and the mixed result's distance from it and FP64 residual."""
+    import torch
+
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import Plan
+
+    d, L, nu = spec["dim"], spec["L"], spec.get("nu", 2)
+    flags = args.flags | (0 if args.no_autotune else capi.GMG_AUTOTUNE)
+    p64 = Plan(d, L, flags=flags, nu1=nu, nu2=nu)
+    u64 = torch.zeros_like(f)
+    p64.solve(u64, f, rtol=1e-10)  # warm-up (autotunes)
+    ts = []
+    for _ in range(max(1, min(args.steps, 3))):
+        u64.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it64, rel64 = p64.solve(u64, f, rtol=1e-10)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ms64 = 1e3 * sum(ts) / len(ts)
+    diff = float(torch.linalg.vector_norm(u_mixed - u64) / torch.linalg.vector_norm(u64))
+    # FP64 residual of the mixed result, by the FP64 plan's own residual kernel
+    r = torch.empty_like(f)
+    nrm = p64.op_residual(0, u_mixed, f, r, want_norm=True)
+    res0 = float(torch.linalg.vector_norm(f))
+    del r, p64, u64
+    return {"fp64_ms_per_solve": ms64, "fp64_iters": it64,
+            "speedup_vs_fp64": ms64 / mixed_ms,
+            "mixed_vs_fp64_rel_diff": diff,
+            "mixed_fp64_relres": (nrm / res0) if res0 > 0 else 0.0}
 
 
 def main():
@@ -171,16 +239,23 @@ def main():
     if spec["rhs"] == "batch":
         return bench_batch(args)
     d, L = spec["dim"], spec["L"]
+    nu = spec.get("nu", 2)
+    inner = spec.get("inner", 1)
     m = (1 << L) - 1
     N = m ** d
     f_host = make_rhs(spec)
     torch.cuda.set_device(0)
-    f = torch.from_numpy(f_host).cuda()
+    if f_host is None:
+        from paper_1208_4247_amd import workloads as wl
+
+        f = wl.rhs_sine_modes_device(d, m, 5, "cuda")
+    else:
+        f = torch.from_numpy(f_host).cuda()
     u = torch.zeros_like(f)
     flags = args.flags | capi.GMG_PROFILE
     if not args.no_autotune:
         flags |= capi.GMG_AUTOTUNE
-    plan = Plan(d, L, precision=spec["prec"], flags=flags)
+    plan = Plan(d, L, precision=spec["prec"], flags=flags, nu1=nu, nu2=nu, inner_cycles=inner)
     print("# workload %s: %d^%d, plan workspace %.1f MB" % (args.workload, m, d,
           plan.workspace.numel() / 1e6), flush=True)
 
@@ -242,14 +317,17 @@ def main():
         "dtype": "f64" if spec["prec"] == "fp64" else "f32-in-f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
-                   "cycle": "V(2,2) red-black GS", "rtol": 1e-10, "iters": iters[-1]},
+                   "cycle": "V(%d,%d) red-black GS" % (nu, nu), "rtol": 1e-10, "iters": iters[-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch,
                      "tile": {"stages": tile[0], "variant": tile[1], "tz": tile[2]},
                      "timer": "HIP events recorded by each dispatch of the kernel"},
     }
-    if not args.no_cpu_baseline:
+    if spec["prec"] == "mixed":
+        line["config"].update(compare_fp64(args, spec, plan, u, f, ms_per_step))
+        line["config"]["inner_cycles"] = inner
+    if not args.no_cpu_baseline and f_host is not None:
         line["cpu_baseline"] = cpu_baseline(spec, f_host)
     print(json.dumps(line), flush=True)
 

@@ -66,6 +66,7 @@ struct PendingEv {
   int cls;
   hipEvent_t a, b;
   double bytes;
+  int tag;  // solve-loop body that enqueued the launch (-1: outside a solve)
 };
 
 struct PassChoice {
@@ -156,6 +157,7 @@ struct gmg_plan {
   unsigned prof_mask = ~0u;
   std::vector<Prof> prof;
   std::vector<PendingEv> pending;
+  int prof_tag = -1;  // body index of the solve loop being enqueued
   std::vector<hipEvent_t> evpool;
 
   SolveState *hstate = nullptr;  // pinned host copy
@@ -242,9 +244,28 @@ struct ProfScope {
       p->evpool.push_back(b);
       return;
     }
-    p->pending.push_back({cls, a, b, bytes});
+    p->pending.push_back({cls, a, b, bytes, p->prof_tag});
   }
 };
+
+// The solve loop enqueues bodies ahead of its stop test; the kernels of a
+// body after the one that stopped the loop return at once.  Drop their
+// timings (and, in the stopping body, everything after the step that ran
+// the test), so profiles average over launches that did their work.
+void prune_profile(gmg_plan *p, int last_body, int keep_cls) {
+  std::vector<PendingEv> kept;
+  kept.reserve(p->pending.size());
+  for (auto &e : p->pending) {
+    const bool drop = e.tag >= 0 && (e.tag > last_body || (e.tag == last_body && e.cls != keep_cls));
+    if (drop) {
+      p->evpool.push_back(e.a);
+      p->evpool.push_back(e.b);
+    } else {
+      kept.push_back(e);
+    }
+  }
+  p->pending.swap(kept);
+}
 
 gmg_status harvest(gmg_plan *p) {
   if (p->pending.empty()) return GMG_OK;
@@ -1587,6 +1608,10 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
   if (!p || !u || !f || p->batch) return GMG_ERR_INVALID_ARG;
   if (!(rtol > 0.0) || maxit < 1) return GMG_ERR_INVALID_ARG;
   if (res0_opt && !(*res0_opt >= 0.0)) return GMG_ERR_INVALID_ARG;
+  struct TagReset {
+    gmg_plan *p;
+    ~TagReset() { p->prof_tag = -1; }
+  } tag_reset{p};
   if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) {
     if (p->cfg.precision == GMG_FP64)
       HIPCHK(tune_plan<double>(p, u, f, p->partials));
@@ -1604,6 +1629,7 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
   int batch = 2;
   for (;;) {
     for (int b = 0; b < batch; ++b, ++enq) {
+      p->prof_tag = enq;
       if (!mixed) {
         HIPCHK(enqueue_vcycle<double>(p, u, f, u, p->partials, act));
       } else {
@@ -1643,7 +1669,9 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
     batch = std::min(estimate_cycles(*p->hstate, p->hstate->iter - 1), maxit + 1 - enq);
     if (batch < 1) batch = 1;
   }
+  p->prof_tag = -1;
   const SolveState st = *p->hstate;
+  if (p->profile) prune_profile(p, st.iter, mixed ? PC_IR : PC_PRE0);
   if (mixed && (st.iter % 2 == 1)) {
     // the final iterate x_iter sits in the workspace copy
     HIPCHK(launch_copy(p->x2, u, N0 * sizeof(double), nullptr, p->stream));

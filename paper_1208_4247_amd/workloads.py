@@ -122,6 +122,29 @@ def rhs_sine_modes(d: int, m: int, seed: int, nmodes: int = 8, kmax: int = 32) -
     return f
 
 
+def rhs_sine_modes_device(d: int, m: int, seed: int, device, nmodes: int = 8,
+                          kmax: int = 32):
+    """The same array as rhs_sine_modes, built on a torch device: the per-axis
+    sine vectors come from the host in FP64 and each mode is the same chain of
+    IEEE products and one addition, so the result is bitwise the host one.
+    For grids too large to build on the host comfortably (1023^3)."""
+    import torch
+
+    amps, ks = sine_modes(seed, d, nmodes, kmax)
+    x = nodes(m)
+    f = torch.zeros((m,) * d, dtype=torch.float64, device=device)
+    for a, k in zip(amps, ks):
+        fac = [torch.from_numpy(np.sin(int(kk) * math.pi * x)).to(device) for kk in k]
+        if d == 2:
+            prod = fac[1][:, None] * fac[0][None, :]
+        else:
+            prod = (fac[2][:, None, None] * fac[1][None, :, None]) * fac[0][None, None, :]
+        prod.mul_(float(a))
+        f.add_(prod)
+        del prod
+    return f
+
+
 def batch_problems(seed: int = 4, n2d: int = 128, n3d: int = 128,
                    k2d=(6, 10), k3d=(5, 7)):
     """The uneven batch: (dim, side) per problem.  Problem p < n2d is 2D with

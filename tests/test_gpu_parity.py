@@ -298,3 +298,41 @@ def test_fused_coarse_kernels_bitwise(dim, m, nu, post_forward):
     want = oracle.vcycle(host(u0), host(f), nu[0], nu[1]) if not post_forward else None
     if want is not None:
         assert maxrel(outs[0], want) <= 1e-12
+
+
+# ------------------------------------------------------------------ profiling
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profile_counts_only_launches_that_ran(precision):
+    """The solve loop enqueues cycles ahead of its stop test; the launches of
+    cycles after the stopping one exit at once and must not enter the
+    profile (their near-zero durations would deflate per-launch averages).
+    FP64: the pre-pass runs once per cycle plus once for the final norm; the
+    post-pass and restriction once per cycle.  Mixed: one refinement step
+    per cycle plus the final one."""
+    from paper_1208_4247_amd import capi
+
+    f = dev(wl.rhs_uniform(3, 127, seed=21))
+    plan = Plan(3, 7, precision=precision, flags=capi.GMG_PROFILE)
+    u = torch.zeros_like(f)
+    st, it, rel = plan.solve(u, f, rtol=1e-10)
+    prof = plan.profile()
+    assert st == 0 and it >= 3
+    if precision == "fp64":
+        # passes per smoothing step: nu = 2 sweeps in passes of stages / 2 sweeps
+        npre = 2 // (plan.get_tile(0, 0)[0] // 2)
+        npost = 2 // (plan.get_tile(0, 1)[0] // 2)
+        assert prof["smooth_pre_l0"]["launches"] == npre * (it + 1)
+        assert prof["smooth_post_l0"]["launches"] == npost * it
+        assert prof["resid_restrict_l0"]["launches"] == it
+        assert prof["bottom"]["launches"] == it
+    else:
+        assert prof["ir_step"]["launches"] == it + 1
+        assert prof["bottom"]["launches"] == it
+    # a second solve accumulates the same counts again
+    u.zero_()
+    plan.solve(u, f, rtol=1e-10)
+    prof2 = plan.profile()
+    key = "smooth_pre_l0" if precision == "fp64" else "ir_step"
+    assert prof2[key]["launches"] == 2 * prof[key]["launches"]

@@ -1,4 +1,5 @@
 """The seeded input generator (shared by the oracle's and the GPU's tests)."""
+import pytest
 import numpy as np
 
 from paper_1208_4247_amd import workloads as wl
@@ -32,3 +33,13 @@ def test_batch_recipe():
 def test_normals():
     z = wl.normal(5, 1, 20000)
     assert abs(z.mean()) < 0.05 and abs(z.std() - 1) < 0.05
+
+
+def test_device_sine_modes_equal_host_recipe():
+    """The torch-built sum of sine modes (used for the 1023^3 workload) is
+    bitwise the host recipe."""
+    torch = pytest.importorskip("torch")
+    for d, m in ((3, 31), (2, 63), (3, 15)):
+        a = wl.rhs_sine_modes(d, m, 5)
+        b = wl.rhs_sine_modes_device(d, m, 5, "cpu").numpy()
+        assert np.array_equal(a, b)
