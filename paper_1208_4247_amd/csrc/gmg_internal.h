@@ -43,6 +43,61 @@ inline void gmg_launch(F k, dim3 grid, dim3 block, size_t lds, hipStream_t s, Ar
   }
 }
 
+// ---- buffer-resource access used by the plane-marching kernels.  A raw
+// buffer over one plane (no records for a plane outside the grid) with a
+// per-element byte offset that is out of range outside the grid: such loads
+// return 0 and such stores are dropped, so the zero Dirichlet boundary costs
+// no branches.
+constexpr int kOOB = 0x7ffffff0;  // byte offset beyond any plane resource
+
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, int z, int m,
+                                                             int plane) {
+  // raw buffer over plane z (no records when z is outside 0..m-1)
+  const bool in = z >= 0 && z < m;
+  const T *p = base + (in ? (size_t)z * plane : 0);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0,
+                                           in ? plane * (int)sizeof(T) : 0, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+typedef unsigned int gmg_u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct PairOf {
+  T lo, hi;
+};
+
+// two adjacent elements in one load (16 bytes for FP64, 8 for FP32)
+template <typename T>
+__device__ __forceinline__ PairOf<T> bload2(__amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(PairOf<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(PairOf<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gmg_u32x2, v), r, off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
+
 // Flags of a fused smoothing pass.
 enum PassFlags : int {
   F_ZERO_IN = 1,     // start value is zero: u_in is not read
@@ -145,7 +200,8 @@ struct IrArgs {
   float *r32;           // (float)(f - A (x + e))
   double *partials;
   const int *active;
-  int m, nblocks;
+  int m, nblocks;       // nblocks must equal ir_blocks(dim, m)
+  int cz;               // set by the launcher: planes per workgroup
   double inv_h2;
 };
 

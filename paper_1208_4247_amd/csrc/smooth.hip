@@ -137,55 +137,6 @@ __device__ __forceinline__ void slot_setup(SlotGeo (&g)[NS], int X0, int Y0, int
 // compile-time choice between the two elements of a pair, and the LDS planes
 // are double-buffered by step parity, so one barrier per step suffices.
 // ------------------------------------------------------------------------
-constexpr int kOOB = 0x7ffffff0;  // byte offset beyond any plane resource
-
-template <int V>
-struct IntC {
-  static constexpr int value = V;
-};
-
-template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, int z, int m,
-                                                             int plane) {
-  // raw buffer over plane z (no records when z is outside 0..m-1)
-  const bool in = z >= 0 && z < m;
-  const T *p = base + (in ? (size_t)z * plane : 0);
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0,
-                                           in ? plane * (int)sizeof(T) : 0, 0x00020000);
-}
-
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off) {
-  if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-  else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-
-typedef unsigned int gmg_u32x2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-struct PairOf {
-  T lo, hi;
-};
-
-// two adjacent elements in one load (16 bytes for FP64, 8 for FP32)
-template <typename T>
-__device__ __forceinline__ PairOf<T> bload2(__amdgpu_buffer_rsrc_t r, int off) {
-  if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(PairOf<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-  else
-    return __builtin_bit_cast(PairOf<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-
-template <typename T>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
-  if constexpr (sizeof(T) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gmg_u32x2, v), r, off, 0, 0);
-  else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
-}
-
 // Argument block of this workgroup: the kernel argument, or (batch mode) the
 // table entry of problem blockIdx.y, read through the scalar cache.
 template <typename A>

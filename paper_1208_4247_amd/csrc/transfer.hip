@@ -280,43 +280,101 @@ int residual_blocks(int dim, int m) {
 
 // ------------------------------------------------------------------------
 // Refinement step: x_out = x + e (FP64), r32 = float(f - A x_out), norm
-// partials.  Both x and e are read at the neighbours, so x_out never aliases
-// x (the caller ping-pongs).
+// partials of |f - A x_out|^2.  Both x and e are read at the neighbours, so
+// x_out never aliases x (the caller ping-pongs).
+//
+// A workgroup owns a TX x TY column tile (3D; TX x 1 in 2D) and marches along
+// the outermost axis over a chunk of planes.  x + e of a plane, with a
+// one-point halo, is formed once per plane into a four-plane LDS ring; the
+// next plane's loads are in flight while the current plane's residual is
+// computed.  Loads use plane buffer resources (zero outside the grid).
 // ------------------------------------------------------------------------
-template <int DIM, int NT>
+template <int DIM, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
-  if (a.active && *a.active == 0) return;
+  if (a.active && *gbl(a.active) == 0) return;
+  constexpr int HX = TX + 2, HY = DIM == 3 ? TY + 2 : 1, HP = HX * HY;
+  constexpr int NL = (HP + NT - 1) / NT;
+  __shared__ double ring[4][HP];
   const int m = a.m;
-  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
-  double acc = 0.0;
-  const GMG_GLOBAL double *__restrict__ xg = gbl(a.x);
-  const GMG_GLOBAL float *__restrict__ eg = gbl(a.e);
-  const GMG_GLOBAL double *__restrict__ fg = gbl(a.f);
-  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
-    const int x = (int)(p % m);
-    const size_t rest = p / m;
-    const int y = (int)(rest % m);
-    const int z = DIM == 3 ? (int)(rest / m) : 0;
-    auto val = [&](int i, int j, int k) -> double {
-      if (i < 0 || j < 0 || i >= m || j >= m) return 0.0;
-      if (DIM == 3 && (k < 0 || k >= m)) return 0.0;
-      const size_t o = DIM == 3 ? ((size_t)k * m + j) * m + i : (size_t)j * m + i;
-      double v = xg[o];
-      if (eg) v += double(eg[o]);
-      return v;
-    };
-    const double c = val(x, y, z);
-    double nb = val(x - 1, y, z) + val(x + 1, y, z);
-    nb += val(x, y - 1, z);
-    nb += val(x, y + 1, z);
-    if (DIM == 3) {
-      nb += val(x, y, z - 1);
-      nb += val(x, y, z + 1);
+  const int planeS = DIM == 3 ? m * m : m;
+  const int ntx = (m + TX - 1) / TX, nty = DIM == 3 ? (m + TY - 1) / TY : 1;
+  const int bid = xcd_remap_t(blockIdx.x, gridDim.x);
+  const int tx = bid % ntx;
+  const int rest = bid / ntx;
+  const int ty = DIM == 3 ? rest % nty : 0;
+  const int tzc = DIM == 3 ? rest / nty : rest;
+  const int X0 = tx * TX, Y0 = ty * TY;
+  const int Z0 = tzc * a.cz, Z1 = min(Z0 + a.cz, m);
+  // halo-tile elements this thread loads (byte offsets in a plane)
+  int hoff[NL];
+  int hj[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int j = threadIdx.x + NT * k;
+    hj[k] = j < HP ? j : -1;
+    const int hx = j % HX, hy = j / HX;
+    const int x = X0 - 1 + hx, y = DIM == 3 ? Y0 - 1 + hy : 0;
+    const bool in = j < HP && x >= 0 && x < m && (DIM == 2 || (y >= 0 && y < m));
+    hoff[k] = in ? ((DIM == 3 ? y * m : 0) + x) : -1;
+  }
+  const bool use_e = a.e != nullptr;
+  double xv[NL];
+  auto load_plane = [&](int z, double *v) {
+    const __amdgpu_buffer_rsrc_t rx = plane_rsrc(a.x, z, m, planeS);
+    const __amdgpu_buffer_rsrc_t re = plane_rsrc(a.e, use_e ? z : -1, m, planeS);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int o = hoff[k];
+      double v0 = bload<double>(rx, o >= 0 ? o * 8 : kOOB);
+      if (use_e) v0 += double(bload<float>(re, o >= 0 ? o * 4 : kOOB));
+      v[k] = v0;
     }
-    const double r = fg[p] - (double(2 * DIM) * c - nb) * a.inv_h2;
-    if (eg) gbl(a.x_out)[p] = c;
-    gbl(a.r32)[p] = float(r);
-    acc += r * r;
+  };
+  auto store_plane = [&](int z, const double *v) {
+    double *dst = ring[z & 3];
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (hj[k] >= 0) dst[hj[k]] = v[k];
+  };
+  // this thread's point
+  const int cx = threadIdx.x % TX, cy = threadIdx.x / TX;
+  const int gx = X0 + cx, gy = DIM == 3 ? Y0 + cy : 0;
+  const bool mine = threadIdx.x < TX * TY && gx < m && (DIM == 2 || gy < m);
+  const int ci = (DIM == 3 ? (cy + 1) * HX : 0) + cx + 1;
+  const int coff = (DIM == 3 ? gy * m : 0) + gx;
+  // prologue: planes Z0 - 1, Z0, Z0 + 1 in the ring
+  load_plane(Z0 - 1, xv);
+  store_plane(Z0 - 1, xv);
+  load_plane(Z0, xv);
+  store_plane(Z0, xv);
+  load_plane(Z0 + 1, xv);
+  store_plane(Z0 + 1, xv);
+  __syncthreads();
+  const double inv_h2 = a.inv_h2;
+  double acc = 0.0;
+  for (int z = Z0; z < Z1; ++z) {
+    load_plane(z + 2, xv);  // in flight during this plane's residual
+    const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.f, z, m, planeS);
+    const double fv = bload<double>(rf, mine ? coff * 8 : kOOB);
+    if (mine) {
+      const double *P = ring[z & 3];
+      const double c = P[ci];
+      double nb = P[ci - 1] + P[ci + 1];
+      if (DIM == 3) {
+        nb += P[ci - HX];
+        nb += P[ci + HX];
+      }
+      nb += ring[(z - 1) & 3][ci];
+      nb += ring[(z + 1) & 3][ci];
+      const double r = fv - (double(2 * DIM) * c - nb) * inv_h2;
+      const size_t o = (size_t)z * planeS + coff;
+      if (use_e) gbl(a.x_out)[o] = c;
+      gbl(a.r32)[o] = float(r);
+      acc += r * r;
+    }
+    // slot (z + 2) & 3 last held plane z - 2, read by nobody in this step
+    store_plane(z + 2, xv);
+    __syncthreads();
   }
   __shared__ double red[NT / 64];
 #pragma unroll
@@ -330,7 +388,26 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
   }
 }
 
-int ir_blocks(int dim, int m) { return residual_blocks(dim, m); }
+namespace {
+constexpr int kIrTX3 = 64, kIrTY3 = 8, kIrTX2 = 256;
+// planes per workgroup: enough workgroups to fill the chip, at most 65536
+// (one norm partial each)
+int ir_chunk(int dim, int m) {
+  const long tiles = dim == 3 ? (long)((m + kIrTX3 - 1) / kIrTX3) * ((m + kIrTY3 - 1) / kIrTY3)
+                              : (long)((m + kIrTX2 - 1) / kIrTX2);
+  long cz = dim == 3 ? 16 : 8;
+  while (tiles * ((m + cz - 1) / cz) > 65536) cz *= 2;
+  if (cz > m) cz = m;
+  return (int)cz;
+}
+}  // namespace
+
+int ir_blocks(int dim, int m) {
+  const int cz = ir_chunk(dim, m);
+  const long tiles = dim == 3 ? (long)((m + kIrTX3 - 1) / kIrTX3) * ((m + kIrTY3 - 1) / kIrTY3)
+                              : (long)((m + kIrTX2 - 1) / kIrTX2);
+  return (int)(tiles * ((m + cz - 1) / cz));
+}
 
 __global__ void __launch_bounds__(64) k_finalize(const double *partials, int n, SolveState *st) {
   if (st->active == 0) return;
@@ -484,11 +561,15 @@ hipError_t launch_residual(int dim, ResidArgs<T> a, hipStream_t s) {
 }
 
 hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s) {
-  const int nb = a.nblocks > 0 ? a.nblocks : ir_blocks(dim, a.m);
+  // the grid must be exactly the tiling the partial sums are counted for
+  a.cz = ir_chunk(dim, a.m);
+  const int nb = ir_blocks(dim, a.m);
+  if (a.nblocks != nb) return hipErrorInvalidValue;
   if (dim == 3)
-    gmg_launch((k_ir_step<3, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_ir_step<3, kIrTX3, kIrTY3, kIrTX3 * kIrTY3>), dim3(nb), dim3(kIrTX3 * kIrTY3), 0,
+               s, a);
   else
-    gmg_launch((k_ir_step<2, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_ir_step<2, kIrTX2, 1, kIrTX2>), dim3(nb), dim3(kIrTX2), 0, s, a);
   return hipGetLastError();
 }
 
