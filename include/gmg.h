@@ -82,6 +82,9 @@ typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
 #define GMG_NO_FUSED_COARSE 0x20u   /* small coarse levels through the general
                                        passes instead of the fused LDS-tile
                                        kernels (same results, for testing)    */
+#define GMG_NO_FUSED_RESTRICT 0x40u /* residual + restriction as a kernel of its
+                                       own instead of inside the last
+                                       pre-smoothing pass (same results)      */
 
 typedef struct {
   int dim;                 /* 2 or 3                                            */

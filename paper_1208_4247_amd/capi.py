@@ -34,6 +34,7 @@ GMG_PROFILE = 0x4
 GMG_POST_FORWARD = 0x8
 GMG_NO_TEMPORAL_BLOCKING = 0x10
 GMG_NO_FUSED_COARSE = 0x20
+GMG_NO_FUSED_RESTRICT = 0x40
 
 EXPORTED = [
     "gmg_config_default", "gmg_setup", "gmg_vcycle", "gmg_solve", "gmg_batch_solve",

@@ -73,6 +73,7 @@ struct PassChoice {
   int smax = 2;
   std::array<int, 5> var{{0, 0, 0, 0, 0}};
   std::array<int, 5> tz{{0, 0, 0, 0, 0}};
+  int fuse = 1;  // pre-smoothing: fold the residual + restriction into the last pass
 };
 
 template <typename T>
@@ -252,11 +253,12 @@ struct ProfScope {
 // body after the one that stopped the loop return at once.  Drop their
 // timings (and, in the stopping body, everything after the step that ran
 // the test), so profiles average over launches that did their work.
-void prune_profile(gmg_plan *p, int last_body, int keep_cls) {
+void prune_profile(gmg_plan *p, int last_body, unsigned keep_mask) {
   std::vector<PendingEv> kept;
   kept.reserve(p->pending.size());
   for (auto &e : p->pending) {
-    const bool drop = e.tag >= 0 && (e.tag > last_body || (e.tag == last_body && e.cls != keep_cls));
+    const bool drop =
+        e.tag >= 0 && (e.tag > last_body || (e.tag == last_body && !((keep_mask >> e.cls) & 1u)));
     if (drop) {
       p->evpool.push_back(e.a);
       p->evpool.push_back(e.b);
@@ -292,19 +294,20 @@ int stages_of(const gmg_plan *p, int sweeps) {
 template <typename T>
 hipError_t one_pass(gmg_plan *p, int level, int role, int sweeps, int flags, const T *src,
                     const T *ec, const T *f, T *dst, double *partials, const int *active,
-                    int cls) {
+                    int cls, T *fc = nullptr) {
   const int dim = p->dim, m = p->m[level];
   const int st = stages_of(p, sweeps);
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
   const PassChoice &c = p->ch[level][role];
   const int v = c.var[st];
   const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
-  const PassGeom g = pass_geometry(dim, m, st, t, c.tz[st]);
+  const PassGeom g = pass_geometry(dim, m, st, t, c.tz[st], (flags & F_RESTRICT) != 0);
   PassArgs<T> a;
   a.u_in = src;
   a.f = f;
   a.u_out = dst;
   a.e_c = ec;
+  a.f_c = fc;
   a.partials = partials;
   a.active = active;
   a.m = m;
@@ -318,29 +321,59 @@ hipError_t one_pass(gmg_plan *p, int level, int role, int sweeps, int flags, con
   a.inv_h2 = 1.0 / (h * h);
   a.omega = p->cfg.omega;
   double bytes = (double)npts(dim, m) * sizeof(T) * ((flags & F_ZERO_IN) ? 2 : 3);
-  if (flags & F_PROLONG) bytes += (double)npts(dim, a.mc) * sizeof(T);
+  if (flags & (F_PROLONG | F_RESTRICT)) bytes += (double)npts(dim, a.mc) * sizeof(T);
   ProfScope ps(p, cls, bytes);
   return wj ? launch_wj_pass<T>(dim, st, flags, v, a, p->stream)
             : launch_rb_pass<T>(dim, st, flags, v, a, p->stream);
 }
 
-int pass_blocks(const gmg_plan *p, int level, int role, int sweeps) {
+int pass_blocks(const gmg_plan *p, int level, int role, int sweeps, bool rst = false) {
   const int st = stages_of(p, sweeps);
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
   const PassChoice &c = p->ch[level][role];
   const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, c.var[st]);
-  return pass_geometry(p->dim, p->m[level], st, t, c.tz[st]).nblocks;
+  return pass_geometry(p->dim, p->m[level], st, t, c.tz[st], rst).nblocks;
+}
+
+// Whether the pre-smoothing of `level` (nsweeps sweeps in passes of the
+// level's pre choice) can end in a pass that also restricts: red-black, a
+// coarser level exists, the choice asks for it, and the last pass's tile
+// fits in LDS with the restriction's planes.
+bool can_fuse_restrict(const gmg_plan *p, int level, int nsweeps, size_t elem) {
+  if (p->cfg.smoother != GMG_SMOOTH_RBGS || (p->cfg.flags & GMG_NO_FUSED_RESTRICT)) return false;
+  if (nsweeps < 1 || level + 1 >= p->L) return false;
+  const PassChoice &c = p->ch[level][0];
+  if (!c.fuse) return false;
+  // sweeps of the chain's last pass (the split smooth_chain makes)
+  const int smax = c.smax;
+  const int K = (nsweeps + smax - 1) / smax;
+  int left = nsweeps, last = 0;
+  for (int k = 1; k <= K; ++k) {
+    last = std::min(smax, left - (K - k));
+    left -= last;
+  }
+  const int st = stages_of(p, last);
+  if (pass_geometry(p->dim, p->m[level], st, pass_variant(p->dim, st, 0, c.var[st]), c.tz[st], true)
+          .nblocks > kMaxPartials)
+    return false;
+  return rb_pass_fits(p->dim, st, c.var[st], F_RESTRICT | F_NORM_IN, elem);
 }
 
 // nsweeps of the plan's smoother from (src [+ P ec]) to dst through fused
 // passes of at most smax sweeps; intermediate passes alternate between tmp
 // and dst so the last one lands in dst and no pass reads what it writes.
 // partials != NULL: the first pass emits |f - A src|^2 partial sums.
+// fc_out != NULL (pre-smoothing only): when the level allows it, the last
+// pass also writes the restricted residual f_c = R (f - A dst) to fc_out and
+// *fused is set; otherwise the caller restricts separately.
 template <typename T>
 hipError_t smooth_chain(gmg_plan *p, int level, int nsweeps, bool backward, const T *src,
                         const T *ec, const T *f, T *dst, T *tmp, double *partials,
-                        const int *active, int cls, int *nparts) {
+                        const int *active, int cls, int *nparts, T *fc_out = nullptr,
+                        bool *fused = nullptr) {
   const int role = ec ? 1 : 0;
+  const bool fuse = fc_out && !ec && !backward && can_fuse_restrict(p, level, nsweeps, sizeof(T));
+  if (fused) *fused = fuse;
   const int smax = p->ch[level][role].smax;
   const int dim = p->dim;
   const int m = p->m[level];
@@ -380,16 +413,18 @@ hipError_t smooth_chain(gmg_plan *p, int level, int nsweeps, bool backward, cons
     const int swk = std::min(sw, smax);
     T *out = ((K - k) % 2 == 1) ? tmp : dst;
     int flags = backward ? F_BLACK_FIRST : 0;
+    const bool rst = fuse && k == K;
+    if (rst) flags |= F_RESTRICT;
     if (k == 1) {
       if (!in) flags |= F_ZERO_IN;
       if (ec) flags |= F_PROLONG;
       if (partials) {
         flags |= F_NORM_IN;
-        if (nparts) *nparts = pass_blocks(p, level, role, swk);
+        if (nparts) *nparts = pass_blocks(p, level, role, swk, rst);
       }
     }
     hipError_t e = one_pass<T>(p, level, role, swk, flags, in, k == 1 ? ec : nullptr, f, out,
-                               k == 1 ? partials : nullptr, active, cls);
+                               k == 1 ? partials : nullptr, active, cls, rst ? fc_out : nullptr);
     if (e != hipSuccess) return e;
     in = out;
     left -= swk;
@@ -466,11 +501,14 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
       if (e != hipSuccess) return e;
       continue;
     }
+    bool fused = false;
     e = smooth_chain<T>(p, l, nu1, false, nullptr, nullptr, S.f[l], S.w[l], S.t[l], nullptr,
-                        active, PC_PRE_C, nullptr);
+                        active, PC_PRE_C, nullptr, S.f[l + 1], &fused);
     if (e != hipSuccess) return e;
-    e = restrict_level<T>(p, l, S.w[l], S.f[l], S.f[l + 1], active, PC_RES_C);
-    if (e != hipSuccess) return e;
+    if (!fused) {
+      e = restrict_level<T>(p, l, S.w[l], S.f[l], S.f[l + 1], active, PC_RES_C);
+      if (e != hipSuccess) return e;
+    }
   }
   {
     BottomArgs<T> ba;
@@ -591,15 +629,24 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
     return launch_bottom<T>(1, ba, nullptr, p->stream);
   }
   // ---- descent
+  bool fused = false;
   e = smooth_chain<T>(p, 0, nu1, false, u0_in, nullptr, f0, S.w[0], S.t[0], norm_partials, active,
-                      PC_PRE0, &nparts);
+                      PC_PRE0, &nparts, S.f[1], &fused);
   if (e != hipSuccess) return e;
   // (nu1 == 0: the chain copied the start value into w0, so the post-pass
   // below never reads the array it writes)
   const T *w0 = S.w[0];
-  // the stop test runs in workgroup 0 of the level-0 restriction
-  e = restrict_level<T>(p, 0, w0, f0, S.f[1], active, PC_RES0, norm_partials, nparts);
-  if (e != hipSuccess) return e;
+  if (fused) {
+    if (norm_partials) {  // the stop test, before any coarse work
+      ProfScope ps(p, PC_FIN, 0.0);
+      e = launch_finalize(norm_partials, nparts, p->state, p->stream);
+      if (e != hipSuccess) return e;
+    }
+  } else {
+    // the stop test runs in workgroup 0 of the level-0 restriction
+    e = restrict_level<T>(p, 0, w0, f0, S.f[1], active, PC_RES0, norm_partials, nparts);
+    if (e != hipSuccess) return e;
+  }
   e = run_coarse<T>(p, active);
   if (e != hipSuccess) return e;
   return smooth_chain<T>(p, 0, nu2, bwd, w0, S.u[1], f0, u0_out, S.t[0], nullptr, active,
@@ -828,9 +875,10 @@ std::string arch_name() {
 
 std::string tune_key(const gmg_plan &p, int l, int role, size_t elem) {
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d", arch_name().c_str(), p.dim,
-                p.m[l], (int)(elem * 8), p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs",
-                role == 0 ? p.cfg.nu1 : p.cfg.nu2, role, p.smax_cap);
+  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d", arch_name().c_str(),
+                p.dim, p.m[l], (int)(elem * 8), p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs",
+                role == 0 ? p.cfg.nu1 : p.cfg.nu2, role, p.smax_cap,
+                (p.cfg.flags & GMG_NO_FUSED_RESTRICT) ? 0 : 1);
   return buf;
 }
 
@@ -846,14 +894,18 @@ void tune_cache_load() {
   while (std::fgets(line, sizeof(line), fh)) {
     char key[256];
     PassChoice c;
-    int st = 0, v = 0, tz = 0;
-    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d",
-                    key, &c.smax, &st, &v, &tz) == 5 && st >= 1 && st <= 4) {
+    int st = 0, v = 0, tz = 0, fz = 1;
+    if (std::sscanf(line,
+                    "{\"key\": \"%255[^\"]\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, "
+                    "\"fuse\": %d",
+                    key, &c.smax, &st, &v, &tz, &fz) == 6 && st >= 1 && st <= 4) {
+      c.fuse = fz;
       auto it = tune_cache().find(key);
       PassChoice &d = it == tune_cache().end() ? (tune_cache()[key] = c) : it->second;
       d.smax = c.smax;
       d.var[st] = v;
       d.tz[st] = tz;
+      d.fuse = c.fuse;
     }
   }
   std::fclose(fh);
@@ -865,14 +917,20 @@ void tune_cache_store(const std::string &key, const PassChoice &c, int st, doubl
   if (!path || !*path) return;
   FILE *fh = std::fopen(path, "a");
   if (!fh) return;
-  std::fprintf(fh, "{\"key\": \"%s\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, \"us\": %.2f}\n",
-               key.c_str(), c.smax, st, c.var[st], c.tz[st], us);
+  std::fprintf(fh,
+               "{\"key\": \"%s\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, "
+               "\"fuse\": %d, \"us\": %.2f}\n",
+               key.c_str(), c.smax, st, c.var[st], c.tz[st], c.fuse, us);
   std::fclose(fh);
 }
 
+// fc (pre-smoothing): the next coarser level's right-hand side.  Each
+// candidate is timed together with the restriction, fused into the last
+// pass where the tile allows it and as a kernel of its own, and the faster
+// form is kept.
 template <typename T>
 hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, const T *f, T *dst,
-                     T *tmp, double *partials, size_t elem) {
+                     T *tmp, double *partials, size_t elem, T *fc = nullptr) {
   const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;
   if (nu == 0) return hipSuccess;
   const std::string key = tune_key(*p, l, role, elem);
@@ -906,29 +964,39 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
         if (tzv == last) continue;
         last = tzv;
         if (pass_geometry(p->dim, m, st, t, tzv).nblocks > kMaxPartials) continue;
-        PassChoice c = base;
-        c.smax = sm;
-        c.var[st] = v;
-        c.tz[st] = tzv;
-        p->ch[l][role] = c;
-        err = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials, nullptr,
-                              PC_MISC, nullptr);
-        if (err != hipSuccess) break;
-        err = hipEventRecord(e0, p->stream);
-        for (int r = 0; r < reps && err == hipSuccess; ++r)
-          err = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials, nullptr,
-                                PC_MISC, nullptr);
-        if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) break;
-        const double us = 1e3 * ms / reps;
-        if (us < best_us) {
-          best_us = us;
-          best = c;
-          best_st = st;
+        for (int fz = (fc ? 1 : 0); fz >= 0; --fz) {
+          PassChoice c = base;
+          c.smax = sm;
+          c.var[st] = v;
+          c.tz[st] = tzv;
+          c.fuse = fz;
+          p->ch[l][role] = c;
+          if (fz && !can_fuse_restrict(p, l, nu, elem)) continue;
+          auto run = [&]() -> hipError_t {
+            bool fused = false;
+            hipError_t e2 = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials,
+                                            nullptr, PC_MISC, nullptr, fc, &fused);
+            if (e2 == hipSuccess && fc && !fused)
+              e2 = restrict_level<T>(p, l, dst, f, fc, nullptr, PC_MISC);
+            return e2;
+          };
+          err = run();
+          if (err != hipSuccess) break;
+          err = hipEventRecord(e0, p->stream);
+          for (int r = 0; r < reps && err == hipSuccess; ++r) err = run();
+          if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
+          if (err == hipSuccess) err = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+          if (err != hipSuccess) break;
+          const double us = 1e3 * ms / reps;
+          if (us < best_us) {
+            best_us = us;
+            best = c;
+            best_st = st;
+          }
         }
+        if (err != hipSuccess) break;
       }
       if (err != hipSuccess) break;
     }
@@ -955,7 +1023,7 @@ hipError_t tune_plan(gmg_plan *p, const T *src0, const T *f0, double *partials0)
     const T *f = l == 0 ? f0 : S.f[l];
     // descent: level 0 reads the start value (and reports its residual norm)
     e = tune_role<T>(p, l, 0, l == 0 ? src0 : nullptr, nullptr, f, S.w[l], S.t[l],
-                     l == 0 ? partials0 : nullptr, sizeof(T));
+                     l == 0 ? partials0 : nullptr, sizeof(T), S.f[l + 1]);
     if (e != hipSuccess) break;
     // ascent with the fused prolongation from level l+1
     const T *src = l == 0 ? (src0 ? src0 : S.w[0]) : S.w[l];
@@ -1671,7 +1739,9 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
   }
   p->prof_tag = -1;
   const SolveState st = *p->hstate;
-  if (p->profile) prune_profile(p, st.iter, mixed ? PC_IR : PC_PRE0);
+  // the stopping body ran its first step and the stop test
+  if (p->profile)
+    prune_profile(p, st.iter, (1u << PC_FIN) | (1u << (mixed ? PC_IR : PC_PRE0)));
   if (mixed && (st.iter % 2 == 1)) {
     // the final iterate x_iter sits in the workspace copy
     HIPCHK(launch_copy(p->x2, u, N0 * sizeof(double), nullptr, p->stream));

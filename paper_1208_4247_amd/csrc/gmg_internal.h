@@ -104,6 +104,8 @@ enum PassFlags : int {
   F_PROLONG = 2,     // start value is u_in + P e_coarse (linear interpolation)
   F_NORM_IN = 4,     // emit per-workgroup partial sums of |f - A u_in|^2
   F_BLACK_FIRST = 8, // red-black order black -> red (backward sweep)
+  F_RESTRICT = 16,   // red-black: also form f_c = R (f - A u_out), the residual's
+                     // full weighting onto the next coarser grid
 };
 
 // Device-resident state of one solve (one per problem in batch mode).
@@ -124,6 +126,7 @@ struct PassArgs {
   const T *f;           // right-hand side of this level
   T *u_out;             // result (never aliases u_in / f / e_c)
   const T *e_c;         // coarse correction (F_PROLONG)
+  T *f_c;               // coarse right-hand side out (F_RESTRICT)
   double *partials;     // F_NORM_IN: one double per workgroup
   const int *active;    // skip the launch when *active == 0 (NULL: always run)
   int m, mc;            // fine / coarse interior side
@@ -220,7 +223,12 @@ struct PassGeom {
 
 int pass_variant_count(int dim, int stages, int wj);
 PassTile pass_variant(int dim, int stages, int wj, int v);
-PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz);
+PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz,
+                       bool restrict_ = false);
+// LDS of a red-black pass and whether it fits the per-workgroup limit
+constexpr size_t kMaxPassLds = 160 * 1024;
+size_t rb_pass_lds_bytes(int dim, int stages, int exp_, int ey, int flags, size_t elem);
+bool rb_pass_fits(int dim, int stages, int variant, int flags, size_t elem);
 
 // Launchers.  Batch mode: tbl != NULL points to nent device-resident argument
 // entries (one problem each, all with the same level size); the grid gets a

@@ -154,12 +154,19 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr int PL = EXP * EY;
   constexpr int NS = (PL + NT - 1) / NT;        // slots per thread
   constexpr bool TAIL = NS * NT > PL;           // the last slot index has dead lanes
-  constexpr int HP = S / 2;                     // halo in pairs
-  constexpr int TXP = EXP - 2 * HP;             // output pairs per row
-  constexpr int TY = DIM == 3 ? EY - 2 * S : 1;
   constexpr bool ZERO = (FL & F_ZERO_IN) != 0;
   constexpr bool PRO = (FL & F_PROLONG) != 0;
   constexpr bool NORM = (FL & F_NORM_IN) != 0;
+  constexpr bool RST = (FL & F_RESTRICT) != 0;
+  static_assert(!(PRO && RST), "a pass prolongs or restricts, not both");
+  // halo: S points for the stages; RST adds two, so the result is exact one
+  // point past the output tile (the residual there) and the residual one
+  // point past it on the high side (full weighting of the edge coarse points)
+  constexpr int HP = S / 2 + (RST ? 1 : 0);     // halo in pairs
+  constexpr int HY = S + (RST ? 2 : 0);         // halo in rows (3D)
+  constexpr int TXP = EXP - 2 * HP;             // output pairs per row
+  constexpr int TY = DIM == 3 ? EY - 2 * HY : 1;
+  static_assert(TXP > 0 && TY > 0 && (DIM == 2 || TY % 2 == 0), "tile too small");
   constexpr int C1 = (FL & F_BLACK_FIRST) ? 1 : 0;
   constexpr int C0 = 1 - C1;  // colour the first stage reads
   constexpr int NB = S + (NORM ? 1 : 0);  // LDS planes per buffer
@@ -171,9 +178,12 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr int CPL = NCX * NCY;
   constexpr int NCP = PRO ? (CPL + NT - 1) / NT : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  // [2 (step parity)][NB][PL], then PRO: [2][CPL]
+  // [2 (step parity)][NB][PL]; RST: final plane and residual plane, each
+  // [2 (step parity)][2 (element)][PL]; PRO: [2][CPL]
   T *lds = reinterpret_cast<T *>(smem_raw);
-  T *cring = lds + 2 * NB * PL;
+  T *fwl = lds + 2 * NB * PL;
+  T *rl = fwl + 4 * PL;
+  T *cring = lds + 2 * NB * PL + (RST ? 8 * PL : 0);
 
   const int m = a.m;
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -205,22 +215,23 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   bool live[NS];
   int cb[PRO ? NS : 1];
   bool c2[PRO ? NS : 1];
-  bool pone[PRO ? NS : 1];  // element P is element 1 of the pair
+  bool pone[(PRO || RST) ? NS : 1];  // element P is element 1 of the pair
+  bool k0[RST ? NS : 1], k1[RST ? NS : 1];  // element 0 / 1 inside the grid
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int q = threadIdx.x + NT * i;
     live[i] = q < PL;
     const int qc = live[i] ? q : PL - 1;
     const int p = qc % EXP, r = qc / EXP;
-    const int xb = X0 - S + 2 * p;
-    const int y = DIM == 3 ? Y0 - S + r : 0;
+    const int xb = X0 - 2 * HP + 2 * p;
+    const int y = DIM == 3 ? Y0 - HY + r : 0;
     const bool yin = DIM == 2 || (y >= 0 && y < m);
     const int par = (y + DIM) & 1;
     const int off = (DIM == 3 ? y * m : 0) + xb;
     const bool in0 = live[i] && yin && xb >= 0 && xb < m;
     const bool in1 = live[i] && yin && xb + 1 >= 0 && xb + 1 < m;
     const bool outp = live[i] && yin && p >= HP && p < HP + TXP &&
-                      (DIM == 2 || (r >= S && r < S + TY)) && xb < m;
+                      (DIM == 2 || (r >= HY && r < HY + TY)) && xb < m;
     const int o0 = in0 ? off * (int)sizeof(T) : kOOB;
     const int o1 = in1 ? (off + 1) * (int)sizeof(T) : kOOB;
     const bool half = in0 && !in1;
@@ -239,8 +250,12 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     lQ[i] = par ? left : right;
     lu[i] = max(qc - EXP, 0);
     ld[i] = min(qc + EXP, PL - 1);
+    if (PRO || RST) pone[i] = par != 0;
+    if (RST) {
+      k0[i] = in0;
+      k1[i] = in1;
+    }
     if (PRO) {
-      pone[i] = par != 0;
       const int rr = DIM == 3 ? r : 0;
       c2[i] = DIM == 3 && !(rr & 1);
       cb[i] = (DIM == 3 ? ((rr & 1) ? (rr + 1) >> 1 : rr >> 1) * NCX : 0) + p;
@@ -258,9 +273,14 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   for (int i = 0; i < (NORM ? NS : 1); ++i) WB[i][0] = WB[i][1] = WB[i][2] = T(0);
   double acc = 0.0;
 
+  // RST: coarse planes c with fine centre 2c+1 in [Z0, Z1) belong to this
+  // chunk; their residual planes are 2*CZ0 .. 2*CZ1
+  const int mc = a.mc;
+  const int CZ0 = Z0 >> 1, CZ1 = min(Z1 >> 1, mc);
   // steps in pairs from an even start; the extra leading or trailing step
   // only touches planes outside the exact region
-  const int t0 = (Z0 - S) & ~1, t1 = Z1 + S;
+  const int t0 = (Z0 - S - (RST ? 2 : 0)) & ~1;
+  const int t1 = RST ? 2 * CZ1 + S + 3 : Z1 + S;
   auto load_u = [&](int t, T *v0, T *v1) {
     if (ZERO) {
 #pragma unroll
@@ -281,9 +301,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   // p reads coarse columns p (left) and p + 1 (right); an odd row r of the
   // extended tile lies on coarse row (r + 1) / 2, an even one halfway between
   // rows r / 2 and r / 2 + 1.
-  const int CX0 = ((X0 - S) >> 1) - 1;
-  const int CY0 = DIM == 3 ? ((Y0 - S) >> 1) - 1 : 0;
-  const int mc = a.mc;
+  const int CX0 = ((X0 - 2 * HP) >> 1) - 1;
+  const int CY0 = DIM == 3 ? ((Y0 - HY) >> 1) - 1 : 0;
   const int cplane = DIM == 3 ? mc * mc : mc;
   int coff[NCP];
   if (PRO) {
@@ -344,9 +363,24 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
       vQ[i] = hQ[i] ? v.hi : v.lo;
     }
   };
-  T fP[S + 1][NS], fQ[S + 1][NS];
+  constexpr int NF = S + 1 + (RST ? 1 : 0);  // RST: plane t-S-1 for the residual
+  T fP[NF][NS], fQ[NF][NS];
 #pragma unroll
-  for (int j = 0; j <= S; ++j) load_f(t0 - j, fP[j], fQ[j]);
+  for (int j = 0; j < NF; ++j) load_f(t0 - j, fP[j], fQ[j]);
+  // RST: final values (elements 0 / 1) of planes t-S, t-S-1, t-S-2, and the
+  // full-weighting accumulator of this thread's coarse point
+  T fw0[RST ? NS : 1][3], fw1[RST ? NS : 1][3];
+#pragma unroll
+  for (int i = 0; i < (RST ? NS : 1); ++i)
+    fw0[i][0] = fw0[i][1] = fw0[i][2] = fw1[i][0] = fw1[i][1] = fw1[i][2] = T(0);
+  constexpr int NCC = DIM == 3 ? TXP * (TY / 2) : TXP;  // coarse points of the tile
+  const int ccx = threadIdx.x % TXP, ccy = DIM == 3 ? threadIdx.x / TXP : 0;
+  const int cgx = (X0 >> 1) + ccx, cgy = DIM == 3 ? (Y0 >> 1) + ccy : 0;
+  const bool cown = RST && (int)threadIdx.x < NCC && cgx < mc && (DIM == 2 || cgy < mc);
+  const int cq = (DIM == 3 ? (HY + 2 * ccy + 1) * EXP : 0) + HP + ccx;  // slot of the centre
+  T cacc = T(0);
+  GMG_GLOBAL T *__restrict__ fcg = gbl(a.f_c);
+  static_assert(!RST || NCC <= NT, "one thread per coarse point");
   T cnext[NCP];  // PRO: coarse plane (t + 1) / 2 for the odd step t, loaded at step t - 1
   if (PRO) load_c((t0 + 2) >> 1, cnext);
 
@@ -362,6 +396,36 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     load_f(t + 1, fnP, fnQ);
     T cnn[NCP];
     if (PRO && TP == 1) load_c((t + 3) >> 1, cnn);
+    const T *Lprev = lds + (1 - TP) * NB * PL;  // planes published at step t-1
+
+    // ---- RST: full weighting of the residual plane t-S-2 (published at step
+    // t-1) onto this thread's coarse point: in-plane x, then y, then the
+    // three fine planes of a coarse plane (1/4, 1/2, 1/4)
+    if (RST) {
+      const int zf = t - S - 2;
+      if (cown && zf >= 2 * CZ0 && zf <= 2 * CZ1) {
+        const T *R0 = rl + (1 - TP) * 2 * PL, *R1 = R0 + PL;
+        auto row = [&](int q) {
+          return T(0.25) * R0[q] + T(0.5) * R1[q] + T(0.25) * R0[q + 1];
+        };
+        T sxy;
+        if (DIM == 3)
+          sxy = T(0.25) * row(cq - EXP) + T(0.5) * row(cq) + T(0.25) * row(cq + EXP);
+        else
+          sxy = row(cq);
+        if (zf & 1) {
+          cacc += T(0.5) * sxy;
+        } else {
+          const int c = zf / 2 - 1;
+          if (c >= CZ0 && c < CZ1) {
+            cacc += T(0.25) * sxy;
+            const size_t o = DIM == 3 ? ((size_t)c * mc + cgy) * mc + cgx : (size_t)c * mc + cgx;
+            fcg[o] = cacc;
+          }
+          cacc = T(0.25) * sxy;
+        }
+      }
+    }
 
     // ---- stage 0: start value on plane t (colour C0 into the window)
     constexpr bool S0P = ((C0 + TP) & 1) == 0;  // colour-C0 element of plane t is P
@@ -393,7 +457,6 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         WB[i][0] = S0P ? vQ : vP;
       }
     }
-    const T *Lprev = lds + (1 - TP) * NB * PL;  // planes published at step t-1
     // ---- residual of the start value on plane t-1 (convergence test)
     if (NORM && rin) {
       const T *L0 = Lprev;           // colour C0 values of plane t-1
@@ -458,6 +521,51 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         bstore<T>(r, isP(S) ? sQ[i] : sP[i], o_old);
       }
     }
+    // ---- RST: final values of plane t-S into the window; residual of plane
+    // t-S-1 (same expression as the separate restriction kernel: neighbours
+    // x-1, x+1, y-1, y+1, z-1, z+1 in that order)
+    T *FWnow = fwl + TP * 2 * PL;
+    T *Rnow = rl + TP * 2 * PL;
+    if (RST) {
+      const T *F0 = fwl + (1 - TP) * 2 * PL, *F1 = F0 + PL;  // plane t-S-1
+      const int zw = t - S - 1;
+      const bool win = zw >= 0 && zw < m;
+      const T inv_h2 = T(a.inv_h2);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const T vP = isP(S) ? newS[i] : W[S - 1][i][1];
+        const T vQ = isP(S) ? W[S - 1][i][1] : newS[i];
+        fw0[i][2] = fw0[i][1];
+        fw0[i][1] = fw0[i][0];
+        fw0[i][0] = pone[i] ? vQ : vP;
+        fw1[i][2] = fw1[i][1];
+        fw1[i][1] = fw1[i][0];
+        fw1[i][0] = pone[i] ? vP : vQ;
+        const int q = lq[i];
+        const int left = max(q - 1, 0), right = min(q + 1, PL - 1);
+        const T f0 = pone[i] ? fQ[S + 1][i] : fP[S + 1][i];
+        const T f1 = pone[i] ? fP[S + 1][i] : fQ[S + 1][i];
+        T nb0 = F1[left] + fw1[i][1];
+        T nb1 = fw0[i][1] + F0[right];
+        if (DIM == 3) {
+          nb0 += F0[lu[i]];
+          nb0 += F0[ld[i]];
+          nb1 += F1[lu[i]];
+          nb1 += F1[ld[i]];
+        }
+        nb0 += fw0[i][2];
+        nb0 += fw0[i][0];
+        nb1 += fw1[i][2];
+        nb1 += fw1[i][0];
+        const T r0 = f0 - (T(2 * DIM) * fw0[i][1] - nb0) * inv_h2;
+        const T r1 = f1 - (T(2 * DIM) * fw1[i][1] - nb1) * inv_h2;
+        if (TAIL && i == NS - 1 && !live[i]) continue;
+        Rnow[q] = (win && k0[i]) ? r0 : T(0);
+        Rnow[PL + q] = (win && k1[i]) ? r1 : T(0);
+        FWnow[q] = fw0[i][0];
+        FWnow[PL + q] = fw1[i][0];
+      }
+    }
     // ---- publish the newest plane of every stage for step t+1
     T *Lnow = lds + TP * NB * PL;
 #pragma unroll
@@ -474,7 +582,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
       pu0[i] = nu0[i];
       pu1[i] = nu1[i];
 #pragma unroll
-      for (int j = S; j >= 1; --j) {
+      for (int j = NF - 1; j >= 1; --j) {
         fP[j][i] = fP[j - 1][i];
         fQ[j][i] = fQ[j - 1][i];
       }
@@ -738,9 +846,23 @@ PassTile pass_variant(int dim, int stages, int wj, int v) {
   return t;
 }
 
-PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz) {
-  // halo in points: S for red-black, rounded up to a pair for Jacobi
-  const int hp = (stages + 1) / 2;
+size_t rb_pass_lds_bytes(int dim, int stages, int exp_, int ey, int flags, size_t elem) {
+  const size_t pl = (size_t)exp_ * ey;
+  size_t n = 2 * pl * (size_t)(stages + ((flags & F_NORM_IN) ? 1 : 0));
+  if (flags & F_RESTRICT) n += 8 * pl;
+  if (flags & F_PROLONG) n += 2 * (size_t)(exp_ + 1) * (dim == 3 ? ey / 2 + 1 : 1);
+  return n * elem;
+}
+
+bool rb_pass_fits(int dim, int stages, int variant, int flags, size_t elem) {
+  const PassTile t = pass_variant(dim, stages, 0, variant);
+  return t.nt > 0 && rb_pass_lds_bytes(dim, stages, t.exp_, t.ey, flags, elem) <= kMaxPassLds;
+}
+
+PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz, bool restrict_) {
+  // halo in points: S for red-black, rounded up to a pair for Jacobi; a pass
+  // that also restricts carries one more pair and two more rows
+  const int hp = (stages + 1) / 2 + (restrict_ ? 1 : 0);
   const int tx = 2 * (t.exp_ - 2 * hp);
   PassGeom g;
   g.ntx = (m + tx - 1) / tx;
@@ -760,9 +882,8 @@ PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz) {
 namespace {
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
-  const size_t cpl = (FL & F_PROLONG) ? 2 * (size_t)(EXP + 1) * (DIM == 3 ? EY / 2 + 1 : 1) : 0;
-  // two step-parity buffers of S (+1 with the norm) planes, then the coarse ring
-  const size_t lds = sizeof(T) * (2 * EXP * EY * (S + ((FL & F_NORM_IN) ? 1 : 0)) + cpl);
+  const size_t lds = rb_pass_lds_bytes(DIM, S, EXP, EY, FL, sizeof(T));
+  if (lds > kMaxPassLds) return hipErrorInvalidConfiguration;
   auto k = k_rb_pass<T, DIM, S, EXP, EY, NT, FL>;
   static bool attr = false;
   if (!attr) {
@@ -790,7 +911,13 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
   return hipGetLastError();
 }
 
-// The fused-flag combinations a cycle uses.
+// The fused-flag combinations a cycle uses (restriction: red-black only).
+#define GMG_RST_CASES_run_rb(RUN, T, D, S, E, Y, N)                                          \
+  case F_RESTRICT: return RUN<T, D, S, E, Y, N, F_RESTRICT>(a, st, tbl, nent);              \
+  case F_RESTRICT | F_ZERO_IN: return RUN<T, D, S, E, Y, N, F_RESTRICT | F_ZERO_IN>(a, st, tbl, nent); \
+  case F_RESTRICT | F_NORM_IN: return RUN<T, D, S, E, Y, N, F_RESTRICT | F_NORM_IN>(a, st, tbl, nent);
+#define GMG_RST_CASES_run_wj(RUN, T, D, S, E, Y, N)
+#define GMG_RST_CASES(RUN, T, D, S, E, Y, N) GMG_RST_CASES_##RUN(RUN, T, D, S, E, Y, N)
 #define GMG_FLAG_SWITCH(RUN, T, D, S, E, Y, N)                                            \
   switch (flags) {                                                                     \
     case 0: return RUN<T, D, S, E, Y, N, 0>(a, st, tbl, nent);                                    \
@@ -801,6 +928,7 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
     case F_ZERO_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_ZERO_IN | F_BLACK_FIRST>(a, st, tbl, nent); \
     case F_PROLONG | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST>(a, st, tbl, nent); \
     case F_NORM_IN | F_BLACK_FIRST: return RUN<T, D, S, E, Y, N, F_NORM_IN | F_BLACK_FIRST>(a, st, tbl, nent); \
+    GMG_RST_CASES(RUN, T, D, S, E, Y, N)                                               \
     default: return hipErrorInvalidValue;                                              \
   }
 }  // namespace

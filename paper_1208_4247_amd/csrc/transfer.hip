@@ -409,10 +409,21 @@ int ir_blocks(int dim, int m) {
   return (int)(tiles * ((m + cz - 1) / cz));
 }
 
-__global__ void __launch_bounds__(64) k_finalize(const double *partials, int n, SolveState *st) {
+// The stop test after a kernel that left n partial sums: 1024 threads,
+// fixed order (strided per-thread sums, then a halving tree).
+__global__ void __launch_bounds__(1024) k_finalize(const double *partials, int n, SolveState *st) {
   if (st->active == 0) return;
-  const double tot = sum_partials(partials, n);
-  if (threadIdx.x == 0) update_state(st, tot);
+  __shared__ double red[1024];
+  const GMG_GLOBAL double *pg = gbl(partials);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += pg[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) update_state(st, red[0]);
 }
 
 // batch: one workgroup per table entry
@@ -574,7 +585,7 @@ hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const double *partials, int n, SolveState *st, hipStream_t s) {
-  gmg_launch(k_finalize, dim3(1), dim3(64), 0, s, partials, n, st);
+  gmg_launch(k_finalize, dim3(1), dim3(1024), 0, s, partials, n, st);
   return hipGetLastError();
 }
 
