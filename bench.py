@@ -129,6 +129,8 @@ def bench_batch(args):
     fs = [torch.from_numpy(wl.batch_rhs(4, q, d, m)).cuda() for q, (d, m) in enumerate(probs)]
     us = [torch.zeros_like(f) for f in fs]
     flags = args.flags | capi.GMG_USE_GRAPH
+    if not args.no_autotune:
+        flags |= capi.GMG_AUTOTUNE  # the warm-up solve tunes one problem per shape
     plan = BatchPlan([(d, (m + 1).bit_length() - 1) for d, m in probs], flags=flags)
     for _ in range(args.warmup):
         for u in us:

@@ -125,6 +125,10 @@ struct Batch {
   SolveState *states = nullptr;
   SolveState *hstates = nullptr;  // pinned
   hipGraphExec_t graph = nullptr;
+  // tile choice per (dim, level side, role) after autotuning (else defaults)
+  std::map<std::array<int, 3>, PassChoice> choice;
+  bool worst = false;      // sizing: one sweep per pass everywhere (most launches)
+  size_t tbl_reserve = 0;  // table region reserved for any choice
 };
 
 struct gmg_plan {
@@ -1075,13 +1079,15 @@ struct ChainEnt {
   double *partials;
 };
 
+PassChoice batch_choice(const gmg_plan *p, const Batch *b, int dim, int m, int role);
+
 void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_flags, bool backward,
                  const std::vector<ChainEnt> &ents, int cls) {
   gmg_plan *p = bb.p;
   Batch *b = bb.b;
   if (ents.empty() || nu == 0) return;
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
-  const PassChoice c = choice_for(p->cfg, dim, m, role, p->smax_cap);
+  const PassChoice c = batch_choice(p, b, dim, m, role);
   const int K = (nu + c.smax - 1) / c.smax;
   int left = nu;
   const double h = 1.0 / double(m + 1);
@@ -1138,9 +1144,34 @@ void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_f
   }
 }
 
-int first_pass_blocks(const gmg_plan *p, int dim, int m, int nu) {
+PassChoice batch_choice(const gmg_plan *p, const Batch *b, int dim, int m, int role) {
+  auto it = b->choice.find({dim, m, role});
+  PassChoice c = it != b->choice.end() ? it->second : choice_for(p->cfg, dim, m, role, p->smax_cap);
+  if (b->worst) c.smax = 1;
+  return c;
+}
+
+// Largest block count any first pass of this level size can have (the
+// partial-sum slice of a problem is sized for it, so tuning keeps layouts).
+int max_first_pass_blocks(const gmg_plan *p, int dim, int m) {
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
-  const PassChoice c = choice_for(p->cfg, dim, m, 0, p->smax_cap);
+  int mx = 1;
+  for (int st = 1; st <= 4; ++st) {
+    const int nv = pass_variant_count(dim, st, wj ? 1 : 0);
+    for (int v = 0; v < nv; ++v) {
+      const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
+      for (int tz : {1, 2, 4, 8, 16, 32, 64, 0}) {  // every z-chunk a choice may hold
+        const int tzv = tz > 0 ? std::min(tz, m) : auto_tz(dim, m, st, t);
+        mx = std::max(mx, pass_geometry(dim, m, st, t, tzv).nblocks);
+      }
+    }
+  }
+  return mx;
+}
+
+int first_pass_blocks(const gmg_plan *p, const Batch *b, int dim, int m, int nu) {
+  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
+  const PassChoice c = batch_choice(p, b, dim, m, 0);
   const int K = (nu + c.smax - 1) / c.smax;
   const int sw = std::min(c.smax, nu - (K - 1));
   const int st = wj ? sw : 2 * sw;
@@ -1164,8 +1195,9 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
     pr.m.resize(pr.L);
     for (int l = 0; l < pr.L; ++l) pr.m[l] = (1 << (pr.L - l)) - 1;
     pr.st = b->states + q;
-    pr.npart = first_pass_blocks(p, pr.dim, pr.m[0], p->cfg.nu1);
-    pr.partials = P(bb.take_bytes(sizeof(double) * pr.npart));
+    pr.npart = first_pass_blocks(p, b, pr.dim, pr.m[0], p->cfg.nu1);
+    pr.partials = P(bb.take_bytes(
+        sizeof(double) * std::max(pr.npart, max_first_pass_blocks(p, pr.dim, pr.m[0]))));
     pr.f.assign(pr.L, nullptr);
     pr.w.assign(pr.L, nullptr);
     pr.u.assign(pr.L, nullptr);
@@ -1374,7 +1406,7 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
     }
   }
   bb.align_tbl();
-  const size_t tbl_off = bb.take_bytes(b->host_tbl.size());
+  const size_t tbl_off = bb.take_bytes(std::max(b->host_tbl.size(), b->tbl_reserve));
   b->dev_tbl = ws + tbl_off;
   return bb.cur;
 }
@@ -1473,7 +1505,12 @@ gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int 
   }
   gmg_plan tmp;
   init_plan_shape(tmp, &c);
+  Batch tw;  // the most launches any tile choice can give sizes the table region
+  tw.worst = true;
+  batch_build(&tmp, &tw, n, dims, levels, nullptr);
+  const size_t reserve = align_up(tw.host_tbl.size());
   Batch tb;
+  tb.tbl_reserve = reserve;
   const size_t total = batch_build(&tmp, &tb, n, dims, levels, nullptr);
   if (!workspace) {
     *ws_bytes = total;
@@ -1489,11 +1526,12 @@ gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int 
   p->ws = (char *)workspace;
   p->ws_bytes = total;
   p->batch = new Batch();
+  p->batch->tbl_reserve = reserve;
   batch_build(p, p->batch, n, dims, levels, p->ws);
   p->prof.resize(PC_COUNT);
   for (int i = 0; i < PC_COUNT; ++i) p->prof[i].name = kProfNames[i];
   Batch *b = p->batch;
-  if (hipHostMalloc((void **)&b->pinned, b->host_tbl.size() + 64, hipHostMallocDefault) !=
+  if (hipHostMalloc((void **)&b->pinned, reserve + 64, hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void **)&b->hstates, sizeof(SolveState) * n, hipHostMallocDefault) !=
           hipSuccess) {
@@ -1504,6 +1542,59 @@ gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int 
   }
   *out = p;
   return GMG_OK;
+}
+
+// Autotuning of a batch plan (first gmg_batch_solve): one problem of every
+// distinct (dim, levels) shape is tuned with the single-problem tuner on its
+// own slice of the workspace (the caller's u and f are only read), the
+// choices are kept per (dim, level side, role), and the launch tables are
+// rebuilt.  Batch launches keep the restriction a kernel of its own, so the
+// candidates are timed that way.
+hipError_t batch_tune(gmg_plan *p, double *const *u, const double *const *f) {
+  Batch *b = p->batch;
+  const int n = p->nproblems;
+  std::vector<int> dims(n), levels(n);
+  std::map<std::pair<int, int>, int> shapes;
+  for (int q = 0; q < n; ++q) {
+    dims[q] = b->pb[q].dim;
+    levels[q] = b->pb[q].L;
+    shapes.emplace(std::make_pair(dims[q], levels[q]), q);
+  }
+  for (const auto &sh : shapes) {
+    const int q = sh.second;
+    const BProblem &pr = b->pb[q];
+    gmg_config c = p->cfg;
+    c.dim = pr.dim;
+    c.levels = pr.L;
+    c.flags = (c.flags & ~(unsigned)GMG_PROFILE) | GMG_NO_FUSED_RESTRICT;
+    gmg_plan v;
+    init_plan_shape(v, &c);
+    if (v.B != pr.B) continue;
+    v.stream = p->stream;
+    v.profile = false;
+    v.ch.resize(v.L);
+    for (int l = 0; l < v.L; ++l)
+      for (int r = 0; r < 2; ++r) v.ch[l][r] = batch_choice(p, b, pr.dim, pr.m[l], r);
+    v.d.f = pr.f;
+    v.d.w = pr.w;
+    v.d.u = pr.u;
+    v.d.t = pr.t;
+    v.d.f[0] = const_cast<double *>(f[q]);
+    hipError_t e = tune_plan<double>(&v, u[q], f[q], nullptr);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < v.B && l + 1 < v.L; ++l)
+      for (int r = 0; r < 2; ++r) {
+        PassChoice ch = v.ch[l][r];
+        ch.fuse = 0;
+        b->choice.emplace(std::array<int, 3>{pr.dim, pr.m[l], r}, ch);
+      }
+  }
+  batch_build(p, b, n, dims.data(), levels.data(), p->ws);
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -1765,6 +1856,10 @@ gmg_status gmg_batch_solve(gmg_plan *p, double *const *u, const double *const *f
   const int n = p->nproblems;
   for (int q = 0; q < n; ++q)
     if (!u[q] || !f[q]) return GMG_ERR_INVALID_ARG;
+  if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) {
+    HIPCHK(batch_tune(p, u, f));
+    p->tuned = true;
+  }
   // the caller's arrays go into the level-0 entries of the launch tables
   for (const auto &pt : b->patches) {
     void *v = pt.which == 0 ? (void *)u[pt.prob] : (void *)f[pt.prob];

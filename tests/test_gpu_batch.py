@@ -145,3 +145,25 @@ def test_batch_uneven_256_problems():
         u_ref, it_ref, *_ = oracle.solve(rhs[q], rtol=1e-10)
         assert its[q] == it_ref, (q, d, m)
         assert rel2(us[q], u_ref) <= 1e-12, (q, d, m)
+
+
+def test_batch_autotuned_matches_oracle_and_replays():
+    """With the autotuner the first batch solve tunes one problem of each
+    shape and rebuilds the launch tables; results still follow each
+    problem's own algorithm, and the graph replays give the same bits."""
+    from paper_1208_4247_amd import capi
+
+    probs = SMALL[:10]
+    rhs = [wl.batch_rhs(17, q, d, m) for q, (d, m) in enumerate(probs)]
+    plan, us, its, rels, sts = run_batch(probs, rhs, flags=capi.GMG_AUTOTUNE | capi.GMG_USE_GRAPH)
+    for q, (d, m) in enumerate(probs):
+        u_ref, it_ref, *_ = oracle.solve(rhs[q], rtol=1e-10)
+        assert its[q] == it_ref, (q, d, m)
+        assert rel2(us[q], u_ref) <= 1e-12, (q, d, m)
+    fs = [dev(f) for f in rhs]
+    for rep in range(2):
+        u2 = [torch.zeros_like(f) for f in fs]
+        s, its2, rels2, sts2 = plan.solve(u2, fs, rtol=1e-10)
+        assert its2 == its
+        for a, b in zip(u2, us):
+            assert np.array_equal(host(a), b)
