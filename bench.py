@@ -37,6 +37,8 @@ WORKLOADS = {
                                                 nu=1),
     "poisson3d_1023_sine_modes_mixed2_v11": dict(dim=3, L=10, rhs="sine_modes", prec="mixed",
                                                  nu=1, inner=2),
+    "poisson3d_255_sine_noise_fp64_wj22": dict(dim=3, L=8, rhs="sine_noise", prec="fp64",
+                                               smoother="wj"),
     "batch256_uneven_fp64_v22": dict(dim=0, L=0, rhs="batch", prec="fp64"),
 }
 DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
@@ -257,7 +259,9 @@ def main():
     flags = args.flags | capi.GMG_PROFILE
     if not args.no_autotune:
         flags |= capi.GMG_AUTOTUNE
-    plan = Plan(d, L, precision=spec["prec"], flags=flags, nu1=nu, nu2=nu, inner_cycles=inner)
+    smoother = spec.get("smoother", "rbgs")
+    plan = Plan(d, L, precision=spec["prec"], flags=flags, nu1=nu, nu2=nu, inner_cycles=inner,
+                smoother=smoother)
     print("# workload %s: %d^%d, plan workspace %.1f MB" % (args.workload, m, d,
           plan.workspace.numel() / 1e6), flush=True)
 
@@ -319,7 +323,9 @@ def main():
         "dtype": "f64" if spec["prec"] == "fp64" else "f32-in-f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
-                   "cycle": "V(%d,%d) red-black GS" % (nu, nu), "rtol": 1e-10, "iters": iters[-1]},
+                   "cycle": "V(%d,%d) %s" % (nu, nu, "weighted Jacobi" if smoother == "wj"
+                                             else "red-black GS"),
+                   "rtol": 1e-10, "iters": iters[-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch,

@@ -42,26 +42,6 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return xcd * per + min(xcd, rem) + loc;
 }
 
-// (P e)(x, y, z): linear interpolation from the coarse grid, zero coarse
-// boundary, in the canonical order of the library (average along x, then y,
-// then z).  Per axis, fine storage index v odd (fine node even) lies on
-// coarse storage (v-1)/2; v even lies halfway between v/2-1 and v/2.
-template <typename T, int DIM>
-__device__ __forceinline__ T interp(const GMG_GLOBAL T *__restrict__ ec, int mc, int x, int y, int z) {
-  auto cv = [&](int a, int b, int c) -> T {
-    if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) return T(0);
-    return ec[DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a];
-  };
-  auto xs = [&](int b, int c) {
-    return (x & 1) ? cv((x - 1) >> 1, b, c) : T(0.5) * (cv((x >> 1) - 1, b, c) + cv(x >> 1, b, c));
-  };
-  auto ys = [&](int c) {
-    return (y & 1) ? xs((y - 1) >> 1, c) : T(0.5) * (xs((y >> 1) - 1, c) + xs(y >> 1, c));
-  };
-  if (DIM == 2) return ys(0);
-  return (z & 1) ? ys((z - 1) >> 1) : T(0.5) * (ys((z >> 1) - 1) + ys(z >> 1));
-}
-
 template <int NT>
 __device__ __forceinline__ void block_sum_store(double acc, GMG_GLOBAL double *out) {
   __shared__ double red[NT / 64];
@@ -603,24 +583,33 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
 
 // ------------------------------------------------------------------------
 // Weighted-Jacobi pass: S full sweeps, every stage updates both elements of
-// every pair from the previous stage's values.
+// every pair from the previous stage's values.  Same pipeline, memory access
+// and fusions as the red-black pass (buffer loads with zero-boundary range
+// checks, pair loads, right-hand-side window, step-parity LDS buffers, the
+// coarse correction staged in LDS); a stage publishes both elements.
 // ------------------------------------------------------------------------
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<T> *tbl) {
-  // batch mode: one table entry (problem) per blockIdx.y
-  const PassArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
+  const PassArgs<T> a = entry_of(arg, tbl);
   if (a.active && *gbl(a.active) == 0) return;
-  constexpr int NS = (EXP * EY + NT - 1) / NT;
+  constexpr int PL = EXP * EY;
+  constexpr int NS = (PL + NT - 1) / NT;
+  constexpr bool TAIL = NS * NT > PL;
   constexpr int HP = (S + 1) / 2;  // halo in pairs (>= S points)
-  constexpr int H = 2 * HP;
+  constexpr int H = 2 * HP;        // halo in rows (3D)
   constexpr int TXP = EXP - 2 * HP;
   constexpr int TY = DIM == 3 ? EY - 2 * H : 1;
   constexpr bool ZERO = (FL & F_ZERO_IN) != 0;
   constexpr bool PRO = (FL & F_PROLONG) != 0;
   constexpr bool NORM = (FL & F_NORM_IN) != 0;
-  constexpr int PL = EXP * EY;
+  constexpr int NCX = EXP + 1;
+  constexpr int NCY = DIM == 3 ? EY / 2 + 1 : 1;
+  constexpr int CPL = NCX * NCY;
+  constexpr int NCP = PRO ? (CPL + NT - 1) / NT : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *lds = reinterpret_cast<T *>(smem_raw);  // [S][2][PL]
+  // [2 (step parity)][S][2 (element)][PL], then PRO: [2][CPL]
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  T *cring = lds + 4 * S * PL;
 
   const int m = a.m;
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -632,37 +621,55 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
   const int Y0 = ty * TY;
   const int Z0 = tzc * a.tz;
   const int Z1 = min(Z0 + a.tz, m);
-  const size_t rowS = (size_t)m;
-  const size_t planeS = DIM == 3 ? (size_t)m * m : (size_t)m;
+  const int planeS = DIM == 3 ? m * m : m;
   const T h2 = T(a.h2);
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const T om = T(a.omega);
   const T om1 = T(1.0 - a.omega);
-  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
-  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u_in);
-  const GMG_GLOBAL T *__restrict__ ecg = gbl(a.e_c);
-  GMG_GLOBAL T *__restrict__ uo = gbl(a.u_out);
 
-  int q[NS], xb[NS], yy[NS], lq[NS], rq[NS], uq[NS], dq[NS];
-  bool live[NS], yin[NS], outp[NS];
+  // per-slot geometry (see the red-black pass; here elements keep their
+  // index: k0 / k1 element inside the grid, h0 element 0 is the high half of
+  // the pair load)
+  int o2[NS], s0[NS], s1[NS], lq[NS], lft[NS], rgt[NS], lu[NS], ld[NS];
+  bool h0[NS], k0[NS], k1[NS], n0[NS], n1[NS], live[NS];
+  int cb[PRO ? NS : 1];
+  bool c2[PRO ? NS : 1];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    q[i] = threadIdx.x + NT * i;
-    live[i] = q[i] < PL;
-    const int p = q[i] % EXP, r = q[i] / EXP;
-    xb[i] = X0 - H + 2 * p;
-    yy[i] = DIM == 3 ? Y0 - H + r : 0;
-    yin[i] = DIM == 2 || (yy[i] >= 0 && yy[i] < m);
-    outp[i] = live[i] && yin[i] && p >= HP && p < HP + TXP &&
-              (DIM == 2 || (r >= H && r < H + TY)) && xb[i] < m;
-    const int rr = min(r, EY - 1);
-    lq[i] = rr * EXP + max(p - 1, 0);
-    rq[i] = rr * EXP + min(p + 1, EXP - 1);
-    uq[i] = max(rr - 1, 0) * EXP + p;
-    dq[i] = min(rr + 1, EY - 1) * EXP + p;
+    const int q = threadIdx.x + NT * i;
+    live[i] = q < PL;
+    const int qc = live[i] ? q : PL - 1;
+    const int p = qc % EXP, r = qc / EXP;
+    const int xb = X0 - H + 2 * p;
+    const int y = DIM == 3 ? Y0 - H + r : 0;
+    const bool yin = DIM == 2 || (y >= 0 && y < m);
+    const int off = (DIM == 3 ? y * m : 0) + xb;
+    const bool in0 = live[i] && yin && xb >= 0 && xb < m;
+    const bool in1 = live[i] && yin && xb + 1 >= 0 && xb + 1 < m;
+    const bool outp = live[i] && yin && p >= HP && p < HP + TXP &&
+                      (DIM == 2 || (r >= H && r < H + TY)) && xb < m;
+    const bool half = in0 && !in1;
+    o2[i] = in0 ? (off - (half ? 1 : 0)) * (int)sizeof(T) : kOOB;
+    h0[i] = half;
+    k0[i] = in0;
+    k1[i] = in1;
+    s0[i] = (outp && in0) ? off * (int)sizeof(T) : kOOB;
+    s1[i] = (outp && in1) ? (off + 1) * (int)sizeof(T) : kOOB;
+    n0[i] = outp && in0;
+    n1[i] = outp && in1;
+    lq[i] = qc;
+    lft[i] = max(qc - 1, 0);
+    rgt[i] = min(qc + 1, PL - 1);
+    lu[i] = max(qc - EXP, 0);
+    ld[i] = min(qc + EXP, PL - 1);
+    if (PRO) {
+      const int rr = DIM == 3 ? r : 0;
+      c2[i] = DIM == 3 && !(rr & 1);
+      cb[i] = (DIM == 3 ? ((rr & 1) ? (rr + 1) >> 1 : rr >> 1) * NCX : 0) + p;
+    }
   }
 
-  T W[S][NS][2][3];  // stage windows per element
+  T W[S][NS][2][3];  // stage windows per element: [0] newest plane
 #pragma unroll
   for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -671,89 +678,164 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
       for (int e = 0; e < 2; ++e) W[s][i][e][0] = W[s][i][e][1] = W[s][i][e][2] = T(0);
   double acc = 0.0;
 
-  for (int t = Z0 - S; t < Z1 + S; ++t) {
+  const int t0 = (Z0 - S) & ~1, t1 = Z1 + S;
+  auto load_pair = [&](const T *base, int z, T *v0, T *v1, bool mask) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(base, z, m, planeS);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const PairOf<T> v = bload2<T>(rs, o2[i]);
+      const T e0 = h0[i] ? v.hi : v.lo, e1 = v.hi;
+      v0[i] = (!mask || k0[i]) ? e0 : T(0);
+      v1[i] = (!mask || k1[i]) ? e1 : T(0);
+    }
+  };
+  T pu0[NS], pu1[NS];
+  if (ZERO) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pu0[i] = pu1[i] = T(0);
+  } else {
+    load_pair(a.u_in, t0, pu0, pu1, true);
+  }
+  T fe0[S + 1][NS], fe1[S + 1][NS];  // f of plane t - j, elements 0 / 1
+#pragma unroll
+  for (int j = 0; j <= S; ++j) load_pair(a.f, t0 - j, fe0[j], fe1[j], false);
+
+  const int CX0 = ((X0 - H) >> 1) - 1;
+  const int CY0 = DIM == 3 ? ((Y0 - H) >> 1) - 1 : 0;
+  const int mc = a.mc;
+  const int cplane = DIM == 3 ? mc * mc : mc;
+  int coff[NCP];
+  if (PRO) {
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) {
+      const int j = threadIdx.x + NT * k;
+      const int cx = CX0 + j % NCX, cy = CY0 + j / NCX;
+      const bool ok = j < CPL && cx >= 0 && cx < mc && (DIM == 2 || (cy >= 0 && cy < mc));
+      coff[k] = ok ? ((DIM == 3 ? cy * mc : 0) + cx) * (int)sizeof(T) : kOOB;
+    }
+  }
+  auto load_c = [&](int cz, T *v) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a.e_c, cz, mc, cplane);
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) v[k] = bload<T>(rs, coff[k]);
+  };
+  auto store_c = [&](int cz, const T *v) {
+    T *dst = cring + (cz & 1) * CPL;
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) {
+      const int j = threadIdx.x + NT * k;
+      if (NCP * NT == CPL || j < CPL) dst[j] = v[k];
+    }
+  };
+  auto cxy = [&](int cz, int i, T &v0, T &v1) {
+    const T *P = cring + (cz & 1) * CPL + cb[i];
+    const T el = P[0], er = P[1];
+    v0 = T(0.5) * (el + er);
+    v1 = er;
+    if (c2[i]) {
+      const T fl = P[NCX], fr = P[NCX + 1];
+      v0 = T(0.5) * (v0 + T(0.5) * (fl + fr));
+      v1 = T(0.5) * (v1 + fr);
+    }
+  };
+  T cnext[NCP];
+  if (PRO) {
+    T cv[NCP];
+    load_c((t0 >> 1) - 1, cv);
+    store_c((t0 >> 1) - 1, cv);
+    load_c(t0 >> 1, cv);
+    store_c(t0 >> 1, cv);
+    load_c((t0 + 2) >> 1, cnext);
+    __syncthreads();
+  }
+
+  // the stencil sum of element e around the previous stage's plane: x-1,
+  // x+1, y-1, y+1, z-1, z+1 in that order
+  auto nbsum = [&](const T *L, const T (&Wp)[NS][2][3], int i, int e) {
+    const T *Ln = L + (1 - e) * PL;  // the other element of neighbouring pairs
+    const T *Ls = L + e * PL;        // same element (y neighbours)
+    const T own = Wp[i][1 - e][1];
+    const T side = e ? Ln[rgt[i]] : Ln[lft[i]];
+    T nb = e ? own : side;
+    nb += e ? side : own;
+    if (DIM == 3) {
+      nb += Ls[lu[i]];
+      nb += Ls[ld[i]];
+    }
+    nb += Wp[i][e][2];
+    nb += Wp[i][e][0];
+    return nb;
+  };
+
+  auto step = [&](int t, auto tp_tag) {
+    constexpr int TP = decltype(tp_tag)::value;
+    T nu0[NS], nu1[NS];
+    if (!ZERO) load_pair(a.u_in, t + 1, nu0, nu1, true);
+    T fn0[NS], fn1[NS];
+    load_pair(a.f, t + 1, fn0, fn1, false);
+    T cnn[NCP];
+    if (PRO && TP == 1) load_c((t + 3) >> 1, cnn);
+    const T *Lprev = lds + (1 - TP) * 2 * S * PL;
+    // ---- stage 0: start value of plane t
     const bool tin = t >= 0 && t < m;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      T v[2] = {T(0), T(0)};
-      if (live[i] && tin && yin[i]) {
-        const size_t base = (size_t)t * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int x = xb[i] + e;
-          if (x < 0 || x >= m) continue;
-          if (!ZERO) v[e] = ug[base + x];
-          if (PRO)
-            v[e] += DIM == 3 ? interp<T, 3>(ecg, a.mc, x, yy[i], t)
-                             : interp<T, 2>(ecg, a.mc, x, t, 0);
+      T v0 = pu0[i], v1 = pu1[i];
+      if (PRO) {
+        T c0, c1;
+        if (TP == 1) {
+          cxy((t - 1) >> 1, i, c0, c1);
+        } else {
+          T l0, l1, g0, g1;
+          cxy((t >> 1) - 1, i, l0, l1);
+          cxy(t >> 1, i, g0, g1);
+          c0 = T(0.5) * (l0 + g0);
+          c1 = T(0.5) * (l1 + g1);
         }
+        v0 = (tin && k0[i]) ? v0 + c0 : v0;
+        v1 = (tin && k1[i]) ? v1 + c1 : v1;
       }
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         W[0][i][e][2] = W[0][i][e][1];
         W[0][i][e][1] = W[0][i][e][0];
-        W[0][i][e][0] = v[e];
       }
+      W[0][i][0][0] = v0;
+      W[0][i][1][0] = v1;
     }
+    // ---- residual of the start value on plane t-1 (convergence test)
     if (NORM) {
       const int zr = t - 1;
       if (zr >= Z0 && zr < Z1) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-          if (!outp[i]) continue;
-          const size_t base = (size_t)zr * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
-            const int x = xb[i] + e;
-            if (x >= m) continue;
-            const T *Ln = lds + (1 - e) * PL;  // the other element of neighbouring pairs
-            const T *Ls = lds + e * PL;        // same element (y neighbours)
-            const T own = W[0][i][1 - e][1];
-            const T side = e ? Ln[rq[i]] : Ln[lq[i]];
-            T nb = e ? own : side;
-            nb += e ? side : own;
-            if (DIM == 3) {
-              nb += Ls[uq[i]];
-              nb += Ls[dq[i]];
-            }
-            nb += W[0][i][e][2];
-            nb += W[0][i][e][0];
-            const double r = double(fg[base + x]) -
-                             (double(T(2 * DIM) * W[0][i][e][1]) - double(nb)) * a.inv_h2;
-            acc += r * r;
+            const T nb = nbsum(Lprev, W[0], i, e);
+            const T fv = e ? fe1[1][i] : fe0[1][i];
+            const double r =
+                double(fv) - (double(T(2 * DIM) * W[0][i][e][1]) - double(nb)) * a.inv_h2;
+            acc += (e ? n1[i] : n0[i]) ? r * r : 0.0;
           }
         }
       }
     }
+    // ---- stages 1..S
     T newS[NS][2];
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
       const int zs = t - s;
       const bool zin = zs >= 0 && zs < m;
-      const T *L = lds + (s - 1) * 2 * PL;
+      const T *L = Lprev + (s - 1) * 2 * PL;
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        const size_t base = (size_t)zs * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
         T nv[2];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-          const T *Ln = L + (1 - e) * PL;
-          const T *Ls = L + e * PL;
-          const T own = W[s - 1][i][1 - e][1];
-          const T side = e ? Ln[rq[i]] : Ln[lq[i]];
-          T nb = e ? own : side;
-          nb += e ? side : own;
-          if (DIM == 3) {
-            nb += Ls[uq[i]];
-            nb += Ls[dq[i]];
-          }
-          nb += W[s - 1][i][e][2];
-          nb += W[s - 1][i][e][0];
-          const int x = xb[i] + e;
-          T v = T(0);
-          if (live[i] && zin && yin[i] && x >= 0 && x < m)
-            v = om1 * W[s - 1][i][e][1] + om * (fma(h2, fg[base + x], nb) * inv2d);
-          nv[e] = v;
+          const T nb = nbsum(L, W[s - 1], i, e);
+          const T fv = e ? fe1[s][i] : fe0[s][i];
+          const bool in = zin && (e ? k1[i] : k0[i]);
+          nv[e] = in ? om1 * W[s - 1][i][e][1] + om * (fma(h2, fv, nb) * inv2d) : T(0);
         }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -767,28 +849,51 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
         }
       }
     }
+    // ---- output plane t-S
     const int zo = t - S;
     if (zo >= Z0 && zo < Z1) {
+      const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a.u_out, zo, m, planeS);
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        if (!outp[i]) continue;
-        const size_t base = (size_t)zo * planeS + (DIM == 3 ? (size_t)yy[i] * rowS : 0);
-        const int x0 = xb[i];
-        uo[base + x0] = newS[i][0];
-        if (x0 + 1 < m) uo[base + x0 + 1] = newS[i][1];
+        bstore<T>(rs, s0[i], newS[i][0]);
+        bstore<T>(rs, s1[i], newS[i][1]);
       }
     }
+    // ---- publish the newest plane of every stage (both elements)
+    T *Lnow = lds + TP * 2 * S * PL;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      if (TAIL && i == NS - 1 && !live[i]) continue;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        Lnow[(2 * s) * PL + lq[i]] = W[s][i][0][0];
+        Lnow[(2 * s + 1) * PL + lq[i]] = W[s][i][1][0];
+      }
+    }
+    if (PRO && TP == 1) store_c((t + 1) >> 1, cnext);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      if (!live[i]) continue;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        lds[(s * 2 + 0) * PL + q[i]] = W[s][i][0][0];
-        lds[(s * 2 + 1) * PL + q[i]] = W[s][i][1][0];
+      if (!ZERO) {
+        pu0[i] = nu0[i];
+        pu1[i] = nu1[i];
       }
+#pragma unroll
+      for (int j = S; j >= 1; --j) {
+        fe0[j][i] = fe0[j - 1][i];
+        fe1[j][i] = fe1[j - 1][i];
+      }
+      fe0[0][i] = fn0[i];
+      fe1[0][i] = fn1[i];
     }
-    __syncthreads();
+    if (PRO && TP == 1) {
+#pragma unroll
+      for (int k = 0; k < NCP; ++k) cnext[k] = cnn[k];
+    }
+  };
+  for (int t = t0; t < t1; t += 2) {
+    step(t, IntC<0>());
+    step(t + 1, IntC<1>());
   }
   if (NORM) block_sum_store<NT>(acc, gbl(a.partials));
 }
@@ -803,8 +908,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
 #define GMG_RB3_S4(X) X(3, 4, 36, 28, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
 #define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 #define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
-#define GMG_WJ3_S1(X) X(3, 1, 66, 18, 256) X(3, 1, 34, 18, 128)
-#define GMG_WJ3_S2(X) X(3, 2, 66, 22, 256) X(3, 2, 34, 20, 128)
+#define GMG_WJ3_S1(X) X(3, 1, 34, 30, 1024) X(3, 1, 66, 14, 1024) X(3, 1, 34, 14, 512)
+#define GMG_WJ3_S2(X) X(3, 2, 34, 30, 1024) X(3, 2, 66, 14, 1024) X(3, 2, 34, 14, 512)
 #define GMG_WJ2_S1(X) X(2, 1, 64, 1, 64) X(2, 1, 128, 1, 128)
 #define GMG_WJ2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 
@@ -898,7 +1003,9 @@ hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
 
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
-  const size_t lds = sizeof(T) * EXP * EY * 2 * S;
+  // two step-parity buffers of S planes of both elements, then the coarse ring
+  const size_t cpl = (FL & F_PROLONG) ? 2 * (size_t)(EXP + 1) * (DIM == 3 ? EY / 2 + 1 : 1) : 0;
+  const size_t lds = sizeof(T) * (4 * (size_t)S * EXP * EY + cpl);
   auto k = k_wj_pass<T, DIM, S, EXP, EY, NT, FL>;
   static bool attr = false;
   if (!attr) {
