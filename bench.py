@@ -40,6 +40,10 @@ WORKLOADS = {
     "poisson3d_255_sine_noise_fp64_wj22": dict(dim=3, L=8, rhs="sine_noise", prec="fp64",
                                                smoother="wj"),
     "batch256_uneven_fp64_v22": dict(dim=0, L=0, rhs="batch", prec="fp64"),
+    # one full-multigrid pass (Algorithm 2) on the model problem u = prod sin(pi x_i)
+    "poisson3d_255_sine_fmg22": dict(dim=3, L=8, rhs="fmg", prec="fp64"),
+    "poisson3d_1023_sine_fmg22": dict(dim=3, L=10, rhs="fmg", prec="fp64"),
+    "poisson2d_4095_sine_fmg22": dict(dim=2, L=12, rhs="fmg", prec="fp64"),
 }
 DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
 
@@ -113,6 +117,53 @@ def measured_traffic(workload, cls, tile):
     if not e or tile is None or (e.get("stages"), e.get("variant"), e.get("tz")) != tuple(tile):
         return None
     return e["traffic_bytes"]
+
+
+def bench_fmg(args, spec):
+    """One FMG(nu,nu) pass (Algorithm 2) for -Lap u = d pi^2 prod sin(pi x_i),
+    u = prod sin(pi x_i): time per pass, and its L2_h error against the exact
+    solution beside the discrete solution's own error (closed form), the
+    comparison of the paper's FMG tables."""
+    import torch
+
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd import workloads as wl
+    from paper_1208_4247_amd.solver import Plan
+
+    d, L, nu = spec["dim"], spec["L"], spec.get("nu", 2)
+    m = (1 << L) - 1
+    N = m ** d
+    h = 1.0 / (m + 1)
+    torch.cuda.set_device(0)
+    phi = wl.sine_product_device(d, m, "cuda")
+    f = (d * math.pi ** 2) * phi
+    flags = args.flags | (0 if args.no_autotune else capi.GMG_AUTOTUNE)
+    plan = Plan(d, L, nu1=nu, nu2=nu, flags=flags)
+    u = torch.empty_like(f)
+    for _ in range(max(1, args.warmup)):
+        plan.fmg(u, f)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.fmg(u, f)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ms = 1e3 * sum(ts) / len(ts)
+    err = float(torch.sqrt(h ** d * torch.sum((u - phi) ** 2)))
+    lam = d * (4.0 / h ** 2) * math.sin(math.pi * h / 2) ** 2
+    disc = abs(d * math.pi ** 2 / lam - 1.0) * float(torch.sqrt(h ** d * torch.sum(phi ** 2)))
+    line = {
+        "metric": "fine-grid unknowns/s, one FMG(%d,%d) pass to discretisation accuracy" % (nu, nu),
+        "value": N / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
+                   "cycle": "FMG(%d,%d) red-black GS" % (nu, nu), "l2h_error": err,
+                   "discretisation_error": disc, "error_ratio": err / disc},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_batch(args):
@@ -242,6 +293,8 @@ def main():
     spec = WORKLOADS[args.workload]
     if spec["rhs"] == "batch":
         return bench_batch(args)
+    if spec["rhs"] == "fmg":
+        return bench_fmg(args, spec)
     d, L = spec["dim"], spec["L"]
     nu = spec.get("nu", 2)
     inner = spec.get("inner", 1)

@@ -126,6 +126,15 @@ gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, cons
  * refinement step x <- x + V32(f - A x).  u and f: device, m0^d FP64. */
 gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f);
 
+/* Full multigrid FMG(nu1, nu2) (Algorithm 2; single-problem FP64 plans):
+ * f is restricted to every level by full weighting, the one-node level is
+ * solved exactly, and for each level from the coarse end the coarser result
+ * is interpolated and one V(nu1, nu2) cycle is run on that level and the
+ * ones below it.  u (output only, m0^d FP64) receives the finest result;
+ * it reaches the discretisation error in one pass for smooth data.
+ * Enqueue only.  GMG_ERR_UNSUPPORTED for mixed-precision plans. */
+gmg_status gmg_fmg(gmg_plan *p, double *u, const double *f);
+
 /* Solve loop of Algorithm 3 with every level on the GPU: res0 = ||f - A u||_2
  * for the initial u (or *res0_opt when resuming); repeat V-cycles while
  * ||f - A u||_2 > rtol * res0 and the cycle count is below maxit.  The

@@ -41,7 +41,7 @@ EXPORTED = [
     "gmg_destroy", "gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
     "gmg_op_smooth", "gmg_op_restrict_residual", "gmg_op_residual", "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
-    "gmg_profile_set_mask", "gmg_plan_get_tile",
+    "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg",
 ]
 
 
@@ -93,6 +93,7 @@ def lib():
     L.gmg_config_default.argtypes = [cfgp, i, i]
     L.gmg_setup.argtypes = [cfgp, i, ip, ip, vp, ctypes.POINTER(sz), vp, ctypes.POINTER(vp)]
     L.gmg_vcycle.argtypes = [vp, vp, vp]
+    L.gmg_fmg.argtypes = [vp, vp, vp]
     L.gmg_solve.argtypes = [vp, vp, vp, d, i, dp, ip, dp]
     L.gmg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), d, i, ip, dp, ip]
     L.gmg_destroy.argtypes = [vp]

@@ -179,6 +179,42 @@ __device__ __forceinline__ int bl_offset(int dim, int L, int l) {
   return off;
 }
 
+// One V-cycle (Algorithm 1) on the levels top .. L-1 of the LDS hierarchy,
+// from the start value held in level top's u; the coarser levels start from
+// zero (cleared here when `clear`, otherwise already zero).
+template <typename T, int DIM>
+__device__ void b_vcycle(const BottomArgs<T> &a, T *sm, T *R, int L, int top, bool clear) {
+  const T omega = T(a.omega);
+  for (int l = top; l + 1 < L; ++l) {
+    const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
+    T *U = sm + bl_offset(DIM, L, l);
+    T *F = U + b.size;
+    T *Fc = sm + bl_offset(DIM, L, l + 1) + c.size;
+    if (clear && l > top) {
+      b_for_all<DIM>(b, [&](int i, int, int, int) { U[i] = T(0); });
+      __syncthreads();
+    }
+    b_smooth<T, DIM>(b, U, F, R, a.nu1, false, a.smoother, omega);
+    b_restrict<T, DIM>(b, U, F, R, c, Fc);
+  }
+  if (threadIdx.x == 0) {  // one-node level: 2d u / h^2 = f, in FP64
+    const BL c = bl_make(DIM, L, L - 1);
+    T *U = sm + bl_offset(DIM, L, L - 1);
+    const int i = DIM == 3 ? c.n * c.n : c.n;  // element (0,0[,0])
+    const double h = 1.0 / double(c.n);
+    U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
+  }
+  __syncthreads();
+  for (int l = L - 2; l >= top; --l) {
+    const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
+    T *U = sm + bl_offset(DIM, L, l);
+    T *F = U + b.size;
+    const T *Uc = sm + bl_offset(DIM, L, l + 1);
+    b_prolong<T, DIM>(b, U, c, Uc);
+    b_smooth<T, DIM>(b, U, F, R, a.nu2, !a.post_forward, a.smoother, omega);
+  }
+}
+
 template <typename T, int DIM>
 __device__ void bottom_body(const BottomArgs<T> &a, const GMG_GLOBAL T *fin, GMG_GLOBAL T *uout, T *sm) {
   const int L = a.L;
@@ -195,30 +231,30 @@ __device__ void bottom_body(const BottomArgs<T> &a, const GMG_GLOBAL T *fin, GMG
     });
   }
   __syncthreads();
-  const T omega = T(a.omega);
-  for (int l = 0; l + 1 < L; ++l) {
-    const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
-    T *U = sm + bl_offset(DIM, L, l);
-    T *F = U + b.size;
-    T *Fc = sm + bl_offset(DIM, L, l + 1) + c.size;
-    b_smooth<T, DIM>(b, U, F, R, a.nu1, false, a.smoother, omega);
-    b_restrict<T, DIM>(b, U, F, R, c, Fc);
-  }
-  if (threadIdx.x == 0) {  // one-node level: 2d u / h^2 = f, in FP64
-    const BL c = bl_make(DIM, L, L - 1);
-    T *U = sm + bl_offset(DIM, L, L - 1);
-    const int i = DIM == 3 ? c.n * c.n : c.n;  // element (0,0[,0])
-    const double h = 1.0 / double(c.n);
-    U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
-  }
-  __syncthreads();
-  for (int l = L - 2; l >= 0; --l) {
-    const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
-    T *U = sm + bl_offset(DIM, L, l);
-    T *F = U + b.size;
-    const T *Uc = sm + bl_offset(DIM, L, l + 1);
-    b_prolong<T, DIM>(b, U, c, Uc);
-    b_smooth<T, DIM>(b, U, F, R, a.nu2, !a.post_forward, a.smoother, omega);
+  if (!a.fmg) {
+    b_vcycle<T, DIM>(a, sm, R, L, 0, false);
+  } else {
+    // Algorithm 2: f to every level by full weighting (the residual of the
+    // zero iterate), the coarsest level exactly, then per level from the
+    // coarse end: interpolate the coarser solution and run one V-cycle
+    for (int l = 0; l + 1 < L; ++l) {
+      const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
+      T *U = sm + bl_offset(DIM, L, l);
+      b_restrict<T, DIM>(b, U, U + b.size, R, c, sm + bl_offset(DIM, L, l + 1) + c.size);
+    }
+    if (threadIdx.x == 0) {
+      const BL c = bl_make(DIM, L, L - 1);
+      T *U = sm + bl_offset(DIM, L, L - 1);
+      const int i = DIM == 3 ? c.n * c.n : c.n;
+      const double h = 1.0 / double(c.n);
+      U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
+    }
+    __syncthreads();
+    for (int l = L - 2; l >= 0; --l) {
+      const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
+      b_prolong<T, DIM>(b, sm + bl_offset(DIM, L, l), c, sm + bl_offset(DIM, L, l + 1));
+      b_vcycle<T, DIM>(a, sm, R, L, l, true);
+    }
   }
   b_for_all<DIM>(b0, [&](int i, int x, int y, int z) {
     const int m = b0.m;

@@ -480,13 +480,13 @@ bool use_small(const gmg_plan *p, int dim, int m, int nu, size_t elem) {
 // Levels 1..B-1 of the descent, the bottom kernel and levels B-1..1 of the
 // ascent: everything of a cycle that touches only workspace arrays.
 template <typename T>
-hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
+hipError_t enqueue_coarse(gmg_plan *p, const int *active, int first = 1) {
   LevelSet<T> &S = levels_of<T>(p);
   const int L = p->L, B = p->B;
   const bool bwd = !(p->cfg.flags & GMG_POST_FORWARD);
   const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
   hipError_t e;
-  for (int l = 1; l < B; ++l) {
+  for (int l = first; l < B; ++l) {
     const int m = p->m[l];
     const double h = 1.0 / double(m + 1);
     if (use_small(p, p->dim, m, nu1, sizeof(T))) {
@@ -515,7 +515,7 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
     }
   }
   {
-    BottomArgs<T> ba;
+    BottomArgs<T> ba{};
     ba.active = active;
     ba.dim = p->dim;
     ba.nu1 = nu1;
@@ -530,7 +530,7 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active) {
     e = launch_bottom<T>(1, ba, nullptr, p->stream);
     if (e != hipSuccess) return e;
   }
-  for (int l = B - 1; l >= 1; --l) {
+  for (int l = B - 1; l >= first; --l) {
     const int m = p->m[l];
     if (use_small(p, p->dim, m, nu2, sizeof(T))) {
       const double h = 1.0 / double(m + 1);
@@ -606,7 +606,7 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
   const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
   hipError_t e;
   int nparts = 0;
-  BottomArgs<T> ba;
+  BottomArgs<T> ba{};
   ba.active = active;
   ba.dim = p->dim;
   ba.nu1 = nu1;
@@ -655,6 +655,75 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
   if (e != hipSuccess) return e;
   return smooth_chain<T>(p, 0, nu2, bwd, w0, S.u[1], f0, u0_out, S.t[0], nullptr, active,
                          PC_POST0, nullptr);
+}
+
+// ------------------------------------------------------------------ FMG
+// One V-cycle on the levels s .. L-1 (1 <= s < B) from the start value in the
+// workspace u of level s, right-hand side f of level s, result back in u of
+// level s: the general passes on level s (non-zero start), then the usual
+// coarse part from level s+1.
+hipError_t enqueue_vcycle_level(gmg_plan *p, int s) {
+  LevelSet<double> &S = p->d;
+  const bool bwd = !(p->cfg.flags & GMG_POST_FORWARD);
+  bool fused = false;
+  hipError_t e = smooth_chain<double>(p, s, p->cfg.nu1, false, S.u[s], nullptr, S.f[s], S.w[s],
+                                      S.t[s], nullptr, nullptr, PC_PRE_C, nullptr, S.f[s + 1],
+                                      &fused);
+  if (e != hipSuccess) return e;
+  if (!fused) {
+    e = restrict_level<double>(p, s, S.w[s], S.f[s], S.f[s + 1], nullptr, PC_RES_C);
+    if (e != hipSuccess) return e;
+  }
+  e = enqueue_coarse<double>(p, nullptr, s + 1);
+  if (e != hipSuccess) return e;
+  return smooth_chain<double>(p, s, p->cfg.nu2, bwd, S.w[s], S.u[s + 1], S.f[s], S.u[s], S.t[s],
+                              nullptr, nullptr, PC_POST_C, nullptr);
+}
+
+// Full multigrid (Algorithm 2) into u: f restricted to every level (full
+// weighting), the bottom levels by the bottom kernel's own full multigrid,
+// then for each finer level the interpolated coarser solution and one
+// V-cycle, ending with the finest level.
+hipError_t enqueue_fmg(gmg_plan *p, double *u, const double *f) {
+  LevelSet<double> &S = p->d;
+  const int L = p->L, B = p->B;
+  BottomArgs<double> ba{};
+  ba.dim = p->dim;
+  ba.nu1 = p->cfg.nu1;
+  ba.nu2 = p->cfg.nu2;
+  ba.smoother = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+  ba.post_forward = (p->cfg.flags & GMG_POST_FORWARD) ? 1 : 0;
+  ba.omega = p->cfg.omega;
+  ba.fmg = 1;
+  hipError_t e;
+  if (L == 1) {
+    ba.f = f;
+    ba.u = u;
+    ba.L = 1;
+    return launch_bottom<double>(1, ba, nullptr, p->stream);
+  }
+  for (int l = 0; l < B; ++l) {
+    e = restrict_level<double>(p, l, nullptr, l == 0 ? f : S.f[l], S.f[l + 1], nullptr, PC_MISC);
+    if (e != hipSuccess) return e;
+  }
+  ba.f = S.f[B];
+  ba.u = S.u[B];
+  ba.L = L - B;
+  {
+    ProfScope ps(p, PC_BOTTOM, (double)npts(p->dim, p->m[B]) * sizeof(double) * 2);
+    e = launch_bottom<double>(1, ba, nullptr, p->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int l = B - 1; l >= 1; --l) {
+    e = launch_prolong_add<double>(p->dim, p->m[l], p->m[l + 1], nullptr, S.u[l + 1], S.u[l],
+                                   nullptr, p->stream);
+    if (e != hipSuccess) return e;
+    e = enqueue_vcycle_level(p, l);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_prolong_add<double>(p->dim, p->m[0], p->m[1], nullptr, S.u[1], u, nullptr, p->stream);
+  if (e != hipSuccess) return e;
+  return enqueue_vcycle<double>(p, u, f, u, nullptr, nullptr);
 }
 
 // ------------------------------------------------------------------ layout
@@ -1716,6 +1785,14 @@ int gmg_level_side(const gmg_plan *p, int problem, int level) {
   }
   if (!p || problem != 0 || level < 0 || level >= p->L) return -1;
   return p->m[level];
+}
+
+gmg_status gmg_fmg(gmg_plan *p, double *u, const double *f) {
+  if (!p || !u || !f || p->batch) return GMG_ERR_INVALID_ARG;
+  if (p->cfg.precision != GMG_FP64) return GMG_ERR_UNSUPPORTED;
+  if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) HIPCHK(tune_plan<double>(p, u, f, nullptr));
+  HIPCHK(enqueue_fmg(p, u, f));
+  return GMG_OK;
 }
 
 gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f) {

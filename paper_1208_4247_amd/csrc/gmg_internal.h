@@ -175,6 +175,8 @@ struct BottomArgs {
   int nu1, nu2;
   int smoother;         // 0 RBGS, 1 WJ
   int post_forward;     // post-smoothing in forward order
+  int fmg;              // 1: full multigrid over the bottom levels (Algorithm 2)
+                        // instead of one V-cycle from zero
   double omega;
 };
 

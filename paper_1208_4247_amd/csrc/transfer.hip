@@ -124,7 +124,8 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
   }
   auto load_u = [&](int z, T *v) {
 #pragma unroll
-    for (int k = 0; k < NU; ++k) v[k] = (z >= 0 && z < m && uo[k] >= 0) ? ug[z * planeS + uo[k]] : T(0);
+    for (int k = 0; k < NU; ++k)
+      v[k] = (ug && z >= 0 && z < m && uo[k] >= 0) ? ug[z * planeS + uo[k]] : T(0);
   };
   auto load_f = [&](int z, T *v) {
 #pragma unroll

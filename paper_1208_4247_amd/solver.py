@@ -77,6 +77,10 @@ class Plan:
     def vcycle(self, u: torch.Tensor, f: torch.Tensor) -> None:
         capi.check(capi.lib().gmg_vcycle(self._plan, _ptr(u), _ptr(f)), "gmg_vcycle")
 
+    def fmg(self, u: torch.Tensor, f: torch.Tensor) -> None:
+        """Full multigrid (Algorithm 2) into u (enqueue only)."""
+        capi.check(capi.lib().gmg_fmg(self._plan, _ptr(u), _ptr(f)), "gmg_fmg")
+
     def solve(self, u: torch.Tensor, f: torch.Tensor, rtol: float = 1e-10, maxit: int = 100,
               res0: float | None = None):
         it = ctypes.c_int(0)

@@ -145,6 +145,17 @@ def rhs_sine_modes_device(d: int, m: int, seed: int, device, nmodes: int = 8,
     return f
 
 
+def sine_product_device(d: int, m: int, device):
+    """prod_i sin(pi x_i) on a torch device, the same chain of products as
+    sine_product (bitwise equal)."""
+    import torch
+
+    s = torch.from_numpy(np.sin(math.pi * nodes(m))).to(device)
+    if d == 2:
+        return s[:, None] * s[None, :]
+    return (s[:, None, None] * s[None, :, None]) * s[None, None, :]
+
+
 def batch_problems(seed: int = 4, n2d: int = 128, n3d: int = 128,
                    k2d=(6, 10), k3d=(5, 7)):
     """The uneven batch: (dim, side) per problem.  Problem p < n2d is 2D with

@@ -390,3 +390,41 @@ def test_profile_counts_only_launches_that_ran(precision):
     prof2 = plan.profile()
     key = "smooth_pre_l0" if precision == "fp64" else "ir_step"
     assert prof2[key]["launches"] == 2 * prof[key]["launches"]
+
+
+# ------------------------------------------------------------------ FMG
+
+
+@pytest.mark.parametrize("dim,m,nu,smoother", [
+    (2, 127, (1, 1), "rbgs"), (2, 255, (2, 2), "rbgs"), (3, 63, (1, 1), "rbgs"),
+    (3, 127, (2, 2), "rbgs"), (3, 31, (2, 1), "rbgs"), (2, 63, (2, 2), "wj"),
+    (3, 63, (1, 1), "wj"), (2, 7, (1, 1), "rbgs"), (3, 3, (1, 1), "rbgs"), (3, 1, (1, 1), "rbgs")])
+def test_fmg_matches_oracle(dim, m, nu, smoother):
+    """Full multigrid (Algorithm 2) on the GPU equals the oracle's FMG."""
+    fh = wl.rhs_sine(dim, m) + 0.1 * wl.rhs_uniform(dim, m, seed=81)
+    f = dev(fh)
+    plan = Plan(dim, levels_of(m), nu1=nu[0], nu2=nu[1], smoother=smoother)
+    u = torch.full_like(f, float("nan"))  # output only
+    plan.fmg(u, f)
+    omega = 2 * dim / (2 * dim + 1)
+    want = oracle.fmg(fh, nu[0], nu[1], smoother=oracle.WJ if smoother == "wj" else oracle.RBGS,
+                      omega=omega)
+    assert maxrel(host(u), want) <= 1e-12
+
+
+def test_fmg_reaches_discretisation_accuracy():
+    """FMG for the model problem lands within a small factor of the
+    discretisation error of the exact discrete solution, as the FMG columns
+    of Tables 12 and 14 do (the oracle's pin uses the same bounds: 2D
+    FMG(2,2) within 1.5x, 3D FMG(3,3) within 3x)."""
+    for dim, m, nu, bound in ((2, 255, 2, 1.5), (3, 127, 3, 3.0)):
+        fh = wl.rhs_sine(dim, m)
+        plan = Plan(dim, levels_of(m), nu1=nu, nu2=nu)
+        u = torch.zeros_like(dev(fh))
+        plan.fmg(u, dev(fh))
+        exact = wl.sine_product(dim, m)
+        h = 1.0 / (m + 1)
+        err = float(np.sqrt(h ** dim * np.sum((host(u) - exact) ** 2)))
+        ud, *_ = oracle.solve(fh, rtol=1e-12)
+        disc = float(np.sqrt(h ** dim * np.sum((ud - exact) ** 2)))
+        assert err <= bound * disc, (dim, m, err, disc)
