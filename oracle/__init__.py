@@ -24,6 +24,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 RBGS = 0
 WJ = 1
+MCGS = 2  # multicolour Gauss-Seidel: 4 colours in 2D, 8 in 3D
+
+# variant bits of the cycle functions
+FE_TRANSFER = 1   # the paper's linear finite-element restriction / interpolation
+COARSE_RELAX = 2  # coarsest level relaxed by nu1 smoother sweeps instead of solved exactly
 
 
 def build(force: bool = False) -> str:
@@ -57,15 +62,19 @@ def lib():
         L.orc_residual.argtypes = [i, i, dp, dp, dp]
         L.orc_rbgs_color.argtypes = [i, i, dp, dp, i]
         L.orc_rbgs.argtypes = [i, i, dp, dp, i, i]
+        L.orc_mcgs_color.argtypes = [i, i, dp, dp, i]
+        L.orc_mcgs.argtypes = [i, i, dp, dp, i, i]
         L.orc_wj.argtypes = [i, i, dp, dp, d, i, dp]
         L.orc_restrict_fw.argtypes = [i, i, dp, dp]
         L.orc_prolong_add.argtypes = [i, i, dp, dp]
-        L.orc_vcycle.argtypes = [i, i, dp, dp, i, i, i, d]
+        L.orc_restrict_fe.argtypes = [i, i, dp, dp]
+        L.orc_prolong_add_fe.argtypes = [i, i, dp, dp]
+        L.orc_vcycle.argtypes = [i, i, dp, dp, i, i, i, d, i]
         L.orc_vcycle.restype = i
         L.orc_solve.argtypes = [i, i, dp, dp, i, i, i, d, d, i, d,
-                                ctypes.POINTER(ctypes.c_int), dp, dp]
+                                ctypes.POINTER(ctypes.c_int), dp, dp, i]
         L.orc_solve.restype = i
-        L.orc_fmg.argtypes = [i, i, dp, dp, i, i, i, d]
+        L.orc_fmg.argtypes = [i, i, dp, dp, i, i, i, d, i]
         L.orc_fmg.restype = i
         _lib = L
     return _lib
@@ -133,6 +142,20 @@ def rbgs(u: np.ndarray, f: np.ndarray, nsweeps: int, backward: bool = False) -> 
     return u
 
 
+def mcgs_color(u: np.ndarray, f: np.ndarray, color: int) -> np.ndarray:
+    d, m = u.ndim, u.shape[0]
+    u = _grid(u, d, m).copy()
+    lib().orc_mcgs_color(d, m, _p(u), _p(_grid(f, d, m)), int(color))
+    return u
+
+
+def mcgs(u: np.ndarray, f: np.ndarray, nsweeps: int, backward: bool = False) -> np.ndarray:
+    d, m = u.ndim, u.shape[0]
+    u = _grid(u, d, m).copy()
+    lib().orc_mcgs(d, m, _p(u), _p(_grid(f, d, m)), int(nsweeps), int(bool(backward)))
+    return u
+
+
 def wj(u: np.ndarray, f: np.ndarray, omega: float, nsweeps: int) -> np.ndarray:
     d, m = u.ndim, u.shape[0]
     u = _grid(u, d, m).copy()
@@ -157,26 +180,44 @@ def prolong_add(e: np.ndarray, u: np.ndarray) -> np.ndarray:
     return u
 
 
-def vcycle(u, f, nu1=2, nu2=2, smoother=RBGS, omega=0.8) -> np.ndarray:
+def restrict_fe(r: np.ndarray) -> np.ndarray:
+    d, mf = r.ndim, r.shape[0]
+    mc = (mf - 1) // 2
+    out = np.empty((mc,) * d)
+    lib().orc_restrict_fe(d, mc, _p(_grid(r, d, mf)), _p(out))
+    return out
+
+
+def prolong_add_fe(e: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Return u + P e with the linear finite-element interpolation."""
+    d, mc = e.ndim, e.shape[0]
+    u = _grid(u, d, 2 * mc + 1).copy()
+    lib().orc_prolong_add_fe(d, mc, _p(_grid(e, d, mc)), _p(u))
+    return u
+
+
+def vcycle(u, f, nu1=2, nu2=2, smoother=RBGS, omega=0.8, variant=0) -> np.ndarray:
     d, m = u.ndim, u.shape[0]
     u = _grid(u, d, m).copy()
-    rc = lib().orc_vcycle(d, m, _p(u), _p(_grid(f, d, m)), nu1, nu2, smoother, float(omega))
+    rc = lib().orc_vcycle(d, m, _p(u), _p(_grid(f, d, m)), nu1, nu2, smoother, float(omega),
+                          int(variant))
     if rc:
         raise ValueError("bad grid for the V-cycle")
     return u
 
 
-def fmg(f, nu1=1, nu2=1, smoother=RBGS, omega=0.8) -> np.ndarray:
+def fmg(f, nu1=1, nu2=1, smoother=RBGS, omega=0.8, variant=0) -> np.ndarray:
     d, m = f.ndim, f.shape[0]
     u = np.zeros((m,) * d)
-    rc = lib().orc_fmg(d, m, _p(u), _p(_grid(f, d, m)), nu1, nu2, smoother, float(omega))
+    rc = lib().orc_fmg(d, m, _p(u), _p(_grid(f, d, m)), nu1, nu2, smoother, float(omega),
+                       int(variant))
     if rc:
         raise ValueError("bad grid for FMG")
     return u
 
 
 def solve(f, u0=None, nu1=2, nu2=2, smoother=RBGS, omega=0.8, rtol=1e-10, maxit=100,
-          res0=0.0):
+          res0=0.0, variant=0):
     """Returns (u, iters, relres, status, res_hist)."""
     d, m = f.ndim, f.shape[0]
     f = _grid(f, d, m)
@@ -185,7 +226,8 @@ def solve(f, u0=None, nu1=2, nu2=2, smoother=RBGS, omega=0.8, rtol=1e-10, maxit=
     rel = ctypes.c_double(0.0)
     hist = np.zeros(maxit + 1)
     st = lib().orc_solve(d, m, _p(u), _p(f), nu1, nu2, smoother, float(omega), float(rtol),
-                         int(maxit), float(res0), ctypes.byref(it), ctypes.byref(rel), _p(hist))
+                         int(maxit), float(res0), ctypes.byref(it), ctypes.byref(rel), _p(hist),
+                         int(variant))
     if st == -1:
         raise ValueError("bad grid for the solver")
     return u, it.value, rel.value, st, hist[: it.value + 1].copy()

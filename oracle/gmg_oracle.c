@@ -42,6 +42,17 @@
  *    the Euclidean norm with the square root; iterate while
  *    res > tol * res0 and iter < maxit.
  *
+ * The paper's own smoother and transfers are kept as a variant (selected per
+ * call): multicolour Gauss-Seidel (4 colours in 2D, 8 in 3D, Remark 1) and the
+ * linear finite-element transfers of Sec. 4 (eq. Restriction2d,
+ * eq. Prolongation2d and the 3D operation counts), with the coarsest level
+ * either solved exactly or relaxed by the smoother as Algorithm 1 writes it.
+ * Readings for the variant: colour of node (i, j[, k]) = (i & 1) + 2 (j & 1)
+ * [+ 4 (k & 1)], the forward sweep visits colours 0, 1, ..., 2^d - 1 and the
+ * backward sweep the reverse; the 3D triangulation is the one whose edges are
+ * the seven directions with components in {0, 1} (the 2D edge set
+ * (1,0), (0,1), (1,1) of eq. Prolongation2d, extended).
+ *
  * Parity status of each function: every function is pinned by the tests
  * (closed forms, the paper's printed FFT error columns, dense and DST exact
  * solves, Fourier symbols, invariants, symmetry, local Fourier analysis).
@@ -203,6 +214,46 @@ void orc_rbgs(int d, int m, double *u, const double *f, int nsweeps, int backwar
   }
 }
 
+/* One colour of the multicolour Gauss-Seidel smoother (Remark 1: four colours
+ * in 2D, eight in 3D).  Node (i, j[, k]) has colour (i&1) + 2(j&1) [+ 4(k&1)];
+ * nodes of one colour differ by an even amount along every axis, so none of
+ * them neighbours another and the order inside a colour does not matter.  The
+ * update is the same pointwise solve as eq. relax_2D. */
+void orc_mcgs_color(int d, int m, double *u, const double *f, int color) {
+  double h = 1.0 / (double)(m + 1);
+  double h2 = h * h;
+  if (d == 2) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < m; j++)
+      for (int i = 0; i < m; i++) {
+        if ((((i + 1) & 1) + 2 * ((j + 1) & 1)) != color) continue;
+        long p = (long)j * m + i;
+        double nb = at2(u, m, i - 1, j) + at2(u, m, i + 1, j) + at2(u, m, i, j - 1) +
+                    at2(u, m, i, j + 1);
+        u[p] = (h2 * f[p] + nb) / 4.0;
+      }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < m; k++)
+      for (int j = 0; j < m; j++)
+        for (int i = 0; i < m; i++) {
+          if ((((i + 1) & 1) + 2 * ((j + 1) & 1) + 4 * ((k + 1) & 1)) != color) continue;
+          long p = ((long)k * m + j) * m + i;
+          double nb = at3(u, m, i - 1, j, k) + at3(u, m, i + 1, j, k) + at3(u, m, i, j - 1, k) +
+                      at3(u, m, i, j + 1, k) + at3(u, m, i, j, k - 1) + at3(u, m, i, j, k + 1);
+          u[p] = (h2 * f[p] + nb) / 6.0;
+        }
+  }
+}
+
+/* nsweeps multicolour sweeps: forward visits colours 0 .. 2^d - 1, backward
+ * the reverse (Relax_forward / Relax_backward of Algorithm 1). */
+void orc_mcgs(int d, int m, double *u, const double *f, int nsweeps, int backward) {
+  int nc = 1 << d;
+  for (int s = 0; s < nsweeps; s++)
+    for (int q = 0; q < nc; q++) orc_mcgs_color(d, m, u, f, backward ? nc - 1 - q : q);
+}
+
 /* nsweeps weighted-Jacobi sweeps (Remark 1; Table 5):
  *   u_new = (1 - omega) u + omega (h^2 f + sum nbrs) / (2d), all from old u.
  * tmp must hold m^d doubles. */
@@ -330,15 +381,100 @@ void orc_prolong_add(int d, int mc, const double *e, double *u) {
   }
 }
 
+/* Edge directions of the triangulation behind the paper's linear
+ * finite-element transfers: every nonzero vector with components in {0, 1}.
+ * In 2D these are (1,0), (0,1), (1,1), the three of eq. Prolongation2d. */
+static int fe_dirs(int d, int dir[7][3]) {
+  int n = 0;
+  for (int o = 1; o < (1 << d); o++) {
+    dir[n][0] = o & 1;
+    dir[n][1] = (o >> 1) & 1;
+    dir[n][2] = (o >> 2) & 1;
+    n++;
+  }
+  return n;
+}
+
+/* u (fine, mf = 2 mc + 1) += P e, P the linear finite-element interpolation
+ * (eq. Prolongation2d and its 3D analogue): fine node 2I coincides with coarse
+ * node I; fine node 2I + o, o a direction above, is the midpoint of the edge
+ * from coarse node I to I + o and takes the mean of the two.  Coarse values on
+ * the boundary are zero. */
+void orc_prolong_add_fe(int d, int mc, const double *e, double *u) {
+  int mf = 2 * mc + 1;
+  long planes = d == 2 ? 1 : mf;
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < planes; k++)
+    for (int j = 0; j < mf; j++)
+      for (int i = 0; i < mf; i++) {
+        /* node indices of the fine point and its parity pattern o */
+        int F[3] = {i + 1, j + 1, (int)k + 1};
+        int o[3] = {F[0] & 1, F[1] & 1, d == 3 ? F[2] & 1 : 0};
+        int I[3] = {(F[0] - o[0]) / 2, (F[1] - o[1]) / 2, (F[2] - o[2]) / 2};
+        double s;
+        if (d == 2) {
+          double c0 = at2(e, mc, I[0] - 1, I[1] - 1);
+          if (!o[0] && !o[1])
+            s = c0;
+          else
+            s = 0.5 * (c0 + at2(e, mc, I[0] + o[0] - 1, I[1] + o[1] - 1));
+          u[(long)j * mf + i] += s;
+        } else {
+          double c0 = at3(e, mc, I[0] - 1, I[1] - 1, I[2] - 1);
+          if (!o[0] && !o[1] && !o[2])
+            s = c0;
+          else
+            s = 0.5 * (c0 + at3(e, mc, I[0] + o[0] - 1, I[1] + o[1] - 1, I[2] + o[2] - 1));
+          u[(k * mf + j) * mf + i] += s;
+        }
+      }
+}
+
+/* Linear finite-element restriction (eq. Restriction2d in 2D; 16 operations
+ * per point in 3D): coarse node I takes twice the fine value at 2I plus the
+ * fine values at 2I + e and 2I - e for every edge direction e, all divided by
+ * 2^(d+1).  This is 2^-d times the transpose of orc_prolong_add_fe. */
+void orc_restrict_fe(int d, int mc, const double *r, double *fc) {
+  int mf = 2 * mc + 1;
+  int dir[7][3];
+  int nd = fe_dirs(d, dir);
+  double scale = 1.0 / (double)(1 << (d + 1));
+  long planes = d == 2 ? 1 : mc;
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < planes; c++)
+    for (int b = 0; b < mc; b++)
+      for (int a = 0; a < mc; a++) {
+        /* fine storage index of fine node 2I, I = (a+1, b+1, c+1) */
+        int x = 2 * a + 1, y = 2 * b + 1, z = 2 * (int)c + 1;
+        double s;
+        if (d == 2) {
+          s = 2.0 * at2(r, mf, x, y);
+          for (int q = 0; q < nd; q++)
+            s += at2(r, mf, x + dir[q][0], y + dir[q][1]) + at2(r, mf, x - dir[q][0], y - dir[q][1]);
+          fc[(long)b * mc + a] = s * scale;
+        } else {
+          s = 2.0 * at3(r, mf, x, y, z);
+          for (int q = 0; q < nd; q++)
+            s += at3(r, mf, x + dir[q][0], y + dir[q][1], z + dir[q][2]) +
+                 at3(r, mf, x - dir[q][0], y - dir[q][1], z - dir[q][2]);
+          fc[(c * mc + b) * mc + a] = s * scale;
+        }
+      }
+}
+
 /* ------------------------------------------------------------------------ */
 /* V-cycle (Algorithm 1) and solve loop (Algorithm 3, all levels on one      */
 /* device)                                                                   */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_RBGS = 0, ORC_WJ = 1 };
+enum { ORC_RBGS = 0, ORC_WJ = 1, ORC_MCGS = 2 };
+/* variant bits: the paper's linear finite-element transfers instead of full
+ * weighting / (bi/tri)linear; the coarsest level relaxed by nu1 sweeps of the
+ * smoother (Algorithm 1 as printed) instead of solved exactly */
+enum { ORC_FE_TRANSFER = 1, ORC_COARSE_RELAX = 2 };
 
 typedef struct {
-  int d, L;
+  int d, L, variant;
   int m[32];
   double *u[32], *f[32], *r[32];
 } hier_t;
@@ -380,6 +516,8 @@ static void smooth(hier_t *H, int l, int smoother, double omega, int nsweeps, in
   if (nsweeps <= 0) return;
   if (smoother == ORC_RBGS)
     orc_rbgs(H->d, H->m[l], H->u[l], H->f[l], nsweeps, backward);
+  else if (smoother == ORC_MCGS)
+    orc_mcgs(H->d, H->m[l], H->u[l], H->f[l], nsweeps, backward);
   else
     orc_wj(H->d, H->m[l], H->u[l], H->f[l], omega, nsweeps, H->r[l]);
 }
@@ -391,26 +529,51 @@ static void coarsest_solve(hier_t *H) {
   H->u[l][0] = (h * h * H->f[l][0]) / (2.0 * H->d);
 }
 
+static void restrict_to(hier_t *H, int l, const double *r, double *fc) {
+  if (H->variant & ORC_FE_TRANSFER)
+    orc_restrict_fe(H->d, H->m[l + 1], r, fc);
+  else
+    orc_restrict_fw(H->d, H->m[l + 1], r, fc);
+}
+
+static void prolong_from(hier_t *H, int l) {
+  if (H->variant & ORC_FE_TRANSFER)
+    orc_prolong_add_fe(H->d, H->m[l + 1], H->u[l + 1], H->u[l]);
+  else
+    orc_prolong_add(H->d, H->m[l + 1], H->u[l + 1], H->u[l]);
+}
+
+/* Coarsest level: exact, or (variant) nu1 smoother sweeps from zero. */
+static void coarsest(hier_t *H, int nu1, int smoother, double omega) {
+  if (H->variant & ORC_COARSE_RELAX) {
+    H->u[H->L - 1][0] = 0.0;
+    smooth(H, H->L - 1, smoother, omega, nu1, 0);
+  } else {
+    coarsest_solve(H);
+  }
+}
+
 static void vcycle(hier_t *H, int nu1, int nu2, int smoother, double omega) {
   int d = H->d, L = H->L;
   for (int l = 0; l <= L - 2; l++) {
     if (l > 0) memset(H->u[l], 0, sizeof(double) * (size_t)npts(d, H->m[l]));
     smooth(H, l, smoother, omega, nu1, 0);
     orc_residual(d, H->m[l], H->u[l], H->f[l], H->r[l]);
-    orc_restrict_fw(d, H->m[l + 1], H->r[l], H->f[l + 1]);
+    restrict_to(H, l, H->r[l], H->f[l + 1]);
   }
-  coarsest_solve(H);
+  coarsest(H, nu1, smoother, omega);
   for (int l = L - 2; l >= 0; l--) {
-    orc_prolong_add(d, H->m[l + 1], H->u[l + 1], H->u[l]);
+    prolong_from(H, l);
     smooth(H, l, smoother, omega, nu2, 1);
   }
 }
 
 /* One V(nu1, nu2) cycle applied in place to u (level 0, side m0). */
 int orc_vcycle(int d, int m0, double *u, const double *f, int nu1, int nu2, int smoother,
-               double omega) {
+               double omega, int variant) {
   hier_t H;
   if (hier_init(&H, d, m0, u, f)) return -1;
+  H.variant = variant;
   vcycle(&H, nu1, nu2, smoother, omega);
   hier_free(&H);
   return 0;
@@ -423,9 +586,10 @@ int orc_vcycle(int d, int m0, double *u, const double *f, int nu1, int nu2, int 
  * Returns 0 converged, 1 maxit reached, -3 non-finite residual. */
 int orc_solve(int d, int m0, double *u, const double *f, int nu1, int nu2, int smoother,
               double omega, double rtol, int maxit, double res0_in, int *iters, double *relres,
-              double *res_hist) {
+              double *res_hist, int variant) {
   hier_t H;
   if (hier_init(&H, d, m0, u, f)) return -1;
+  H.variant = variant;
   orc_residual(d, m0, u, f, H.r[0]);
   double res = orc_norm2(d, m0, H.r[0]);
   double res0 = res0_in > 0.0 ? res0_in : res;
@@ -447,25 +611,28 @@ int orc_solve(int d, int m0, double *u, const double *f, int nu1, int nu2, int s
   return status;
 }
 
-/* Full multigrid (Algorithm 2): restrict f to every level by full weighting,
- * solve the coarsest level exactly, then for l = L-2 .. 0 interpolate the
+/* Full multigrid (Algorithm 2): restrict f to every level (full weighting,
+ * or the finite-element restriction for that variant), solve the coarsest
+ * level (exactly, or by the variant's relaxation), then for l = L-2 .. 0 interpolate the
  * level-(l+1) solution to level l and run one V(nu1, nu2) cycle on the
  * sub-hierarchy l .. L-1.  u (level 0) is overwritten. */
 int orc_fmg(int d, int m0, double *u, const double *f, int nu1, int nu2, int smoother,
-            double omega) {
+            double omega, int variant) {
   hier_t H;
   if (hier_init(&H, d, m0, u, f)) return -1;
+  H.variant = variant;
   int L = H.L;
-  for (int l = 0; l <= L - 2; l++) orc_restrict_fw(d, H.m[l + 1], H.f[l], H.f[l + 1]);
-  coarsest_solve(&H);
+  for (int l = 0; l <= L - 2; l++) restrict_to(&H, l, H.f[l], H.f[l + 1]);
+  coarsest(&H, nu1, smoother, omega);
   for (int l = L - 2; l >= 0; l--) {
     memset(H.u[l], 0, sizeof(double) * (size_t)npts(d, H.m[l]));
-    orc_prolong_add(d, H.m[l + 1], H.u[l + 1], H.u[l]);
+    prolong_from(&H, l);
     /* one V-cycle on levels l..L-1 with level l as the finest */
     hier_t S;
     memset(&S, 0, sizeof(S));
     S.d = d;
     S.L = L - l;
+    S.variant = variant;
     for (int q = 0; q < S.L; q++) {
       S.m[q] = H.m[l + q];
       S.u[q] = H.u[l + q];
