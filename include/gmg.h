@@ -61,8 +61,12 @@ typedef enum {
 /* Smoother (Sec. 3.2, Remark 1; Table 5).  RBGS: red-black Gauss-Seidel,
  * red = nodes whose node-index sum is even.  A forward sweep relaxes red then
  * black; a backward sweep black then red.  WJ: weighted Jacobi
- * u <- (1-omega) u + omega (h^2 f + sum of neighbours) / (2d). */
-typedef enum { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_WJ = 1 } gmg_smoother;
+ * u <- (1-omega) u + omega (h^2 f + sum of neighbours) / (2d).  MCGS: the
+ * paper's multicolour Gauss-Seidel (Remark 1), 4 colours in 2D and 8 in 3D:
+ * node (i, j[, k]) has colour (i&1) + 2(j&1) [+ 4(k&1)]; a forward sweep
+ * relaxes colours in increasing order, a backward sweep in decreasing order.
+ * MCGS plans run FP64 single problems only (GMG_ERR_UNSUPPORTED otherwise). */
+typedef enum { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_WJ = 1, GMG_SMOOTH_MCGS = 2 } gmg_smoother;
 
 /* Precision of a plan.  FP64: every level in FP64.  MIXED_FP32_IR: an FP64
  * defect-correction loop (residual, update and norm in FP64) around FP32
@@ -85,6 +89,19 @@ typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
 #define GMG_NO_FUSED_RESTRICT 0x40u /* residual + restriction as a kernel of its
                                        own instead of inside the last
                                        pre-smoothing pass (same results)      */
+/* The paper's own transfers and coarsest rule (with any smoother; FP64 single
+ * problems only, GMG_ERR_UNSUPPORTED otherwise).  Such plans run one kernel
+ * per step and level, without the fused passes, the small-level kernels or
+ * the bottom kernel. */
+#define GMG_FE_TRANSFER 0x80u       /* linear finite-element restriction and
+                                       interpolation (Sec. 4, eq. Restriction2d
+                                       and eq. Prolongation2d; 15-point in 3D)
+                                       instead of full weighting / (bi/tri)-
+                                       linear interpolation                   */
+#define GMG_COARSE_RELAX 0x100u     /* one-node coarsest level relaxed by nu1
+                                       sweeps from zero (Algorithm 1 as printed)
+                                       instead of solved exactly; differs only
+                                       for WJ                                  */
 
 typedef struct {
   int dim;                 /* 2 or 3                                            */
@@ -127,8 +144,9 @@ gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, cons
 gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f);
 
 /* Full multigrid FMG(nu1, nu2) (Algorithm 2; single-problem FP64 plans):
- * f is restricted to every level by full weighting, the one-node level is
- * solved exactly, and for each level from the coarse end the coarser result
+ * f is restricted to every level (full weighting, or the finite-element
+ * restriction with GMG_FE_TRANSFER), the one-node level is solved (exactly,
+ * or relaxed with GMG_COARSE_RELAX), and for each level from the coarse end the coarser result
  * is interpolated and one V(nu1, nu2) cycle is run on that level and the
  * ones below it.  u (output only, m0^d FP64) receives the finest result;
  * it reaches the discretisation error in one pass for smooth data.
@@ -199,18 +217,30 @@ gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages
  * nsweeps sweeps of the plan's smoother applied to the start value
  * u_in + P e_coarse (u_in NULL = zero; e_coarse NULL = no correction;
  * P = (bi/tri)linear interpolation from level+1), with right-hand side f.
- * backward selects black->red order (RBGS only).  If res_in_norm is not
- * NULL, ||f - A u_in||_2 (of the start value, e_coarse must be NULL) is
- * written there (synchronises).  u_out must not alias u_in, f or e_coarse. */
+ * backward selects the reverse colour order (RBGS: black->red; MCGS:
+ * decreasing colours).  If res_in_norm is not NULL, ||f - A u_in||_2 (of the
+ * start value, e_coarse must be NULL) is written there (synchronises).
+ * u_out must not alias u_in, f or e_coarse.  Plans with MCGS or
+ * GMG_FE_TRANSFER: FP64 only and e_coarse must be NULL (interpolate with
+ * gmg_op_prolong_add first); GMG_ERR_UNSUPPORTED otherwise. */
 gmg_status gmg_op_smooth(gmg_plan *p, int level, gmg_dtype dt, int nsweeps, int backward,
                          const void *u_in, const void *f, const void *e_coarse, void *u_out,
                          double *res_in_norm);
 
-/* Residual and full-weighting restriction (Algorithm 1, r_l = f_l - A_l u_l;
- * f_{l+1} = R r_l): f_coarse = FW(f - A u), r never stored.  level must be
- * below the coarsest. */
+/* Residual and restriction (Algorithm 1, r_l = f_l - A_l u_l;
+ * f_{l+1} = R r_l): f_coarse = R(f - A u), r never stored; R is full
+ * weighting, or with GMG_FE_TRANSFER the linear finite-element restriction
+ * (eq. Restriction2d; FP64 only).  level must be below the coarsest. */
 gmg_status gmg_op_restrict_residual(gmg_plan *p, int level, gmg_dtype dt, const void *u,
                                     const void *f, void *f_coarse);
+
+/* Interpolation and correction (Algorithm 1, u_l = u_l + P u_{l+1};
+ * eq. Prolongation2d): u_out = u_in + P e_coarse (u_in NULL = zero; u_in may
+ * equal u_out), P the plan's interpolation from level+1: (bi/tri)linear, or
+ * with GMG_FE_TRANSFER the linear finite-element one (FP64 only).  level must
+ * be below the coarsest; e_coarse must not alias u_out. */
+gmg_status gmg_op_prolong_add(gmg_plan *p, int level, gmg_dtype dt, const void *u_in,
+                              const void *e_coarse, void *u_out);
 
 /* Residual r = f - A u (r may be NULL) and its norm ||r||_2 (norm may be
  * NULL; synchronises when given). */

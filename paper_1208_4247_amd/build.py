@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgmg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GMG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["smooth.hip", "transfer.hip", "bottom.hip", "small.hip", "gmg_capi.cpp"]
+SOURCES = ["smooth.hip", "transfer.hip", "bottom.hip", "small.hip", "variant.hip", "gmg_capi.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -23,6 +23,7 @@ GMG_ERR_UNSUPPORTED = -6
 
 GMG_SMOOTH_RBGS = 0
 GMG_SMOOTH_WJ = 1
+GMG_SMOOTH_MCGS = 2
 GMG_FP64 = 0
 GMG_MIXED_FP32_IR = 1
 GMG_F64 = 0
@@ -35,11 +36,14 @@ GMG_POST_FORWARD = 0x8
 GMG_NO_TEMPORAL_BLOCKING = 0x10
 GMG_NO_FUSED_COARSE = 0x20
 GMG_NO_FUSED_RESTRICT = 0x40
+GMG_FE_TRANSFER = 0x80
+GMG_COARSE_RELAX = 0x100
 
 EXPORTED = [
     "gmg_config_default", "gmg_setup", "gmg_vcycle", "gmg_solve", "gmg_batch_solve",
     "gmg_destroy", "gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
-    "gmg_op_smooth", "gmg_op_restrict_residual", "gmg_op_residual", "gmg_profile_count",
+    "gmg_op_smooth", "gmg_op_restrict_residual", "gmg_op_residual", "gmg_op_prolong_add",
+    "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
     "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg",
 ]
@@ -105,6 +109,7 @@ def lib():
     L.gmg_op_smooth.argtypes = [vp, i, i, i, i, vp, vp, vp, vp, dp]
     L.gmg_op_restrict_residual.argtypes = [vp, i, i, vp, vp, vp]
     L.gmg_op_residual.argtypes = [vp, i, i, vp, vp, vp, dp]
+    L.gmg_op_prolong_add.argtypes = [vp, i, i, vp, vp, vp]
     L.gmg_profile_count.argtypes = [vp]
     L.gmg_profile_get.argtypes = [vp, i, ctypes.POINTER(GmgKernelStat)]
     L.gmg_profile_reset.argtypes = [vp]

@@ -290,6 +290,14 @@ gmg_status harvest(gmg_plan *p) {
   return GMG_OK;
 }
 
+// Plans that run the paper's own smoother or transfers (multicolour GS, the
+// finite-element transfers, the relaxed coarsest level) go through the
+// per-step kernels of variant.hip.
+bool cfg_variant(const gmg_config &c) {
+  return c.smoother == GMG_SMOOTH_MCGS || (c.flags & (GMG_FE_TRANSFER | GMG_COARSE_RELAX));
+}
+bool is_variant(const gmg_plan *p) { return cfg_variant(p->cfg); }
+
 // ------------------------------------------------------------------ passes
 int stages_of(const gmg_plan *p, int sweeps) {
   return p->cfg.smoother == GMG_SMOOTH_RBGS ? 2 * sweeps : sweeps;
@@ -726,6 +734,140 @@ hipError_t enqueue_fmg(gmg_plan *p, double *u, const double *f) {
   return enqueue_vcycle<double>(p, u, f, u, nullptr, nullptr);
 }
 
+// ------------------------------------------------------------------ paper variant
+// nsweeps of the plan's smoother on level l from src (NULL = zero) into dst,
+// alternating with tmp so that the last sweep lands in dst and no launch
+// reads what it writes.  Red-black and Jacobi reuse the plain passes.
+hipError_t var_smooth(gmg_plan *p, int l, int nsweeps, bool backward, const double *src,
+                      const double *f, double *dst, double *tmp, const int *active, int cls) {
+  if (p->cfg.smoother != GMG_SMOOTH_MCGS)
+    return smooth_chain<double>(p, l, nsweeps, backward, src, nullptr, f, dst, tmp, nullptr,
+                                active, cls, nullptr);
+  const int m = p->m[l];
+  const size_t bytes = npts(p->dim, m) * sizeof(double);
+  if (nsweeps == 0) {
+    if (src == dst) return hipSuccess;
+    if (!src) return launch_fill_zero(dst, bytes, p->stream);
+    return launch_copy(src, dst, bytes, active, p->stream);
+  }
+  if (nsweeps >= 2 && !tmp) return hipErrorInvalidValue;
+  const double h = 1.0 / double(m + 1);
+  const double *in = src;
+  for (int k = 1; k <= nsweeps; ++k) {
+    double *out = ((nsweeps - k) % 2 == 1) ? tmp : dst;
+    // bytes of one sweep: old values, f and the result (3D: each plane is
+    // also read once as the other half's neighbour)
+    ProfScope ps(p, cls, (double)bytes * (p->dim == 3 ? 4.0 : 3.0));
+    hipError_t e = launch_mc_sweep(p->dim, m, in, f, out, backward ? 1 : 0, h * h, active,
+                                   p->stream);
+    if (e != hipSuccess) return e;
+    in = out;
+  }
+  return hipSuccess;
+}
+
+hipError_t var_restrict(gmg_plan *p, int l, const double *u, const double *f, double *fc,
+                        const int *active, int cls) {
+  if (!(p->cfg.flags & GMG_FE_TRANSFER)) return restrict_level<double>(p, l, u, f, fc, active, cls);
+  const int m = p->m[l];
+  const double h = 1.0 / double(m + 1);
+  ProfScope ps(p, cls, (double)npts(p->dim, m) * sizeof(double) * (u ? 2 : 1) +
+                           (double)npts(p->dim, p->m[l + 1]) * sizeof(double));
+  return launch_restrict_fe(p->dim, m, p->m[l + 1], u, f, fc, 1.0 / (h * h), active, p->stream);
+}
+
+hipError_t var_prolong(gmg_plan *p, int l, const double *in, const double *ec, double *out,
+                       const int *active) {
+  const int m = p->m[l];
+  ProfScope ps(p, PC_MISC, (double)npts(p->dim, m) * sizeof(double) * (in ? 2 : 1) +
+                               (double)npts(p->dim, p->m[l + 1]) * sizeof(double));
+  if (p->cfg.flags & GMG_FE_TRANSFER)
+    return launch_prolong_fe(p->dim, m, p->m[l + 1], in, ec, out, active, p->stream);
+  return launch_prolong_add<double>(p->dim, m, p->m[l + 1], in, ec, out, active, p->stream);
+}
+
+hipError_t var_coarsest(gmg_plan *p, const double *f, double *u, const int *active) {
+  ProfScope ps(p, PC_BOTTOM, 2.0 * sizeof(double));
+  return launch_coarsest(p->dim, f, u, (p->cfg.flags & GMG_COARSE_RELAX) ? 1 : 0,
+                         p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0, p->cfg.nu1, p->cfg.omega,
+                         active, p->stream);
+}
+
+// One V-cycle (Algorithm 1) on levels s .. L-1 of a variant plan: start value
+// u_in (NULL = zero), right-hand side f_s, result u_out (may equal u_in).
+// norm_partials (s = 0 only): residual norm of u_in and the stop test first.
+hipError_t var_cycle(gmg_plan *p, int s, const double *u_in, const double *f_s, double *u_out,
+                     double *norm_partials, const int *active) {
+  LevelSet<double> &S = p->d;
+  const int L = p->L;
+  const bool bwd = !(p->cfg.flags & GMG_POST_FORWARD);
+  const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
+  hipError_t e;
+  if (norm_partials) {
+    const int m = p->m[s];
+    ResidArgs<double> r{};
+    r.u = u_in;
+    r.f = f_s;
+    r.partials = norm_partials;
+    r.active = active;
+    r.m = m;
+    r.nblocks = residual_blocks(p->dim, m);
+    const double h = 1.0 / double(m + 1);
+    r.inv_h2 = 1.0 / (h * h);
+    {
+      // the stop test's residual norm is timed with the stop test
+      ProfScope ps(p, PC_FIN, (double)npts(p->dim, m) * sizeof(double) * 2);
+      e = launch_residual<double>(p->dim, r, p->stream);
+      if (e != hipSuccess) return e;
+    }
+    ProfScope ps(p, PC_FIN, 0.0);
+    e = launch_finalize(norm_partials, r.nblocks, p->state, p->stream);
+    if (e != hipSuccess) return e;
+  }
+  if (s == L - 1) return var_coarsest(p, f_s, u_out, active);
+  for (int l = s; l <= L - 2; ++l) {
+    const double *f = l == s ? f_s : S.f[l];
+    e = var_smooth(p, l, nu1, false, l == s ? u_in : nullptr, f, S.w[l], S.t[l], active,
+                   l == 0 ? PC_PRE0 : PC_PRE_C);
+    if (e != hipSuccess) return e;
+    e = var_restrict(p, l, S.w[l], f, S.f[l + 1], active, l == 0 ? PC_RES0 : PC_RES_C);
+    if (e != hipSuccess) return e;
+  }
+  e = var_coarsest(p, S.f[L - 1], S.u[L - 1], active);
+  if (e != hipSuccess) return e;
+  for (int l = L - 2; l >= s; --l) {
+    const double *f = l == s ? f_s : S.f[l];
+    e = var_prolong(p, l, S.w[l], S.u[l + 1], S.w[l], active);
+    if (e != hipSuccess) return e;
+    e = var_smooth(p, l, nu2, bwd, S.w[l], f, l == s ? u_out : S.u[l], S.t[l], active,
+                   l == 0 ? PC_POST0 : PC_POST_C);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Full multigrid (Algorithm 2) of a variant plan.
+hipError_t var_fmg(gmg_plan *p, double *u, const double *f) {
+  LevelSet<double> &S = p->d;
+  const int L = p->L;
+  hipError_t e;
+  if (L == 1) return var_coarsest(p, f, u, nullptr);
+  for (int l = 0; l <= L - 2; ++l) {
+    e = var_restrict(p, l, nullptr, l == 0 ? f : S.f[l], S.f[l + 1], nullptr, PC_MISC);
+    if (e != hipSuccess) return e;
+  }
+  e = var_coarsest(p, S.f[L - 1], S.u[L - 1], nullptr);
+  if (e != hipSuccess) return e;
+  for (int l = L - 2; l >= 0; --l) {
+    double *ul = l == 0 ? u : S.u[l];
+    e = var_prolong(p, l, nullptr, S.u[l + 1], ul, nullptr);
+    if (e != hipSuccess) return e;
+    e = var_cycle(p, l, ul, l == 0 ? f : S.f[l], ul, nullptr, nullptr);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // ------------------------------------------------------------------ layout
 struct Layout {
   size_t total = 0;
@@ -870,7 +1012,9 @@ gmg_status validate_cfg(const gmg_config *c) {
   if (c->dim == 3 && c->levels > 10) return GMG_ERR_INVALID_ARG;  // 1023^3 max (int32 index)
   if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 8 || c->nu2 > 8)
     return GMG_ERR_INVALID_ARG;
-  if (c->smoother != GMG_SMOOTH_RBGS && c->smoother != GMG_SMOOTH_WJ) return GMG_ERR_INVALID_ARG;
+  if (c->smoother != GMG_SMOOTH_RBGS && c->smoother != GMG_SMOOTH_WJ &&
+      c->smoother != GMG_SMOOTH_MCGS)
+    return GMG_ERR_INVALID_ARG;
   if (c->smoother == GMG_SMOOTH_WJ && !(c->omega >= 0.0 && c->omega <= 1.0))
     return GMG_ERR_INVALID_ARG;
   if (c->precision != GMG_FP64 && c->precision != GMG_MIXED_FP32_IR) return GMG_ERR_INVALID_ARG;
@@ -895,6 +1039,9 @@ gmg_status init_plan_shape(gmg_plan &p, const gmg_config *cfg) {
       break;
     }
   if (p.L == 1) p.B = 1;
+  // the paper's variant has no bottom kernel: only the one-node level is
+  // handled separately
+  if (cfg_variant(p.cfg)) p.B = std::max(1, p.L - 1);
   p.smax_cap = (cfg->flags & GMG_NO_TEMPORAL_BLOCKING) ? 1 : 2;
   // chained passes need a scratch array whenever a level may run more than
   // one pass (any choice of sweeps per pass, so tuning never changes layout)
@@ -1567,6 +1714,7 @@ gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int 
   gmg_status st = validate_cfg(&c);
   if (st != GMG_OK) return st;
   if (c.precision != GMG_FP64) return GMG_ERR_UNSUPPORTED;  // batch: FP64 cycles
+  if (cfg_variant(c)) return GMG_ERR_UNSUPPORTED;
   if (c.nu1 < 1 || c.nu2 < 1) return GMG_ERR_UNSUPPORTED;
   for (int q = 0; q < n; ++q) {
     if (dims[q] != 2 && dims[q] != 3) return GMG_ERR_INVALID_ARG;
@@ -1711,6 +1859,7 @@ gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, cons
   if (levels) c.levels = levels[0];
   gmg_status st = validate_cfg(&c);
   if (st != GMG_OK) return st;
+  if (cfg_variant(c) && c.precision != GMG_FP64) return GMG_ERR_UNSUPPORTED;
   gmg_plan tmp;
   init_plan_shape(tmp, &c);
   const Layout Y = make_layout(tmp);
@@ -1790,6 +1939,10 @@ int gmg_level_side(const gmg_plan *p, int problem, int level) {
 gmg_status gmg_fmg(gmg_plan *p, double *u, const double *f) {
   if (!p || !u || !f || p->batch) return GMG_ERR_INVALID_ARG;
   if (p->cfg.precision != GMG_FP64) return GMG_ERR_UNSUPPORTED;
+  if (is_variant(p)) {
+    HIPCHK(var_fmg(p, u, f));
+    return GMG_OK;
+  }
   if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) HIPCHK(tune_plan<double>(p, u, f, nullptr));
   HIPCHK(enqueue_fmg(p, u, f));
   return GMG_OK;
@@ -1797,6 +1950,10 @@ gmg_status gmg_fmg(gmg_plan *p, double *u, const double *f) {
 
 gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f) {
   if (!p || !u || !f || p->batch) return GMG_ERR_INVALID_ARG;
+  if (is_variant(p)) {
+    HIPCHK(var_cycle(p, 0, u, f, u, nullptr, nullptr));
+    return GMG_OK;
+  }
   if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) {
     if (p->cfg.precision == GMG_FP64)
       HIPCHK(tune_plan<double>(p, u, f, nullptr));
@@ -1848,7 +2005,7 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
     gmg_plan *p;
     ~TagReset() { p->prof_tag = -1; }
   } tag_reset{p};
-  if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned) {
+  if ((p->cfg.flags & GMG_AUTOTUNE) && !p->tuned && !is_variant(p)) {
     if (p->cfg.precision == GMG_FP64)
       HIPCHK(tune_plan<double>(p, u, f, p->partials));
     else
@@ -1866,7 +2023,9 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
   for (;;) {
     for (int b = 0; b < batch; ++b, ++enq) {
       p->prof_tag = enq;
-      if (!mixed) {
+      if (is_variant(p)) {
+        HIPCHK(var_cycle(p, 0, u, f, u, p->partials, act));
+      } else if (!mixed) {
         HIPCHK(enqueue_vcycle<double>(p, u, f, u, p->partials, act));
       } else {
         // body k: x_k = x_{k-1} + e (k >= 1), r32 = f - A x_k, norm, stop
@@ -1909,7 +2068,9 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
   const SolveState st = *p->hstate;
   // the stopping body ran its first step and the stop test
   if (p->profile)
-    prune_profile(p, st.iter, (1u << PC_FIN) | (1u << (mixed ? PC_IR : PC_PRE0)));
+    prune_profile(p, st.iter,
+                  is_variant(p) ? (1u << PC_FIN)
+                                : (1u << PC_FIN) | (1u << (mixed ? PC_IR : PC_PRE0)));
   if (mixed && (st.iter % 2 == 1)) {
     // the final iterate x_iter sits in the workspace copy
     HIPCHK(launch_copy(p->x2, u, N0 * sizeof(double), nullptr, p->stream));
@@ -2035,6 +2196,32 @@ template <typename T>
 static gmg_status op_smooth_t(gmg_plan *p, int level, int nsweeps, int backward, const T *u_in,
                               const T *f, const T *ec, T *u_out, double *res_in_norm) {
   LevelSet<T> &S = levels_of<T>(p);
+  if (is_variant(p) && p->cfg.smoother == GMG_SMOOTH_MCGS) {
+    if constexpr (sizeof(T) != 8) {
+      return GMG_ERR_UNSUPPORTED;
+    } else {
+      if (ec) return GMG_ERR_UNSUPPORTED;
+      double *tmp = level < (int)S.t.size() ? S.t[level] : nullptr;
+      if (nsweeps >= 2 && !tmp) return GMG_ERR_UNSUPPORTED;
+      const int m = p->m[level];
+      const int nb = residual_blocks(p->dim, m);
+      if (res_in_norm) {
+        const double h = 1.0 / double(m + 1);
+        ResidArgs<double> r{u_in, f, nullptr, p->partials, nullptr, m, nb, 1.0 / (h * h)};
+        HIPCHK(launch_residual<double>(p->dim, r, p->stream));
+      }
+      HIPCHK(var_smooth(p, level, nsweeps, backward != 0, u_in, f, u_out, tmp, nullptr, PC_MISC));
+      if (res_in_norm) {
+        HIPCHK(launch_reduce_norm(p->partials, nb, p->scalar, p->stream));
+        HIPCHK(hipMemcpyAsync(p->hscalar, p->scalar, sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+        *res_in_norm = *p->hscalar;
+      }
+      return GMG_OK;
+    }
+  }
+  if (is_variant(p) && ec) return GMG_ERR_UNSUPPORTED;
   T *tmp = level < (int)S.t.size() ? S.t[level] : nullptr;
   const int smax = p->ch[level][ec ? 1 : 0].smax;
   const int K = nsweeps == 0 ? 0 : (nsweeps + smax - 1) / smax;
@@ -2075,12 +2262,34 @@ gmg_status gmg_op_restrict_residual(gmg_plan *p, int level, gmg_dtype dt, const 
   gmg_status s = check_level(p, level, dt);
   if (s != GMG_OK) return s;
   if (level + 1 >= p->L || !u || !f || !f_coarse) return GMG_ERR_INVALID_ARG;
+  if (p->cfg.flags & GMG_FE_TRANSFER) {
+    if (dt != GMG_F64) return GMG_ERR_UNSUPPORTED;
+    HIPCHK(var_restrict(p, level, (const double *)u, (const double *)f, (double *)f_coarse,
+                        nullptr, PC_MISC));
+    return GMG_OK;
+  }
   if (dt == GMG_F64)
     HIPCHK(restrict_level<double>(p, level, (const double *)u, (const double *)f,
                                   (double *)f_coarse, nullptr, PC_MISC));
   else
     HIPCHK(restrict_level<float>(p, level, (const float *)u, (const float *)f, (float *)f_coarse,
                                  nullptr, PC_MISC));
+  return GMG_OK;
+}
+
+gmg_status gmg_op_prolong_add(gmg_plan *p, int level, gmg_dtype dt, const void *u_in,
+                              const void *e_coarse, void *u_out) {
+  gmg_status s = check_level(p, level, dt);
+  if (s != GMG_OK) return s;
+  if (level + 1 >= p->L || !e_coarse || !u_out || e_coarse == u_out) return GMG_ERR_INVALID_ARG;
+  if (dt == GMG_F64) {
+    HIPCHK(var_prolong(p, level, (const double *)u_in, (const double *)e_coarse, (double *)u_out,
+                       nullptr));
+    return GMG_OK;
+  }
+  if (p->cfg.flags & GMG_FE_TRANSFER) return GMG_ERR_UNSUPPORTED;
+  HIPCHK(launch_prolong_add<float>(p->dim, p->m[level], p->m[level + 1], (const float *)u_in,
+                                   (const float *)e_coarse, (float *)u_out, nullptr, p->stream));
   return GMG_OK;
 }
 

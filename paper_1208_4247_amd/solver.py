@@ -35,7 +35,8 @@ class Plan:
                  flags: int = 0):
         L = capi.lib()
         cfg = capi.config_default(dim, levels)
-        cfg.smoother = {"rbgs": capi.GMG_SMOOTH_RBGS, "wj": capi.GMG_SMOOTH_WJ}[smoother]
+        cfg.smoother = {"rbgs": capi.GMG_SMOOTH_RBGS, "wj": capi.GMG_SMOOTH_WJ,
+                        "mcgs": capi.GMG_SMOOTH_MCGS}[smoother]
         cfg.nu1, cfg.nu2 = int(nu1), int(nu2)
         cfg.omega = float(omega)
         cfg.precision = {"fp64": capi.GMG_FP64, "mixed": capi.GMG_MIXED_FP32_IR}[precision]
@@ -122,6 +123,12 @@ class Plan:
         capi.check(capi.lib().gmg_op_restrict_residual(self._plan, int(level), dt, _ptr(u), _ptr(f),
                                                        _ptr(fc)), "gmg_op_restrict_residual")
 
+    def op_prolong_add(self, level, u_in, e_coarse, u_out):
+        dt = capi.GMG_F64 if e_coarse.dtype == torch.float64 else capi.GMG_F32
+        capi.check(capi.lib().gmg_op_prolong_add(self._plan, int(level), dt, _ptr(u_in),
+                                                 _ptr(e_coarse), _ptr(u_out)),
+                   "gmg_op_prolong_add")
+
     def op_residual(self, level, u, f, r=None, want_norm=True):
         dt = capi.GMG_F64 if f.dtype == torch.float64 else capi.GMG_F32
         nrm = ctypes.c_double(0.0)
@@ -164,7 +171,8 @@ class BatchPlan:
         dims = [int(d) for d, _ in problems]
         levels = [int(lv) for _, lv in problems]
         cfg = capi.config_default(dims[0], levels[0])
-        cfg.smoother = {"rbgs": capi.GMG_SMOOTH_RBGS, "wj": capi.GMG_SMOOTH_WJ}[smoother]
+        cfg.smoother = {"rbgs": capi.GMG_SMOOTH_RBGS, "wj": capi.GMG_SMOOTH_WJ,
+                        "mcgs": capi.GMG_SMOOTH_MCGS}[smoother]
         cfg.nu1, cfg.nu2 = int(nu1), int(nu2)
         cfg.omega = float(omega)
         cfg.flags = int(flags)

@@ -108,3 +108,22 @@ def test_setup_null_checks(capi):
     assert lib.gmg_destroy(None) == capi.GMG_ERR_INVALID_ARG
     assert lib.gmg_plan_workspace_bytes(None) == 0
     assert lib.gmg_level_side(None, 0, 0) == -1
+
+
+def test_paper_variant_rejected_where_unsupported(capi):
+    """The paper's smoother and transfers run FP64 single problems only."""
+    for smoother, flags in ((capi.GMG_SMOOTH_MCGS, 0), (capi.GMG_SMOOTH_RBGS, capi.GMG_FE_TRANSFER),
+                            (capi.GMG_SMOOTH_WJ, capi.GMG_COARSE_RELAX)):
+        cfg = capi.config_default(3, 5)
+        cfg.smoother = smoother
+        cfg.flags = flags
+        s, n = capi.workspace_bytes(cfg)
+        assert s == capi.GMG_OK and n > 0
+        cfg.precision = capi.GMG_MIXED_FP32_IR
+        assert capi.workspace_bytes(cfg)[0] == capi.GMG_ERR_UNSUPPORTED
+        cfg.precision = capi.GMG_FP64
+        s, _ = capi.workspace_bytes(cfg, nproblems=2, dims=[3, 2], levels=[5, 6])
+        assert s == capi.GMG_ERR_UNSUPPORTED
+    cfg = capi.config_default(2, 5)
+    cfg.smoother = 3
+    assert capi.workspace_bytes(cfg)[0] == capi.GMG_ERR_INVALID_ARG

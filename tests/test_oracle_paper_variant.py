@@ -218,3 +218,28 @@ def test_coarse_relax_variant_on_one_node():
         u = oracle.vcycle(np.zeros((1, 1, 1)), f, 1, 1, smoother=s, omega=w,
                           variant=oracle.COARSE_RELAX)
         assert u[0, 0, 0] == pytest.approx(want, rel=1e-15)
+
+
+def test_2d_multicolour_cycle_blind_to_transfer_diagonals():
+    """In 2D the finite-element and full-weighting transfers differ only on the
+    fine nodes with both indices odd: the restriction weights the diagonal
+    neighbours differently and the interpolation fills those nodes
+    differently.  Those nodes form colour 3, the last colour of the forward
+    sweep (zero residual there) and the first of the backward sweep (their
+    interpolated values are overwritten before anything reads them), so
+    multicolour V-cycles are the same with either pair, while red-black ones
+    are not.  In 3D the colour of the (1,1,0)-type diagonals is not last, and
+    the cycles differ."""
+    f = wl.rhs_uniform(2, 63, seed=15)
+    u0 = wl.rhs_uniform(2, 63, seed=16) * 1e-3
+    a = oracle.vcycle(u0, f, 1, 1, smoother=oracle.MCGS)
+    b = oracle.vcycle(u0, f, 1, 1, smoother=oracle.MCGS, variant=oracle.FE_TRANSFER)
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
+    a = oracle.vcycle(u0, f, 1, 1, smoother=oracle.RBGS)
+    b = oracle.vcycle(u0, f, 1, 1, smoother=oracle.RBGS, variant=oracle.FE_TRANSFER)
+    assert np.max(np.abs(a - b)) > 1e-3 * np.max(np.abs(a))
+    f3 = wl.rhs_uniform(3, 15, seed=17)
+    a = oracle.vcycle(np.zeros_like(f3), f3, 1, 1, smoother=oracle.MCGS)
+    b = oracle.vcycle(np.zeros_like(f3), f3, 1, 1, smoother=oracle.MCGS,
+                      variant=oracle.FE_TRANSFER)
+    assert np.max(np.abs(a - b)) > 1e-3 * np.max(np.abs(a))
