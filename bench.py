@@ -44,6 +44,17 @@ WORKLOADS = {
     "poisson3d_255_sine_fmg22": dict(dim=3, L=8, rhs="fmg", prec="fp64"),
     "poisson3d_1023_sine_fmg22": dict(dim=3, L=10, rhs="fmg", prec="fp64"),
     "poisson2d_4095_sine_fmg22": dict(dim=2, L=12, rhs="fmg", prec="fp64"),
+    # the paper's own method (multicolour GS, finite-element transfers, V(1,1),
+    # tol 1e-6, u = prod sin(pi x_i)): the configuration of its Tables 5, 7, 8
+    "poisson2d_4095_paper_mcgs_v11": dict(dim=2, L=12, rhs="model", prec="fp64", nu=1,
+                                          smoother="mcgs", flags=0x80, rtol=1e-6,
+                                          paper_s=0.4339),
+    "poisson3d_255_paper_mcgs_v11": dict(dim=3, L=8, rhs="model", prec="fp64", nu=1,
+                                         smoother="mcgs", flags=0x80, rtol=1e-6, paper_s=0.7287),
+    "poisson3d_255_paper_fmg33": dict(dim=3, L=8, rhs="fmg", prec="fp64", nu=3,
+                                      smoother="mcgs", flags=0x80, paper_s=0.1456),
+    "poisson2d_4095_paper_fmg12": dict(dim=2, L=12, rhs="fmg", prec="fp64", nu1=1, nu2=2,
+                                       smoother="mcgs", flags=0x80, paper_s=0.09167),
 }
 DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
 
@@ -61,27 +72,34 @@ def make_rhs(spec):
         return wl.rhs_sine(d, m)
     if spec["rhs"] == "uniform":
         return wl.rhs_uniform(d, m, 3)
+    if spec["rhs"] == "model":
+        return d * math.pi ** 2 * wl.sine_product(d, m)
     raise ValueError(spec["rhs"])
 
 
-def cpu_baseline(spec, f, budget_s=30.0):
-    """The FP64 CPU oracle (untuned) solving the same workload on the host
-    cores, bounded in time: full solve when it fits, else a fixed number of
-    V-cycles scaled to unknowns/s at the GPU's cycle count."""
+def cpu_baseline(spec, f, gpu_iters, budget_s=30.0):
+    """The FP64 CPU oracle (untuned) solving the same workload with the same
+    cycle on the host cores, bounded in time: the full solve when it fits,
+    else a few V-cycles scaled to unknowns/s at the GPU's cycle count."""
     import oracle
 
     oracle.build()
     threads = min(16, os.cpu_count() or 1)
     oracle.set_threads(threads)
-    m = f.shape[0]
     N = f.size
+    nu = spec.get("nu", 2)
+    smoother = {"rbgs": oracle.RBGS, "wj": oracle.WJ, "mcgs": oracle.MCGS}[
+        spec.get("smoother", "rbgs")]
+    variant = oracle.FE_TRANSFER if spec.get("flags", 0) & 0x80 else 0
+    omega = 6.0 / 7.0 if f.ndim == 3 else 0.8
+    kw = dict(nu1=nu, nu2=nu, smoother=smoother, omega=omega, variant=variant)
+    rtol = spec.get("rtol", 1e-10)
     t0 = time.perf_counter()
-    u = oracle.vcycle(f * 0.0, f)
+    u = oracle.vcycle(f * 0.0, f, **kw)
     t_cycle = time.perf_counter() - t0
-    est = t_cycle * 12
-    if est <= budget_s:
+    if t_cycle * gpu_iters <= budget_s:
         t0 = time.perf_counter()
-        _, it, rel, st, _ = oracle.solve(f, rtol=1e-10)
+        _, it, rel, st, _ = oracle.solve(f, rtol=rtol, **kw)
         t = time.perf_counter() - t0
         return dict(value=N / t, unit="unknowns/s", cores=oracle.num_threads(), kind="oracle",
                     sample="full solve of the same workload (%d V-cycles to relres %.1e), %.2f s"
@@ -89,11 +107,12 @@ def cpu_baseline(spec, f, budget_s=30.0):
     ncyc = max(1, min(int(budget_s / t_cycle), 20))
     t0 = time.perf_counter()
     for _ in range(ncyc):
-        u = oracle.vcycle(u, f)
+        u = oracle.vcycle(u, f, **kw)
     t = (time.perf_counter() - t0) / ncyc
-    return dict(value=N / (t * 12), unit="unknowns/s", cores=oracle.num_threads(), kind="oracle",
-                sample="%d V-cycles of the same workload at %.3f s each, scaled to 12 cycles"
-                % (ncyc, t))
+    return dict(value=N / (t * gpu_iters), unit="unknowns/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample="%d V-cycles of the same workload at %.3f s each, scaled to the GPU's %d "
+                "cycles" % (ncyc, t, gpu_iters))
 
 
 def measured_traffic(workload, cls, tile):
@@ -131,16 +150,18 @@ def bench_fmg(args, spec):
     from paper_1208_4247_amd.solver import Plan
 
     d, L = spec["dim"], spec["L"]
-    nu1 = spec.get("nu", 2) if args.nu1 is None else args.nu1
-    nu2 = spec.get("nu", 2) if args.nu2 is None else args.nu2
+    nu1 = spec.get("nu1", spec.get("nu", 2)) if args.nu1 is None else args.nu1
+    nu2 = spec.get("nu2", spec.get("nu", 2)) if args.nu2 is None else args.nu2
+    smoother = spec.get("smoother", "rbgs")
     m = (1 << L) - 1
     N = m ** d
+    n = m + 1
     h = 1.0 / (m + 1)
     torch.cuda.set_device(0)
     phi = wl.sine_product_device(d, m, "cuda")
     f = (d * math.pi ** 2) * phi
-    flags = args.flags | (0 if args.no_autotune else capi.GMG_AUTOTUNE)
-    plan = Plan(d, L, nu1=nu1, nu2=nu2, flags=flags)
+    flags = args.flags | spec.get("flags", 0) | (0 if args.no_autotune else capi.GMG_AUTOTUNE)
+    plan = Plan(d, L, nu1=nu1, nu2=nu2, flags=flags, smoother=smoother)
     u = torch.empty_like(f)
     for _ in range(max(1, args.warmup)):
         plan.fmg(u, f)
@@ -162,10 +183,20 @@ def bench_fmg(args, spec):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
-                   "cycle": "FMG(%d,%d) red-black GS" % (nu1, nu2), "l2h_error": err,
-                   "discretisation_error": disc, "error_ratio": err / disc},
+                   "cycle": "FMG(%d,%d) %s" % (nu1, nu2, cycle_name(smoother, spec)),
+                   "l2h_error": err, "discretisation_error": disc, "error_ratio": err / disc,
+                   # the norm of the paper's FMG tables: (sum e^2 / (n+1)^d)^(1/2)
+                   "paper_norm_error": err * (n / (n + 1)) ** (d / 2)},
     }
+    if "paper_s" in spec:
+        line["config"]["paper_gtx480_s"] = spec["paper_s"]
     print(json.dumps(line), flush=True)
+
+
+def cycle_name(smoother, spec):
+    if smoother == "mcgs":
+        return "%d-colour GS, finite-element transfers" % (4 if spec["dim"] == 2 else 8)
+    return "weighted Jacobi" if smoother == "wj" else "red-black GS"
 
 
 def bench_batch(args):
@@ -315,10 +346,11 @@ def main():
     else:
         f = torch.from_numpy(f_host).cuda()
     u = torch.zeros_like(f)
-    flags = args.flags | capi.GMG_PROFILE
+    flags = args.flags | capi.GMG_PROFILE | spec.get("flags", 0)
     if not args.no_autotune:
         flags |= capi.GMG_AUTOTUNE
     smoother = spec.get("smoother", "rbgs")
+    rtol = spec.get("rtol", 1e-10)
     plan = Plan(d, L, precision=spec["prec"], flags=flags, nu1=nu, nu2=nu, inner_cycles=inner,
                 smoother=smoother)
     print("# workload %s: %d^%d, plan workspace %.1f MB" % (args.workload, m, d,
@@ -327,7 +359,7 @@ def main():
     # warm-up (the first solve also runs the tile autotuner)
     for _ in range(args.warmup):
         u.zero_()
-        st, it, rel = plan.solve(u, f, rtol=1e-10)
+        st, it, rel = plan.solve(u, f, rtol=rtol)
     torch.cuda.synchronize()
     # timed region: hipEvents only around the level-0 smoothing passes
     smoothers = ["smooth_pre_l0", "smooth_post_l0"]
@@ -339,7 +371,7 @@ def main():
         u.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, it, rel = plan.solve(u, f, rtol=1e-10)
+        st, it, rel = plan.solve(u, f, rtol=rtol)
         torch.cuda.synchronize()
         t_total += time.perf_counter() - t0
         iters.append(it)
@@ -348,8 +380,8 @@ def main():
     value = N / (t_total / args.steps)
     dom = max(smoothers, key=lambda k: prof[k]["ms"])
     pv = prof[dom]
-    tile = plan.get_tile(0, 0 if dom == "smooth_pre_l0" else 1)
-    traffic = measured_traffic(args.workload, dom, tile)
+    tile = None if smoother == "mcgs" else plan.get_tile(0, 0 if dom == "smooth_pre_l0" else 1)
+    traffic = measured_traffic(args.workload, dom, tile) if tile else None
     achieved = pv["bytes"] / (pv["ms"] * 1e-3) / 1e9 if pv["ms"] > 0 else 0.0
     avg_us = 1e3 * pv["ms"] / max(pv["launches"], 1)
     bytes_per_launch = pv["bytes"] / max(pv["launches"], 1)
@@ -361,7 +393,7 @@ def main():
     plan.profile_reset()
     for _ in range(2):
         u.zero_()
-        plan.solve(u, f, rtol=1e-10)
+        plan.solve(u, f, rtol=rtol)
     full = plan.profile()
     for k, v in full.items():
         if v["launches"]:
@@ -369,7 +401,7 @@ def main():
                 k, v["launches"], 1e3 * v["ms"] / v["launches"],
                 v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0), flush=True)
     line = {
-        "metric": "fine-grid unknowns/s to 1e-10 rel. residual; smoother HBM GB/s % of peak",
+        "metric": "fine-grid unknowns/s to %g rel. residual; smoother HBM GB/s %% of peak" % rtol,
         "value": value,
         "unit": "unknowns/s",
         "n_gpus": 1,
@@ -382,20 +414,22 @@ def main():
         "dtype": "f64" if spec["prec"] == "fp64" else "f32-in-f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
-                   "cycle": "V(%d,%d) %s" % (nu, nu, "weighted Jacobi" if smoother == "wj"
-                                             else "red-black GS"),
-                   "rtol": 1e-10, "iters": iters[-1]},
+                   "cycle": "V(%d,%d) %s" % (nu, nu, cycle_name(smoother, spec)),
+                   "rtol": rtol, "iters": iters[-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch,
-                     "tile": {"stages": tile[0], "variant": tile[1], "tz": tile[2]},
+                     "tile": ({"stages": tile[0], "variant": tile[1], "tz": tile[2]} if tile
+                              else None),
                      "timer": "HIP events recorded by each dispatch of the kernel"},
     }
+    if "paper_s" in spec:
+        line["config"]["paper_gtx480_s"] = spec["paper_s"]
     if spec["prec"] == "mixed":
         line["config"].update(compare_fp64(args, spec, plan, u, f, ms_per_step))
         line["config"]["inner_cycles"] = inner
     if not args.no_cpu_baseline and f_host is not None:
-        line["cpu_baseline"] = cpu_baseline(spec, f_host)
+        line["cpu_baseline"] = cpu_baseline(spec, f_host, iters[-1])
     print(json.dumps(line), flush=True)
 
 

@@ -753,14 +753,17 @@ hipError_t var_smooth(gmg_plan *p, int l, int nsweeps, bool backward, const doub
   if (nsweeps >= 2 && !tmp) return hipErrorInvalidValue;
   const double h = 1.0 / double(m + 1);
   const double *in = src;
+  const int parts = p->dim == 3 ? 2 : 1;
   for (int k = 1; k <= nsweeps; ++k) {
     double *out = ((nsweeps - k) % 2 == 1) ? tmp : dst;
-    // bytes of one sweep: old values, f and the result (3D: each plane is
-    // also read once as the other half's neighbour)
-    ProfScope ps(p, cls, (double)bytes * (p->dim == 3 ? 4.0 : 3.0));
-    hipError_t e = launch_mc_sweep(p->dim, m, in, f, out, backward ? 1 : 0, h * h, active,
-                                   p->stream);
-    if (e != hipSuccess) return e;
+    for (int part = 0; part < parts; ++part) {
+      // algorithmic bytes of a sweep: old values and f read, result written
+      // once (3D: half of them in each part)
+      ProfScope ps(p, cls, (double)bytes * 3.0 / parts);
+      hipError_t e = launch_mc_sweep(p->dim, m, in, f, out, backward ? 1 : 0, h * h, active,
+                                     p->stream, part);
+      if (e != hipSuccess) return e;
+    }
     in = out;
   }
   return hipSuccess;

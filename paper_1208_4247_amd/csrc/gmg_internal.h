@@ -281,12 +281,14 @@ hipError_t launch_reduce_norm(const double *partials, int n, double *out, hipStr
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, const int *active, hipStream_t s);
 
 // The paper's smoother and transfers (FP64): one multicolour Gauss-Seidel
-// sweep src -> dst (src NULL = zero start; dst must differ from src and f),
+// sweep src -> dst (src NULL = zero start; dst must differ from src and f;
+// in 3D a sweep is two launches, part 0 then part 1, each relaxing the
+// planes of one node-index parity; part is ignored in 2D),
 // the fused residual + finite-element restriction (u NULL = zero iterate),
 // the finite-element interpolation out = in + P ec (in NULL = zero; in may
 // equal out), and the one-node coarsest level.
 hipError_t launch_mc_sweep(int dim, int m, const double *src, const double *f, double *dst,
-                           int backward, double h2, const int *active, hipStream_t s);
+                           int backward, double h2, const int *active, hipStream_t s, int part);
 hipError_t launch_restrict_fe(int dim, int m, int mc, const double *u, const double *f, double *fc,
                               double inv_h2, const int *active, hipStream_t s);
 hipError_t launch_prolong_fe(int dim, int m, int mc, const double *in, const double *ec,

@@ -349,7 +349,7 @@ hipError_t mc_sweep_dim(McArgs a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_mc_sweep(int dim, int m, const double *src, const double *f, double *dst,
-                           int backward, double h2, const int *active, hipStream_t s) {
+                           int backward, double h2, const int *active, hipStream_t s, int part) {
   if (m < 1 || !f || !dst || dst == src || dst == f) return hipErrorInvalidValue;
   McArgs a{};
   a.src = src;
@@ -362,12 +362,13 @@ hipError_t launch_mc_sweep(int dim, int m, const double *src, const double *f, d
   if (dim == 2) return mc_sweep_dim<2>(a, s);
   // forward: planes of even node index, then odd; backward: odd, then even
   const int first = backward ? 1 : 0;
-  a.pz = first;
-  a.zsrc = src;  // the other planes still hold their old values
-  hipError_t e = mc_sweep_dim<3>(a, s);
-  if (e != hipSuccess) return e;
-  a.pz = 1 - first;
-  a.zsrc = dst;  // the planes just updated
+  if (part == 0) {
+    a.pz = first;
+    a.zsrc = src;  // the other planes still hold their old values
+  } else {
+    a.pz = 1 - first;
+    a.zsrc = dst;  // the planes the first part updated
+  }
   return mc_sweep_dim<3>(a, s);
 }
 
