@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rb_pass_restrict_l0_poisson3d_255_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_255_traffic.md")
 
 WORKLOADS = {
     # name: dim, levels, right-hand side, precision, sweeps nu1 = nu2, FP32
@@ -116,26 +116,28 @@ def cpu_baseline(spec, f, gpu_iters, budget_s=30.0):
 
 
 def measured_traffic(workload, cls, tile):
-    """HBM bytes per launch of kernel class `cls` from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None
-    when the summary is for another workload, kernel source or tile."""
+    """HBM bytes per launch of the level-0 pass class `cls` (smooth_pre_l0 /
+    smooth_post_l0) with tile (stages, variant, tz), from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled
+    by a plain copy; one entry per autotuner candidate), or None when the
+    summary is for another workload or kernel source."""
     import hashlib
 
-    if workload != DEFAULT or not os.path.exists(TRAFFIC_PROFILE):
+    if workload != DEFAULT or tile is None or not os.path.exists(TRAFFIC_PROFILE):
         return None
     line = [l for l in open(TRAFFIC_PROFILE) if l.startswith("traffic-json: ")]
     if not line:
         return None
     rec = json.loads(line[-1][len("traffic-json: "):])
     csrc = os.path.join(ROOT, "paper_1208_4247_amd", "csrc")
-    for name, key in (("smooth.hip", "smooth_hip_sha256"), ("transfer.hip", "transfer_hip_sha256")):
+    for name, digest in rec.get("sources_sha256", {}).items():
         with open(os.path.join(csrc, name), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != rec.get(key):
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
                 return None
-    e = rec["entries"].get(cls)
-    if not e or tile is None or (e.get("stages"), e.get("variant"), e.get("tz")) != tuple(tile):
+    role = {"smooth_pre_l0": "pre", "smooth_post_l0": "post"}.get(cls)
+    if role is None:
         return None
-    return e["traffic_bytes"]
+    return rec["tiles"].get("%s|%d|%d|%d" % ((role,) + tuple(tile)))
 
 
 def bench_fmg(args, spec):
@@ -381,7 +383,6 @@ def main():
     dom = max(smoothers, key=lambda k: prof[k]["ms"])
     pv = prof[dom]
     tile = None if smoother == "mcgs" else plan.get_tile(0, 0 if dom == "smooth_pre_l0" else 1)
-    traffic = measured_traffic(args.workload, dom, tile) if tile else None
     achieved = pv["bytes"] / (pv["ms"] * 1e-3) / 1e9 if pv["ms"] > 0 else 0.0
     avg_us = 1e3 * pv["ms"] / max(pv["launches"], 1)
     bytes_per_launch = pv["bytes"] / max(pv["launches"], 1)
@@ -395,6 +396,10 @@ def main():
         u.zero_()
         plan.solve(u, f, rtol=rtol)
     full = plan.profile()
+    # the counter table covers the plain passes; a pre-smoothing pass with the
+    # restriction folded in (no separate restriction launches) is not in it
+    fused_pre = dom == "smooth_pre_l0" and full["resid_restrict_l0"]["launches"] == 0
+    traffic = None if fused_pre else measured_traffic(args.workload, dom, tile)
     for k, v in full.items():
         if v["launches"]:
             print("#   %-22s launches %6d  avg %9.3f us  alg %8.1f GB/s" % (

@@ -83,6 +83,51 @@ def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=Non
     return rows
 
 
+TUNER_TZ = (4, 8, 16, 32, 64, 0)  # the z-chunks the autotuner tries (0: automatic)
+
+
+def traffic_table(dim, m):
+    """Every tile candidate the autotuner tries for the level-0 red-black
+    passes of a V(2,2) cycle -- pre-smoothing with the norm partials of the
+    start value, post-smoothing with the interpolated correction -- launched
+    twice each in a fixed order, with one manifest line per candidate.  Under
+    a hardware-counter profiler (FETCH_SIZE, WRITE_SIZE) the k_rb_pass
+    dispatches map two by two onto the manifest, giving the HBM bytes of
+    every candidate the cycle may run."""
+    L = (m + 1).bit_length() - 1
+    plan = Plan(dim, L, nu1=2, nu2=2)
+    mc = (m - 1) // 2
+    g = torch.Generator(device="cuda").manual_seed(0)
+    f = torch.rand((m,) * dim, dtype=torch.float64, device="cuda", generator=g)
+    u = torch.rand((m,) * dim, dtype=torch.float64, device="cuda", generator=g) * 1e-3
+    o = torch.empty_like(u)
+    e = torch.rand((mc,) * dim, dtype=torch.float64, device="cuda", generator=g) * 1e-3
+    for role in ("pre", "post"):
+        for st in (2, 4):
+            nsw = st // 2
+            for v in range(plan.tile_variants(st)):
+                seen = set()
+                for tz in TUNER_TZ:
+                    try:
+                        plan.set_tile(0, st, v, tz)
+                    except Exception:
+                        continue  # more workgroups than the partial-sum buffer holds
+                    tzv = plan.get_tile(0, 0)[2]
+                    if tzv in seen:
+                        continue
+                    seen.add(tzv)
+                    if role == "pre":
+                        fn = lambda: plan.op_smooth(0, nsw, False, u, f, None, o, want_norm=True)
+                    else:
+                        fn = lambda: plan.op_smooth(0, nsw, True, u, f, e, o)
+                    print(json.dumps(dict(manifest=role, dim=dim, m=m, stages=st, variant=v,
+                                          tz=tzv, launches=2)), flush=True)
+                    fn()
+                    fn()
+    torch.cuda.synchronize()
+    plan.close()
+
+
 def copy_calibration(mib, reps=20):
     """A plain device copy of known size (torch's copy kernel): the yardstick
     that converts the HBM byte counters of a profiler into bytes, and the
@@ -112,7 +157,14 @@ def main():
     ap.add_argument("--variants", type=int, nargs="+", default=None)
     ap.add_argument("--kinds", nargs="+", default=["plain", "zero", "prolong", "prolong_bwd"])
     ap.add_argument("--no-transfers", action="store_true")
+    ap.add_argument("--traffic-table", action="store_true",
+                    help="launch every autotuner candidate of the level-0 passes twice "
+                    "(for a counter profiler)")
     a = ap.parse_args()
+    if a.traffic_table:
+        for m in a.m:
+            traffic_table(a.dim, m)
+        return
     if a.copy_mib:
         copy_calibration(a.copy_mib, a.reps)
         return
