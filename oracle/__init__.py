@@ -216,6 +216,25 @@ def fmg(f, nu1=1, nu2=1, smoother=RBGS, omega=0.8, variant=0) -> np.ndarray:
     return u
 
 
+def dst_solve(f: np.ndarray) -> np.ndarray:
+    """Exact solution of A u = f (Sec. 2.2 scheme, zero Dirichlet data) by the
+    discrete sine transform: the sine modes prod_i sin(k_i pi x_i) are the
+    eigenvectors of A with eigenvalues sum_i (4/h^2) sin^2(k_i pi h/2), so
+    u = S^-1 (S f / lambda) with S the DST-I along every axis (scipy's
+    transform as a library step).  The direct method of the paper's FFT
+    comparison (Sec. 5.4, Tables 12-15)."""
+    import scipy.fft
+
+    d, m = f.ndim, f.shape[0]
+    h = 1.0 / (m + 1)
+    lam1 = 4.0 / h ** 2 * np.sin(np.arange(1, m + 1) * np.pi * h / 2) ** 2
+    lam = lam1[:, None] + lam1[None, :]
+    if d == 3:
+        lam = lam[:, :, None] + lam1[None, None, :]
+    fh = scipy.fft.dstn(np.asarray(f, dtype=np.float64), type=1)
+    return scipy.fft.idstn(fh / lam, type=1)
+
+
 def solve(f, u0=None, nu1=2, nu2=2, smoother=RBGS, omega=0.8, rtol=1e-10, maxit=100,
           res0=0.0, variant=0):
     """Returns (u, iters, relres, status, res_hist)."""
