@@ -55,6 +55,10 @@ WORKLOADS = {
                                       smoother="mcgs", flags=0x80, paper_s=0.1456),
     "poisson2d_4095_paper_fmg12": dict(dim=2, L=12, rhs="fmg", prec="fp64", nu1=1, nu2=2,
                                        smoother="mcgs", flags=0x80, paper_s=0.09167),
+    # exact solve by the sine transform (the paper's FFT comparison, Tables 12-15)
+    "poisson2d_4095_sine_dst": dict(dim=2, L=12, rhs="dst", prec="fp64", paper_s=0.1364),
+    "poisson3d_255_sine_dst": dict(dim=3, L=8, rhs="dst", prec="fp64", paper_s=0.1893),
+    "poisson3d_1023_sine_dst": dict(dim=3, L=10, rhs="dst", prec="fp64"),
 }
 DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
 
@@ -195,6 +199,48 @@ def bench_fmg(args, spec):
     print(json.dumps(line), flush=True)
 
 
+def bench_dst(args, spec):
+    """One exact solve by the sine transform of -Lap u = d pi^2 prod sin(pi x_i)
+    (gmg_dst_solve): time per solve and the L2_h error against the exact u,
+    which is the paper's FFT column (Tables 12, 14)."""
+    import torch
+
+    from paper_1208_4247_amd import workloads as wl
+    from paper_1208_4247_amd.solver import DstSolver
+
+    d, L = spec["dim"], spec["L"]
+    m = (1 << L) - 1
+    N = m ** d
+    h = 1.0 / (m + 1)
+    torch.cuda.set_device(0)
+    phi = wl.sine_product_device(d, m, "cuda")
+    f = (d * math.pi ** 2) * phi
+    solver = DstSolver(d, L)
+    u = torch.empty_like(f)
+    for _ in range(max(1, args.warmup)):
+        solver.solve(u, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(u, f)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    err = float(torch.sqrt(h ** d * torch.sum((u - phi) ** 2)))
+    line = {
+        "metric": "fine-grid unknowns/s, one exact sine-transform solve",
+        "value": N / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
+                   "method": "DST-I along every axis (rocFFT batched real FFTs), eigenvalue "
+                             "division, inverse", "l2h_error": err,
+                   "workspace_MB": solver.workspace.numel() / 1e6},
+    }
+    if "paper_s" in spec:
+        line["config"]["paper_gtx480_cufft_s"] = spec["paper_s"]
+    print(json.dumps(line), flush=True)
+
+
 def cycle_name(smoother, spec):
     if smoother == "mcgs":
         return "%d-colour GS, finite-element transfers" % (4 if spec["dim"] == 2 else 8)
@@ -332,6 +378,8 @@ def main():
         return bench_batch(args)
     if spec["rhs"] == "fmg":
         return bench_fmg(args, spec)
+    if spec["rhs"] == "dst":
+        return bench_dst(args, spec)
     if args.nu1 is not None or args.nu2 is not None:
         sys.exit("bench.py: --nu1/--nu2 apply to the FMG workloads only")
     d, L = spec["dim"], spec["L"]

@@ -248,6 +248,33 @@ gmg_status gmg_op_residual(gmg_plan *p, int level, gmg_dtype dt, const void *u, 
                            void *r, double *norm);
 
 /* ---------------------------------------------------------------------- */
+/* Exact discrete solve by the sine transform (Sec. 5.4, the fast direct   */
+/* method the paper compares full multigrid with; Tables 12-15).           */
+/* ---------------------------------------------------------------------- */
+typedef struct gmg_dst gmg_dst; /* opaque, host side */
+
+/* Set up u = A^-1 f for the 5-/7-point scheme on the (2^levels - 1)^dim
+ * interior grid with zero Dirichlet data, computed as S^-1 diag(lambda)^-1 S f
+ * with S the DST-I along every axis and lambda_k = sum_i (4/h^2)
+ * sin^2(k_i pi h / 2) (exact up to rounding).  Two-phase like gmg_setup:
+ * with workspace == NULL only *ws_bytes is written.  Otherwise workspace
+ * (device memory, 256-byte aligned, at least *ws_bytes bytes, caller-owned)
+ * holds one grid, the odd extensions, the FFT coefficients and the FFT
+ * library's work area (about 5 grids in all).  dim 2 (levels <= 14) or 3
+ * (levels <= 10).  stream: a hipStream_t (NULL = default).  The batched FFTs
+ * are rocFFT's; plan creation may compile FFT kernels on first use.  Errors:
+ * GMG_ERR_INVALID_ARG, GMG_ERR_WORKSPACE, GMG_ERR_HIP (FFT library failure). */
+gmg_status gmg_dst_setup(int dim, int levels, void *workspace, size_t *ws_bytes, void *stream,
+                         gmg_dst **out);
+
+/* u = A^-1 f (device arrays of m^dim FP64, x fastest; u must not alias f; f is
+ * only read).  Enqueue only. */
+gmg_status gmg_dst_solve(gmg_dst *p, double *u, const double *f);
+
+/* Release the solver (not the workspace). */
+gmg_status gmg_dst_destroy(gmg_dst *p);
+
+/* ---------------------------------------------------------------------- */
 /* Profiling (plans set up with GMG_PROFILE): per kernel class, launches,  */
 /* summed hipEvent durations on the plan's stream and algorithmic bytes.   */
 /* ---------------------------------------------------------------------- */

@@ -18,7 +18,11 @@ LIB = os.path.join(HERE, "libgmg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GMG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["smooth.hip", "transfer.hip", "bottom.hip", "small.hip", "variant.hip", "gmg_capi.cpp"]
+SOURCES = ["smooth.hip", "transfer.hip", "bottom.hip", "small.hip", "variant.hip", "dst.hip",
+           "gmg_capi.cpp"]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# the sine-transform solver calls rocFFT (as a library) for its batched FFTs
+LIBS = ["-L" + os.path.join(ROCM, "lib"), "-lrocfft", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
@@ -52,7 +56,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-20000:]))

@@ -45,7 +45,8 @@ EXPORTED = [
     "gmg_op_smooth", "gmg_op_restrict_residual", "gmg_op_residual", "gmg_op_prolong_add",
     "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
-    "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg",
+    "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg", "gmg_dst_setup", "gmg_dst_solve",
+    "gmg_dst_destroy",
 ]
 
 
@@ -110,6 +111,9 @@ def lib():
     L.gmg_op_restrict_residual.argtypes = [vp, i, i, vp, vp, vp]
     L.gmg_op_residual.argtypes = [vp, i, i, vp, vp, vp, dp]
     L.gmg_op_prolong_add.argtypes = [vp, i, i, vp, vp, vp]
+    L.gmg_dst_setup.argtypes = [i, i, vp, ctypes.POINTER(sz), vp, ctypes.POINTER(vp)]
+    L.gmg_dst_solve.argtypes = [vp, vp, vp]
+    L.gmg_dst_destroy.argtypes = [vp]
     L.gmg_profile_count.argtypes = [vp]
     L.gmg_profile_get.argtypes = [vp, i, ctypes.POINTER(GmgKernelStat)]
     L.gmg_profile_reset.argtypes = [vp]

@@ -221,3 +221,35 @@ class BatchPlan:
 
     def profile_reset(self):
         capi.check(capi.lib().gmg_profile_reset(self._plan), "gmg_profile_reset")
+
+
+class DstSolver:
+    """Exact discrete solve u = A^-1 f by the sine transform (gmg_dst_*):
+    the fast direct method of the paper's FMG-vs-FFT comparison."""
+
+    def __init__(self, dim: int, levels: int):
+        L = capi.lib()
+        self.dim, self.levels = dim, levels
+        self.m0 = (1 << levels) - 1
+        n = ctypes.c_size_t(0)
+        capi.check(L.gmg_dst_setup(dim, levels, None, ctypes.byref(n), _stream(), None),
+                   "gmg_dst_setup(size query)")
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        capi.check(L.gmg_dst_setup(dim, levels, _ptr(self.workspace), ctypes.byref(n), _stream(),
+                                   ctypes.byref(h)), "gmg_dst_setup")
+        self._h = h
+
+    def solve(self, u: torch.Tensor, f: torch.Tensor) -> None:
+        capi.check(capi.lib().gmg_dst_solve(self._h, _ptr(u), _ptr(f)), "gmg_dst_solve")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().gmg_dst_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
