@@ -54,22 +54,36 @@ struct McArgs {
   double h2;
 };
 
+// Raw buffer over the part of an array a tile reads: in 3D one plane (no
+// records for a plane outside the grid), in 2D the rows y0 .. y0+rows-1
+// clipped to the grid.  Offsets are relative to the returned first row.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mc_rsrc(const double *base, int dim, int z,
+                                                         int m, int y0, int rows, int *ybase) {
+  if (dim == 3) {
+    *ybase = 0;
+    return plane_rsrc(base, z, m, m * m);
+  }
+  const int a = max(y0, 0), b = min(y0 + rows, m);
+  *ybase = a;
+  const int n = b > a ? (b - a) * m : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base + (size_t)a * m), (short)0,
+                                           n * (int)sizeof(double), 0x00020000);
+}
+
 template <int DIM, int QX, int QY, int NT>
 __global__ void __launch_bounds__(NT) k_mc_sweep(McArgs a) {
   if (a.active && *a.active == 0) return;
-  constexpr int W = 2 * QX, H = 2 * QY;        // D2 extent
-  constexpr int TX = W - 4, TY = H - 4;        // tile
-  constexpr int NPOS = W * H;
-  constexpr int PER = (NPOS + NT - 1) / NT;    // D2 positions per thread
+  constexpr int W = 2 * QX, H = 2 * QY;  // D2 extent
+  constexpr int TX = W - 4, TY = H - 4;  // tile
   constexpr int NQ = QX * QY;
-  __shared__ double U[NPOS];  // current values on D2
-  __shared__ double R[NPOS];  // h^2 f + z-neighbours on D2
+  static_assert(NQ % NT == 0, "whole quads per thread");
+  constexpr int QPT = NQ / NT;  // quads per thread
+  __shared__ double U[H * W];   // current values on D2
   const int m = a.m;
   const int t = threadIdx.x;
   const int tile = blockIdx.x;
   const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TY;
-  const int xb = x0 - 2, yb = y0 - 2;  // storage index of D2's corner
-  const size_t plane = (size_t)m * m;
+  const int xb = x0 - 2, yb = y0 - 2;  // storage index of D2's corner (even)
   const double diag = 2.0 * DIM;
 
   // own planes of this workgroup (3D): storage z with node parity pz
@@ -83,68 +97,86 @@ __global__ void __launch_bounds__(NT) k_mc_sweep(McArgs a) {
     if (nown <= 0) return;
   }
 
-  // z-neighbour below the first own plane, per owned D2 position
-  double zlo[PER];
-  if (DIM == 3) {
+  // this thread's quads: D2-local corner and the byte offset of each of its
+  // four points (row r, column c) relative to the resource's first row, or
+  // kOOB outside the grid
+  int lx0[QPT], ly0[QPT];
+  int off[QPT][4];
+  int ybase = 0;
+  (void)mc_rsrc(a.f, DIM, 0, m, yb, H, &ybase);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int p = t + q * NT;
-      const int x = xb + p % W, y = yb + p / W, z = z_first - 1;
-      double v = 0.0;
-      if (p < NPOS && a.zsrc && x >= 0 && x < m && y >= 0 && y < m && z >= 0)
-        v = gbl(a.zsrc)[(size_t)z * plane + (size_t)y * m + x];
-      zlo[q] = v;
-    }
+  for (int i = 0; i < QPT; ++i) {
+    const int q = t + i * NT;
+    lx0[i] = 2 * (q % QX);
+    ly0[i] = 2 * (q / QX);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int x = xb + lx0[i] + c, y = yb + ly0[i] + r;
+        const bool in = x >= 0 && x < m && y >= 0 && y < m;
+        off[i][2 * r + c] = in ? ((y - ybase) * m + x) * (int)sizeof(double) : kOOB;
+      }
+  }
+
+  double R[QPT][4];    // h^2 f + z-neighbours of the quad's points
+  double zlo[QPT][4];  // 3D: the plane below, carried from one own plane to the next
+  if (DIM == 3) {
+    const __amdgpu_buffer_rsrc_t rz = a.zsrc ? plane_rsrc(a.zsrc, z_first - 1, m, m * m)
+                                             : plane_rsrc(a.f, -1, m, m * m);
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) zlo[i][k] = bload<double>(rz, off[i][k]);
   }
 
   for (int o = 0; o < nown; ++o) {
     const int z = z_first + 2 * o;
-    const size_t zoff = DIM == 3 ? (size_t)z * plane : 0;
-    // old values on D2 and the fixed part of each update on D2
+    int yb2 = 0;
+    const __amdgpu_buffer_rsrc_t rf = mc_rsrc(a.f, DIM, z, m, yb, H, &yb2);
+    const __amdgpu_buffer_rsrc_t ru = a.src ? mc_rsrc(a.src, DIM, z, m, yb, H, &yb2)
+                                            : plane_rsrc(a.f, -1, m, m * m);  // no records: zero
+    __amdgpu_buffer_rsrc_t rzh = plane_rsrc(a.f, -1, m, m * m);
+    if (DIM == 3 && a.zsrc) rzh = plane_rsrc(a.zsrc, z + 1, m, m * m);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int p = t + q * NT;
-      if (p >= NPOS) break;
-      const int x = xb + p % W, y = yb + p / W;
-      const bool in = x >= 0 && x < m && y >= 0 && y < m;
-      const size_t g = zoff + (size_t)y * m + x;
-      double u = 0.0, r = 0.0;
-      if (in) {
-        if (a.src) u = gbl(a.src)[g];
-        r = a.h2 * gbl(a.f)[g];
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double u = bload<double>(ru, off[i][k]);
+        double r = a.h2 * bload<double>(rf, off[i][k]);
         if (DIM == 3) {
-          double zhi = 0.0;
-          if (a.zsrc && z + 1 < m) zhi = gbl(a.zsrc)[g + plane];
-          r = r + (zlo[q] + zhi);
-          zlo[q] = zhi;  // the plane above is the next own plane's plane below
+          const double zhi = bload<double>(rzh, off[i][k]);
+          r = r + (zlo[i][k] + zhi);
+          zlo[i][k] = zhi;  // the plane above is the next own plane's plane below
         }
-      } else if (DIM == 3) {
-        zlo[q] = 0.0;
+        R[i][k] = r;
+        U[(ly0[i] + (k >> 1)) * W + lx0[i] + (k & 1)] = u;
       }
-      U[p] = u;
-      R[p] = r;
-    }
     __syncthreads();
-    // four colour steps on D1
+    // four colour steps on D1 (the tile plus a halo of one point)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int c = a.backward ? 3 - s : s;
       const int ax = c & 1, by = c >> 1;  // node-index parities of this colour
-      for (int qi = t; qi < NQ; qi += NT) {
-        const int lx = 2 * (qi % QX) + (1 - ax), ly = 2 * (qi / QX) + (1 - by);
-        const int x = xb + lx, y = yb + ly;
+      const int k = 2 * (1 - by) + (1 - ax);  // that point's index in the quad
+#pragma unroll
+      for (int i = 0; i < QPT; ++i) {
+        const int lx = lx0[i] + (1 - ax), ly = ly0[i] + (1 - by);
         if (lx < 1 || lx >= W - 1 || ly < 1 || ly >= H - 1) continue;  // D1 only
-        if (x < 0 || x >= m || y < 0 || y >= m) continue;                 // boundary stays 0
+        if (off[i][k] == kOOB) continue;                                // boundary stays 0
         const int p = ly * W + lx;
-        U[p] = (R[p] + ((U[p - 1] + U[p + 1]) + (U[p - W] + U[p + W]))) / diag;
+        U[p] = (R[i][k] + ((U[p - 1] + U[p + 1]) + (U[p - W] + U[p + W]))) / diag;
       }
       __syncthreads();
     }
-    // the tile's own points
-    for (int p = t; p < TX * TY; p += NT) {
-      const int lx = 2 + p % TX, ly = 2 + p / TX;
-      const int x = xb + lx, y = yb + ly;
-      if (x < m && y < m) gbl(a.dst)[zoff + (size_t)y * m + x] = U[ly * W + lx];
+    // the tile's own points: quads lie wholly inside or outside the tile
+    const __amdgpu_buffer_rsrc_t rd = mc_rsrc(a.dst, DIM, z, m, yb, H, &yb2);
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      if (lx0[i] < 2 || lx0[i] >= W - 2 || ly0[i] < 2 || ly0[i] >= H - 2) continue;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        bstore<double>(rd, off[i][k], U[(ly0[i] + (k >> 1)) * W + lx0[i] + (k & 1)]);
     }
     __syncthreads();
   }
@@ -334,6 +366,10 @@ hipError_t mc_launch(McArgs a, hipStream_t s) {
   int nz = 1;
   if (DIM == 3) {
     const int own = (m + 1) / 2;  // most planes of one parity
+    // planes per workgroup: one while that still leaves a few thousand
+    // workgroups (measured faster than marching over several planes with
+    // fewer workgroups: a workgroup's loads, colour steps and stores do not
+    // overlap, other workgroups hide them)
     a.czp = std::max(1, std::min(16, own * tiles / 2048));
     nz = (own + a.czp - 1) / a.czp;
   }
