@@ -130,8 +130,10 @@ __global__ void __launch_bounds__(NT) k_mc_sweep(McArgs a) {
       for (int k = 0; k < 4; ++k) zlo[i][k] = bload<double>(rz, off[i][k]);
   }
 
-  for (int o = 0; o < nown; ++o) {
-    const int z = z_first + 2 * o;
+  // loads of one own plane: old values, f and (3D) the plane above; issued
+  // for plane o + 1 before the colour steps of plane o so that they overlap
+  double pu[QPT][4], pf[QPT][4], pz[QPT][4];
+  auto load_plane = [&](int z) {
     int yb2 = 0;
     const __amdgpu_buffer_rsrc_t rf = mc_rsrc(a.f, DIM, z, m, yb, H, &yb2);
     const __amdgpu_buffer_rsrc_t ru = a.src ? mc_rsrc(a.src, DIM, z, m, yb, H, &yb2)
@@ -142,16 +144,28 @@ __global__ void __launch_bounds__(NT) k_mc_sweep(McArgs a) {
     for (int i = 0; i < QPT; ++i)
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double u = bload<double>(ru, off[i][k]);
-        double r = a.h2 * bload<double>(rf, off[i][k]);
+        pu[i][k] = bload<double>(ru, off[i][k]);
+        pf[i][k] = bload<double>(rf, off[i][k]);
+        if (DIM == 3) pz[i][k] = bload<double>(rzh, off[i][k]);
+      }
+  };
+  load_plane(z_first);
+
+  for (int o = 0; o < nown; ++o) {
+    const int z = z_first + 2 * o;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double r = a.h2 * pf[i][k];
         if (DIM == 3) {
-          const double zhi = bload<double>(rzh, off[i][k]);
-          r = r + (zlo[i][k] + zhi);
-          zlo[i][k] = zhi;  // the plane above is the next own plane's plane below
+          r = r + (zlo[i][k] + pz[i][k]);
+          zlo[i][k] = pz[i][k];  // the plane above is the next own plane's plane below
         }
         R[i][k] = r;
-        U[(ly0[i] + (k >> 1)) * W + lx0[i] + (k & 1)] = u;
+        U[(ly0[i] + (k >> 1)) * W + lx0[i] + (k & 1)] = pu[i][k];
       }
+    if (o + 1 < nown) load_plane(z + 2);
     __syncthreads();
     // four colour steps on D1 (the tile plus a halo of one point)
 #pragma unroll
@@ -170,6 +184,7 @@ __global__ void __launch_bounds__(NT) k_mc_sweep(McArgs a) {
       __syncthreads();
     }
     // the tile's own points: quads lie wholly inside or outside the tile
+    int yb2 = 0;
     const __amdgpu_buffer_rsrc_t rd = mc_rsrc(a.dst, DIM, z, m, yb, H, &yb2);
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
@@ -275,13 +290,30 @@ __global__ void __launch_bounds__(CX *CY) k_restrict_fe(FeRestrictArgs a) {
   const int c1 = min(mc, c0 + a.czc);
   if (c0 >= c1) return;
   const size_t cplane = (size_t)mc * mc;
-  // fine planes 2c0 .. 2c1 (storage); ring slot of plane z is (z + 3) % 3
+  // fine planes 2c0 .. 2c1 (storage); ring slot of plane z is (z + 3) % 3.
+  // The u plane two ahead is loaded into registers while the residual of
+  // plane z is formed, and stored into the slot plane z - 1 frees.
+  constexpr int UPT = (NU + NT - 1) / NT;
+  double pre[UPT];
+  auto fetch = [&](int z) {
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      const int p = t + q * NT;
+      const int x = fx0 - 1 + p % UW, y = fy0 - 1 + p / UW;
+      double v = 0.0;
+      if (p < NU && a.u && x >= 0 && x < m && y >= 0 && y < m && z >= 0 && z < m)
+        v = gbl(a.u)[(size_t)z * plane + (size_t)y * m + x];
+      pre[q] = v;
+    }
+  };
   load_u((2 * c0 - 1 + 3) % 3, 2 * c0 - 1);
   load_u((2 * c0 + 3) % 3, 2 * c0);
+  load_u((2 * c0 + 1 + 3) % 3, 2 * c0 + 1);
+  __syncthreads();
   double acc = 0.0;
   for (int z = 2 * c0; z <= 2 * c1; ++z) {
-    load_u((z + 1 + 3) % 3, z + 1);
-    __syncthreads();
+    const bool more = z + 2 <= 2 * c1 + 1;
+    if (more) fetch(z + 2);
     residual(z, (z - 1 + 3) % 3, (z + 3) % 3, (z + 1 + 3) % 3);
     __syncthreads();
     if (z & 1) {
@@ -297,7 +329,15 @@ __global__ void __launch_bounds__(CX *CY) k_restrict_fe(FeRestrictArgs a) {
       // the plane below coarse plane z / 2: directions with z = -1
       acc = R(0, 0) + R(-1, 0) + R(0, -1) + R(-1, -1);
     }
-    __syncthreads();  // Rs and the ring slot of plane z - 1 are reused
+    if (more) {
+      // plane z + 2 into the slot of plane z - 1 (no longer read)
+#pragma unroll
+      for (int q = 0; q < UPT; ++q) {
+        const int p = t + q * NT;
+        if (p < NU) Us[(z + 2) % 3][p] = pre[q];
+      }
+    }
+    __syncthreads();  // Rs and the ring are reused
   }
 }
 
@@ -366,11 +406,10 @@ hipError_t mc_launch(McArgs a, hipStream_t s) {
   int nz = 1;
   if (DIM == 3) {
     const int own = (m + 1) / 2;  // most planes of one parity
-    // planes per workgroup: one while that still leaves a few thousand
-    // workgroups (measured faster than marching over several planes with
-    // fewer workgroups: a workgroup's loads, colour steps and stores do not
-    // overlap, other workgroups hide them)
-    a.czp = std::max(1, std::min(16, own * tiles / 2048));
+    // a few planes per workgroup (the next plane's loads overlap this
+    // plane's colour steps, and the plane below comes from the previous
+    // plane's plane above) while keeping a few thousand workgroups
+    a.czp = std::max(2, std::min(16, own * tiles / 2048));
     nz = (own + a.czp - 1) / a.czp;
   }
   gmg_launch((k_mc_sweep<DIM, QX, QY, NT>), dim3(tiles, nz), dim3(NT), 0, s, a);
@@ -379,7 +418,8 @@ hipError_t mc_launch(McArgs a, hipStream_t s) {
 
 template <int DIM>
 hipError_t mc_sweep_dim(McArgs a, hipStream_t s) {
-  if (a.m >= (DIM == 3 ? 127 : 255)) return mc_launch<DIM, 64, 16, 256>(a, s);
+  if (a.m >= (DIM == 3 ? 127 : 255))
+    return DIM == 3 ? mc_launch<DIM, 64, 16, 512>(a, s) : mc_launch<DIM, 64, 16, 256>(a, s);
   return mc_launch<DIM, 16, 8, 128>(a, s);
 }
 }  // namespace
