@@ -90,9 +90,11 @@ typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
                                        own instead of inside the last
                                        pre-smoothing pass (same results)      */
 /* The paper's own transfers and coarsest rule (with any smoother; FP64 single
- * problems only, GMG_ERR_UNSUPPORTED otherwise).  Such plans run one kernel
- * per step and level, without the fused passes, the small-level kernels or
- * the bottom kernel. */
+ * problems only, GMG_ERR_UNSUPPORTED otherwise).  Such plans (and MCGS plans)
+ * run one kernel per step and level, without the small-level kernels, the
+ * bottom kernel or the folded restriction; GMG_USE_GRAPH and GMG_AUTOTUNE
+ * have no effect on them (red-black or Jacobi sweeps keep the default tile
+ * choices). */
 #define GMG_FE_TRANSFER 0x80u       /* linear finite-element restriction and
                                        interpolation (Sec. 4, eq. Restriction2d
                                        and eq. Prolongation2d; 15-point in 3D)
