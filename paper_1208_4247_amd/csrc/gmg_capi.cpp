@@ -609,7 +609,7 @@ template <typename T>
 hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
                           double *norm_partials, const int *active) {
   LevelSet<T> &S = levels_of<T>(p);
-  const int L = p->L, B = p->B;
+  const int L = p->L;
   const bool bwd = !(p->cfg.flags & GMG_POST_FORWARD);
   const int nu1 = p->cfg.nu1, nu2 = p->cfg.nu2;
   hipError_t e;

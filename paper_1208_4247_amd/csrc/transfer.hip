@@ -485,19 +485,20 @@ __global__ void k_fill_zero(unsigned char *dst, size_t n) {
 }
 
 // ------------------------------------------------------------------------
-// out = in + P e (in NULL = zero), one thread per fine point.  Used when a
-// level has no post-smoothing sweep (nu2 = 0); in may alias out.
+// out = in + P e (in NULL = zero), one thread per fine point: x from the
+// block and thread index, the row y and plane z from the grid's y and z, so
+// no wide integer division.  Used when a level has no post-smoothing sweep
+// (nu2 = 0) and for the interpolation of full multigrid; in may alias out.
 // ------------------------------------------------------------------------
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong_add(const T *in, const T *__restrict__ ec, T *out,
                                                      int m, int mc, const int *active) {
   if (active && *active == 0) return;
-  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
-  for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
-    const int x = (int)(p % m);
-    const size_t rest = p / m;
-    const int y = (int)(rest % m);
-    const int z = DIM == 3 ? (int)(rest / m) : 0;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = DIM == 3 ? (int)blockIdx.z : 0;
+  if (x < m) {
+    const size_t p = ((size_t)z * m + y) * m + x;
     // canonical order: average along x, then y, then z (zero coarse boundary)
     auto cv = [&](int a, int b, int c) -> T {
       if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) return T(0);
@@ -635,11 +636,11 @@ hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s) {
 template <typename T>
 hipError_t launch_prolong_add(int dim, int m, int mc, const T *in, const T *ec, T *out,
                               const int *active, hipStream_t s) {
-  const int nb = residual_blocks(dim, m);
+  const dim3 grid((m + 255) / 256, m, dim == 3 ? m : 1);
   if (dim == 3)
-    gmg_launch((k_prolong_add<T, 3>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+    gmg_launch((k_prolong_add<T, 3>), grid, dim3(256), 0, s, in, ec, out, m, mc, active);
   else
-    gmg_launch((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+    gmg_launch((k_prolong_add<T, 2>), grid, dim3(256), 0, s, in, ec, out, m, mc, active);
   return hipGetLastError();
 }
 

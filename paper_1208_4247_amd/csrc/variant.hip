@@ -352,13 +352,15 @@ __global__ void __launch_bounds__(256) k_prolong_fe(const double *in, const doub
                                                     double *out, int m, int mc,
                                                     const int *active) {
   if (active && *active == 0) return;
-  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
-  for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+  const int xs = blockIdx.x * 256 + threadIdx.x;  // storage indices: x, row, plane
+  const int ys = blockIdx.y;
+  const int zs = DIM == 3 ? (int)blockIdx.z : 0;
+  if (xs < m) {
+    const size_t p = ((size_t)zs * m + ys) * m + xs;
     // node indices of the fine point
-    const int i = (int)(p % m) + 1;
-    const size_t rest = p / m;
-    const int j = (int)(rest % m) + 1;
-    const int k = DIM == 3 ? (int)(rest / m) + 1 : 0;
+    const int i = xs + 1;
+    const int j = ys + 1;
+    const int k = DIM == 3 ? zs + 1 : 0;
     const int oi = i & 1, oj = j & 1, ok = k & 1;
     const int I = (i - oi) >> 1, J = (j - oj) >> 1, K = (k - ok) >> 1;
     auto cv = [&](int ci, int cj, int ck) -> double {  // coarse node value, 0 on the boundary
@@ -479,12 +481,11 @@ hipError_t launch_restrict_fe(int dim, int m, int mc, const double *u, const dou
 hipError_t launch_prolong_fe(int dim, int m, int mc, const double *in, const double *ec,
                              double *out, const int *active, hipStream_t s) {
   if (mc < 1 || m != 2 * mc + 1 || !ec || !out) return hipErrorInvalidValue;
-  const size_t N = dim == 3 ? (size_t)m * m * m : (size_t)m * m;
-  const int nb = (int)std::min<size_t>((N + 255) / 256, 65536);
+  const dim3 grid((m + 255) / 256, m, dim == 3 ? m : 1);
   if (dim == 2)
-    gmg_launch((k_prolong_fe<2>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+    gmg_launch((k_prolong_fe<2>), grid, dim3(256), 0, s, in, ec, out, m, mc, active);
   else
-    gmg_launch((k_prolong_fe<3>), dim3(nb), dim3(256), 0, s, in, ec, out, m, mc, active);
+    gmg_launch((k_prolong_fe<3>), grid, dim3(256), 0, s, in, ec, out, m, mc, active);
   return hipGetLastError();
 }
 
