@@ -261,8 +261,8 @@ typedef struct gmg_dst gmg_dst; /* opaque, host side */
  * sin^2(k_i pi h / 2) (exact up to rounding).  Two-phase like gmg_setup:
  * with workspace == NULL only *ws_bytes is written.  Otherwise workspace
  * (device memory, 256-byte aligned, at least *ws_bytes bytes, caller-owned)
- * holds one grid, the odd extensions, the FFT coefficients and the FFT
- * library's work area (about 5 grids in all).  dim 2 (levels <= 14) or 3
+ * holds the odd extensions and the FFT coefficients of every line and the
+ * FFT library's work area (about 4 grids in all).  dim 2 (levels <= 14) or 3
  * (levels <= 10).  stream: a hipStream_t (NULL = default).  The batched FFTs
  * are rocFFT's; plan creation may compile FFT kernels on first use.  Errors:
  * GMG_ERR_INVALID_ARG, GMG_ERR_WORKSPACE, GMG_ERR_HIP (FFT library failure). */

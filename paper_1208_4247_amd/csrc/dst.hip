@@ -13,6 +13,9 @@
 //   unpack  y_k = -Im(X_k) / 2, written with the transformed axis moved to
 //           the slowest position (an LDS tile transpose)
 // so d passes visit every axis and return the array to its own axis order.
+// Only f is packed by a kernel of its own: every unpack but the last writes
+// its result directly as the odd extensions of the next pass's lines, into
+// the buffer the FFT has just consumed.
 // The last forward pass divides by the eigenvalues and applies the inverse's
 // scale (2/(m+1))^d (DST-I is its own inverse up to (m+1)/2 per axis); d
 // more passes invert the transform.  FP64 throughout.
@@ -93,6 +96,62 @@ __global__ void __launch_bounds__(256) k_dst_unpack(const double2 *__restrict__ 
   }
 }
 
+// Unpack straight into the next pass's odd extensions: the value for mode k
+// of line (s, t) (t the fastest index of the line number) belongs to line
+// (k-1) * (lines/m) + s, element t, of the next pass, so it is written to
+// ext[line'][t+1] and, negated, to ext[line'][2(m+1)-(t+1)]; the thread of
+// t = 0 also writes the two zeros of that line.  eig / scale as above.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_dst_unpack_ext(const double2 *__restrict__ C,
+                                                        double *__restrict__ ext, int m,
+                                                        size_t lines, int eig, double scale,
+                                                        double inv_h2) {
+  __shared__ double tile[32][33];
+  const size_t per = (size_t)m + 2;
+  const size_t L2 = 2 * (size_t)(m + 1);
+  const size_t l0 = (size_t)blockIdx.y * 32;
+  const int k0 = 1 + blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const size_t line = l0 + r;
+    const int k = k0 + tx;
+    double v = 0.0;
+    if (line < lines && k <= m) v = -0.5 * C[line * per + k].y;
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  const size_t outer = lines / (size_t)m;  // lines of the next pass per mode
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r;
+    const size_t line = l0 + tx;
+    if (k > m || line >= lines) continue;
+    double v = tile[tx][r];
+    if (eig) {
+      const double t = M_PI / (2.0 * (m + 1));
+      auto s2 = [&](long q) {
+        const double sv = sin(t * (double)q);
+        return sv * sv;
+      };
+      double lam = s2(k);
+      if (DIM == 2) {
+        lam += s2((long)line + 1);
+      } else {
+        lam += s2((long)(line / m) + 1) + s2((long)(line % m) + 1);
+      }
+      v = v * scale / (4.0 * inv_h2 * lam);
+    }
+    const size_t s_ = line / (size_t)m;
+    const int t_ = (int)(line % (size_t)m);
+    double *e = ext + ((size_t)(k - 1) * outer + s_) * L2;
+    e[t_ + 1] = v;
+    e[L2 - (t_ + 1)] = -v;
+    if (t_ == 0) {
+      e[0] = 0.0;
+      e[m + 1] = 0.0;
+    }
+  }
+}
+
 }  // namespace gmg
 
 using namespace gmg;
@@ -101,7 +160,6 @@ struct gmg_dst {
   int dim = 3, m = 1;
   size_t lines = 1;
   hipStream_t stream = nullptr;
-  double *A = nullptr;    // intermediate grid
   double *E = nullptr;    // odd extensions
   double2 *C = nullptr;   // FFT coefficients
   void *work = nullptr;   // rocFFT work buffer
@@ -121,12 +179,11 @@ bool rocfft_ready() {
 }
 
 struct DstSizes {
-  size_t A, E, C;
+  size_t E, C;
 };
 DstSizes dst_sizes(int dim, int m) {
   const size_t lines = dim == 3 ? (size_t)m * m : (size_t)m;
   DstSizes s;
-  s.A = up(lines * m * sizeof(double));
   s.E = up(lines * 2 * (size_t)(m + 1) * sizeof(double));
   s.C = up(lines * (size_t)(m + 2) * sizeof(double2));
   return s;
@@ -139,24 +196,31 @@ rocfft_status make_plan(int dim, int m, rocfft_plan *plan) {
                             rocfft_precision_double, 1, &len, lines, nullptr);
 }
 
-hipError_t dst_pass(gmg_dst *p, const double *src, double *dst, int eig, double scale) {
+// FFT of the extensions in E into C, then the unpack: into the next pass's
+// extensions in E (out == NULL) or, for the last pass, into out.
+hipError_t dst_pass(gmg_dst *p, double *out, int eig, double scale) {
   const int m = p->m;
-  const size_t n = p->lines * (size_t)(m + 2);
-  const int nb = (int)std::min<size_t>((n + 255) / 256, 1 << 20);
-  gmg_launch(k_dst_pack, dim3(nb), dim3(256), 0, p->stream, src, p->E, m, p->lines);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   void *in[1] = {p->E};
-  void *out[1] = {p->C};
-  if (rocfft_execute(p->plan, in, out, p->info) != rocfft_status_success) return hipErrorUnknown;
+  void *o[1] = {p->C};
+  if (rocfft_execute(p->plan, in, o, p->info) != rocfft_status_success) return hipErrorUnknown;
   const double h = 1.0 / double(m + 1);
-  dim3 grid((m + 31) / 32, (unsigned)((p->lines + 31) / 32));
-  if (p->dim == 2)
-    gmg_launch((k_dst_unpack<2>), grid, dim3(256), 0, p->stream, (const double2 *)p->C, dst, m,
-               p->lines, eig, scale, 1.0 / (h * h));
-  else
-    gmg_launch((k_dst_unpack<3>), grid, dim3(256), 0, p->stream, (const double2 *)p->C, dst, m,
-               p->lines, eig, scale, 1.0 / (h * h));
+  const dim3 grid((m + 31) / 32, (unsigned)((p->lines + 31) / 32));
+  const double2 *C = (const double2 *)p->C;
+  if (out) {
+    if (p->dim == 2)
+      gmg_launch((k_dst_unpack<2>), grid, dim3(256), 0, p->stream, C, out, m, p->lines, eig, scale,
+                 1.0 / (h * h));
+    else
+      gmg_launch((k_dst_unpack<3>), grid, dim3(256), 0, p->stream, C, out, m, p->lines, eig, scale,
+                 1.0 / (h * h));
+  } else {
+    if (p->dim == 2)
+      gmg_launch((k_dst_unpack_ext<2>), grid, dim3(256), 0, p->stream, C, p->E, m, p->lines, eig,
+                 scale, 1.0 / (h * h));
+    else
+      gmg_launch((k_dst_unpack_ext<3>), grid, dim3(256), 0, p->stream, C, p->E, m, p->lines, eig,
+                 scale, 1.0 / (h * h));
+  }
   return hipGetLastError();
 }
 
@@ -178,7 +242,7 @@ gmg_status gmg_dst_setup(int dim, int levels, void *workspace, size_t *ws_bytes,
     return GMG_ERR_HIP;
   }
   const DstSizes s = dst_sizes(dim, m);
-  const size_t total = s.A + s.E + s.C + up(wb);
+  const size_t total = s.E + s.C + up(wb);
   if (!workspace) {
     rocfft_plan_destroy(plan);
     *ws_bytes = total;
@@ -198,10 +262,9 @@ gmg_status gmg_dst_setup(int dim, int levels, void *workspace, size_t *ws_bytes,
   p->lines = dim == 3 ? (size_t)m * m : (size_t)m;
   p->stream = (hipStream_t)stream;
   char *w = (char *)workspace;
-  p->A = (double *)w;
-  p->E = (double *)(w + s.A);
-  p->C = (double2 *)(w + s.A + s.E);
-  p->work = wb ? (void *)(w + s.A + s.E + s.C) : nullptr;
+  p->E = (double *)w;
+  p->C = (double2 *)(w + s.E);
+  p->work = wb ? (void *)(w + s.E + s.C) : nullptr;
   p->work_bytes = wb;
   p->plan = plan;
   if (rocfft_execution_info_create(&p->info) != rocfft_status_success ||
@@ -220,18 +283,18 @@ gmg_status gmg_dst_setup(int dim, int levels, void *workspace, size_t *ws_bytes,
 gmg_status gmg_dst_solve(gmg_dst *p, double *u, const double *f) {
   if (!p || !u || !f || (const double *)u == f) return GMG_ERR_INVALID_ARG;
   const double scale = std::pow(2.0 / double(p->m + 1), p->dim);
-  // forward transforms: f -> A -> u [-> A] (the last divides by lambda)
-  const double *src = f;
-  double *bufs[2] = {p->A, u};
-  int b = 0;
+  const int m = p->m;
+  const size_t n = p->lines * (size_t)(m + 2);
+  const int nb = (int)std::min<size_t>((n + 255) / 256, 1 << 20);
+  gmg_launch(k_dst_pack, dim3(nb), dim3(256), 0, p->stream, f, p->E, m, p->lines);
+  if (hipGetLastError() != hipSuccess) return GMG_ERR_HIP;
+  // d forward passes (the last divides by lambda), d inverse passes; only the
+  // last one writes u
   for (int a = 0; a < 2 * p->dim; ++a) {
-    double *dst = bufs[b];
     const int eig = a == p->dim - 1;
-    if (dst_pass(p, src, dst, eig, eig ? scale : 1.0) != hipSuccess) return GMG_ERR_HIP;
-    src = dst;
-    b ^= 1;
+    if (dst_pass(p, a == 2 * p->dim - 1 ? u : nullptr, eig, eig ? scale : 1.0) != hipSuccess)
+      return GMG_ERR_HIP;
   }
-  // 2d passes alternate A, u, A, u, ...: an even count ends in u
   return GMG_OK;
 }
 
