@@ -262,7 +262,7 @@ typedef struct gmg_dst gmg_dst; /* opaque, host side */
  * with workspace == NULL only *ws_bytes is written.  Otherwise workspace
  * (device memory, 256-byte aligned, at least *ws_bytes bytes, caller-owned)
  * holds the odd extensions and the FFT coefficients of every line and the
- * FFT library's work area (about 6 grids in all).  dim 2 (levels <= 14) or 3
+ * FFT library's work area (about 4 grids in all).  dim 2 (levels <= 14) or 3
  * (levels <= 10).  stream: a hipStream_t (NULL = default).  The batched FFTs
  * are rocFFT's; plan creation may compile FFT kernels on first use.  Errors:
  * GMG_ERR_INVALID_ARG, GMG_ERR_WORKSPACE, GMG_ERR_HIP (FFT library failure). */
