@@ -474,7 +474,15 @@ def main():
                      "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch,
                      "tile": ({"stages": tile[0], "variant": tile[1], "tz": tile[2]} if tile
                               else None),
-                     "timer": "HIP events recorded by each dispatch of the kernel"},
+                     "restriction_folded_in": bool(fused_pre),
+                     "timer": "HIP events recorded by each dispatch of the kernel",
+                     # every level-0 kernel class, from the fully profiled breakdown run
+                     "level0_kernels": {
+                         k: {"avg_us": 1e3 * v["ms"] / v["launches"],
+                             "achieved": v["bytes"] / (v["ms"] * 1e-3) / 1e9,
+                             "frac": v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                         for k, v in full.items()
+                         if k.endswith("_l0") and v["launches"] and v["ms"] > 0}},
     }
     if "paper_s" in spec:
         line["config"]["paper_gtx480_s"] = spec["paper_s"]

@@ -1096,9 +1096,23 @@ std::string arch_name() {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
+// z-chunks the tuner tries for a tile on a level of side m: powers of two,
+// the chunks that split the planes into 2, 3, 5, 6 or 12 nearly equal runs,
+// and the automatic choice; duplicates dropped.  The counter table of the
+// microbench (--traffic-table) uses the same rule.
+std::vector<int> tune_z_chunks(int dim, int m, int stages, const PassTile &t) {
+  std::vector<int> v;
+  for (int c : {4, 8, 16, 32, 64}) v.push_back(std::min(c, m));
+  for (int k : {2, 3, 5, 6, 12}) v.push_back(std::max(1, (m + k - 1) / k));
+  v.push_back(auto_tz(dim, m, stages, t));
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
+}
+
 std::string tune_key(const gmg_plan &p, int l, int role, size_t elem) {
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d", arch_name().c_str(),
+  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d|z2", arch_name().c_str(),
                 p.dim, p.m[l], (int)(elem * 8), p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs",
                 role == 0 ? p.cfg.nu1 : p.cfg.nu2, role, p.smax_cap,
                 (p.cfg.flags & GMG_NO_FUSED_RESTRICT) ? 0 : 1);
@@ -1180,12 +1194,8 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
     const int nv = pass_variant_count(p->dim, st, wj ? 1 : 0);
     for (int v = 0; v < nv; ++v) {
       const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, v);
-      int tzs[6] = {4, 8, 16, 32, 64, 0};
-      int last = -1;
-      for (int k = 0; k < 6; ++k) {
-        int tzv = tzs[k] > 0 ? std::min(tzs[k], m) : auto_tz(p->dim, m, st, t);
-        if (tzv == last) continue;
-        last = tzv;
+      const std::vector<int> tzs = tune_z_chunks(p->dim, m, st, t);
+      for (const int tzv : tzs) {
         if (pass_geometry(p->dim, m, st, t, tzv).nblocks > kMaxPartials) continue;
         for (int fz = (fc ? 1 : 0); fz >= 0; --fz) {
           PassChoice c = base;

@@ -83,7 +83,12 @@ def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=Non
     return rows
 
 
-TUNER_TZ = (4, 8, 16, 32, 64, 0)  # the z-chunks the autotuner tries (0: automatic)
+def tuner_tz(m):
+    """The z-chunks the autotuner tries on a level of side m (0: automatic):
+    powers of two up to 64, the chunks that split the planes into 2, 3, 5, 6
+    or 12 nearly equal runs, and the automatic choice."""
+    return sorted({min(c, m) for c in (4, 8, 16, 32, 64)} |
+                  {max(1, -(-m // k)) for k in (2, 3, 5, 6, 12)}) + [0]
 
 
 def traffic_table(dim, m):
@@ -107,7 +112,7 @@ def traffic_table(dim, m):
             nsw = st // 2
             for v in range(plan.tile_variants(st)):
                 seen = set()
-                for tz in TUNER_TZ:
+                for tz in tuner_tz(m):
                     try:
                         plan.set_tile(0, st, v, tz)
                     except Exception:
