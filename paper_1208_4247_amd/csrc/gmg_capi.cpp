@@ -1112,7 +1112,7 @@ std::vector<int> tune_z_chunks(int dim, int m, int stages, const PassTile &t) {
 
 std::string tune_key(const gmg_plan &p, int l, int role, size_t elem) {
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d|z2", arch_name().c_str(),
+  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d|z4", arch_name().c_str(),
                 p.dim, p.m[l], (int)(elem * 8), p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs",
                 role == 0 ? p.cfg.nu1 : p.cfg.nu2, role, p.smax_cap,
                 (p.cfg.flags & GMG_NO_FUSED_RESTRICT) ? 0 : 1);
@@ -1186,9 +1186,10 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
   const size_t N = npts(p->dim, m);
   const int reps = N > (1u << 24) ? 2 : (N > (1u << 20) ? 4 : 10);
   const PassChoice base = p->ch[l][role];
-  PassChoice best = base;
-  double best_us = 1e30;
-  int best_st = stages_of(p, std::min(base.smax, nu));
+  // the best candidate with and without the folded restriction
+  PassChoice best[2] = {base, base};
+  double best_us[2] = {1e30, 1e30};
+  int best_st[2] = {stages_of(p, std::min(base.smax, nu)), stages_of(p, std::min(base.smax, nu))};
   for (int sm = 1; sm <= std::min(p->smax_cap, nu); ++sm) {
     const int st = stages_of(p, sm);
     const int nv = pass_variant_count(p->dim, st, wj ? 1 : 0);
@@ -1205,13 +1206,19 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
           c.fuse = fz;
           p->ch[l][role] = c;
           if (fz && !can_fuse_restrict(p, l, nu, elem)) continue;
+          // exactly the cycle's launches for this step: with a folded
+          // restriction the solve's stop test follows as a kernel of its own,
+          // otherwise it runs in workgroup 0 of the restriction
           auto run = [&]() -> hipError_t {
             bool fused = false;
+            int nparts = 0;
             hipError_t e2 = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials,
-                                            nullptr, PC_MISC, nullptr, fc, &fused);
-            if (e2 == hipSuccess && fc && !fused)
-              e2 = restrict_level<T>(p, l, dst, f, fc, nullptr, PC_MISC);
-            return e2;
+                                            nullptr, PC_MISC, &nparts, fc, &fused);
+            if (e2 != hipSuccess || !fc) return e2;
+            if (fused)
+              return partials ? launch_finalize(partials, nparts, p->state, p->stream)
+                              : hipSuccess;
+            return restrict_level<T>(p, l, dst, f, fc, nullptr, PC_MISC, partials, nparts);
           };
           err = run();
           if (err != hipSuccess) break;
@@ -1223,10 +1230,10 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
           if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
           if (err != hipSuccess) break;
           const double us = 1e3 * ms / reps;
-          if (us < best_us) {
-            best_us = us;
-            best = c;
-            best_st = st;
+          if (us < best_us[fz]) {
+            best_us[fz] = us;
+            best[fz] = c;
+            best_st[fz] = st;
           }
         }
         if (err != hipSuccess) break;
@@ -1237,8 +1244,12 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  p->ch[l][role] = best;
-  if (err == hipSuccess) tune_cache_store(key, best, best_st, best_us);
+  // the folded restriction enlarges the pass's halo and LDS: keep the plain
+  // pass and the separate restriction unless folding is clearly faster
+  // (timing noise of a few percent would otherwise flip the choice)
+  const int pick = best_us[1] < 0.97 * best_us[0] ? 1 : 0;
+  p->ch[l][role] = best[pick];
+  if (err == hipSuccess) tune_cache_store(key, best[pick], best_st[pick], best_us[pick]);
   return err;
 }
 
@@ -1251,7 +1262,13 @@ hipError_t tune_plan(gmg_plan *p, const T *src0, const T *f0, double *partials0)
   LevelSet<T> &S = levels_of<T>(p);
   const bool prof = p->profile;
   p->profile = false;
-  hipError_t e = hipSuccess;
+  // the timed level-0 steps update the solve state like a solve does; give
+  // it defined contents (the solve initialises it again afterwards)
+  hipError_t e = partials0 ? launch_state_init(p->state, 1, 1.0, -1.0, p->stream) : hipSuccess;
+  if (e != hipSuccess) {
+    p->profile = prof;
+    return e;
+  }
   for (int l = 0; l < p->B && l + 1 < p->L && e == hipSuccess; ++l) {
     const T *f = l == 0 ? f0 : S.f[l];
     // descent: level 0 reads the start value (and reports its residual norm)
