@@ -905,7 +905,7 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
 // TX = 2*(EXP - 2*halo_pairs), TY = EY - 2*halo (3D).
 #define GMG_RB3_S2(X) \
   X(3, 2, 66, 30, 1024) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 512) X(3, 2, 34, 30, 1024)
-#define GMG_RB3_S4(X) X(3, 4, 36, 28, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512)
+#define GMG_RB3_S4(X) X(3, 4, 36, 28, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512) X(3, 4, 36, 24, 896)
 #define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 #define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
 #define GMG_WJ3_S1(X) X(3, 1, 34, 30, 1024) X(3, 1, 66, 14, 1024) X(3, 1, 34, 14, 512)

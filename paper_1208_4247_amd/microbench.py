@@ -55,6 +55,9 @@ def run(dim, m, reps=20, dtype=torch.float64, smoother="rbgs", tzs=(0,), out=Non
                     if kind == "plain":
                         fn = lambda: plan.op_smooth(0, nsw, False, u, f, None, o)
                         nb = 3 * n * es
+                    elif kind == "norm":
+                        fn = lambda: plan.op_smooth(0, nsw, False, u, f, None, o, want_norm=True)
+                        nb = 3 * n * es
                     elif kind == "zero":
                         fn = lambda: plan.op_smooth(0, nsw, False, None, f, None, o)
                         nb = 2 * n * es
