@@ -11,11 +11,17 @@
 // to -2i sum_j x_j sin(pi j k/(m+1)).  Two lines a, b therefore share one
 // complex FFT of z = ext_a + i ext_b: Z_k = -2i S_a(k) + 2 S_b(k), so
 // S_a(k) = -Im Z_k / 2 and S_b(k) = Re Z_k / 2, with no post-processing.
-//   pack    the odd extensions of lines 2p, 2p+1 as complex line p (a zero
-//           line pads an odd line count)
+//   pack    the odd extensions of f's lines as complex lines (pairing below)
 //   FFT     a batched complex FFT of length N (rocFFT, used as a library)
 //   unpack  S(k) for every line, written with the transformed axis moved to
 //           the slowest position (an LDS tile transpose)
+// Pairing: a pass's m^(d-1) lines are numbered l = a o + s with o = m in 3D
+// (a, s the two untransformed axes, a the slower) and o = 1 in 2D (s = 0);
+// lines a and a+1 (a even) with the same s form complex line (a/2) o + s,
+// line a in the real part (an odd count of a leaves the last imaginary parts
+// zero).  The unpack moves mode k to the slow axis, so modes k and k+1 of a
+// line land in one complex line of the next pass: every pack and unpack
+// thread reads and writes whole complex values.
 // so d passes visit every axis and return the array to its own axis order.
 // Only f is packed by a kernel of its own: every unpack but the last writes
 // its result directly as the next pass's complex lines, into the buffer the
@@ -34,46 +40,29 @@
 
 namespace gmg {
 
-// Store value v of element t (0-based, t < m) of line `line` into the
-// complex lines z (N = 2(m+1) per line): +v at t+1, -v at N-(t+1), in the
-// real part for an even line and the imaginary part for an odd one.  The
-// thread of t = 0 also writes the zeros at 0 and m+1; for the last of an odd
-// number of lines the partner (padding) line is written as zeros too.
-__device__ __forceinline__ void dst_put(double *z, int m, size_t lines, size_t line, int t,
-                                        double v) {
-  const size_t N = 2 * (size_t)(m + 1);
-  const int c = (int)(line & 1);
-  double *zl = z + (line >> 1) * 2 * N;  // complex line, interleaved
-  zl[2 * (t + 1) + c] = v;
-  zl[2 * (N - (t + 1)) + c] = -v;
-  if (t == 0) {
-    zl[c] = 0.0;
-    zl[2 * (m + 1) + c] = 0.0;
-  }
-  if (c == 0 && line + 1 == lines) {  // odd count: the padding line is zero
-    zl[2 * (t + 1) + 1] = 0.0;
-    zl[2 * (N - (t + 1)) + 1] = 0.0;
-    if (t == 0) {
-      zl[1] = 0.0;
-      zl[2 * (m + 1) + 1] = 0.0;
-    }
-  }
-}
-
-// one thread per element of src (lines x m): the complex lines of f
+// Pack f: thread t of complex line c = (a/2) o + s reads element t of lines
+// a o + s and (a+1) o + s (zero past the last a) and writes both halves of
+// the odd extension; the thread of t = m writes the two zeros.  blockIdx.x
+// covers t, blockIdx.y strides over the complex lines.
 __global__ void __launch_bounds__(256) k_dst_pack(const double *__restrict__ src,
-                                                  double *__restrict__ z, int m, size_t lines) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < lines * (size_t)m;
-       i += (size_t)gridDim.x * 256)
-    dst_put(z, m, lines, i / (size_t)m, (int)(i % (size_t)m), src[i]);
-}
-
-// S(k) of line `line` from the FFT of its complex line
-__device__ __forceinline__ double dst_get(const double2 *__restrict__ Z, int m, size_t line,
-                                          int k) {
+                                                  double2 *__restrict__ z, int m, int o) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t > m) return;
   const size_t N = 2 * (size_t)(m + 1);
-  const double2 c = Z[(line >> 1) * N + k];
-  return (line & 1) ? 0.5 * c.x : -0.5 * c.y;
+  const size_t ncl = (size_t)((m + 1) / 2) * o;
+  for (size_t c = blockIdx.y; c < ncl; c += gridDim.y) {
+    double2 *zl = z + c * N;
+    if (t == m) {
+      zl[0] = make_double2(0.0, 0.0);
+      zl[m + 1] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const int a = 2 * (int)(c / o), sx = (int)(c % o);
+    const double va = src[((size_t)a * o + sx) * m + t];
+    const double vb = a + 1 < m ? src[((size_t)(a + 1) * o + sx) * m + t] : 0.0;
+    zl[t + 1] = make_double2(va, vb);
+    zl[N - 1 - t] = make_double2(-va, -vb);
+  }
 }
 
 // 1/lambda times `scale` for mode k along the axis just transformed; the
@@ -95,37 +84,72 @@ __device__ __forceinline__ double dst_eig(int m, size_t line, int k, double scal
   return scale / (4.0 * inv_h2 * lam);
 }
 
-// Unpack with transpose, a 32 x 32 tile (lines x modes) per workgroup.
-// EXT: write mode k of line (s, t) (t the fastest index of the line number)
-// as element t of line (k-1) * (lines/m) + s of the next pass's complex
-// lines; else to dst[(k-1) * lines + line].  eig != 0 (the last forward
-// pass): divide by the eigenvalue and multiply by `scale`.
+// Unpack with transpose.  A workgroup takes 32 complex lines (3D: a pair
+// (a, a+1) = 2 blockIdx.z + {0, 1} and s = 32 blockIdx.y + r; 2D: a = 64
+// blockIdx.y + 2 r + {0, 1}) times 32 modes k = 1 + 32 blockIdx.x + kk,
+// reads them as whole complex values into LDS, then writes modes k, k+1 (k
+// odd) of each line l = a o + s as one complex value of the next pass: line
+// (k-1) o + l / m, element l % m, i.e. complex line ((k-1)/2) o + l / m
+// (EXT); or, for the last pass, into out[(k-1) m^(d-1) + l].  eig != 0 (the
+// last forward pass): divide by the eigenvalue and multiply by `scale`.
 template <int DIM, bool EXT>
 __global__ void __launch_bounds__(256) k_dst_unpack(const double2 *__restrict__ Z,
-                                                    double *__restrict__ dst, int m, size_t lines,
-                                                    int eig, double scale, double inv_h2) {
-  __shared__ double tile[32][33];
-  const size_t l0 = (size_t)blockIdx.y * 32;
+                                                    void *__restrict__ out, int m, int eig,
+                                                    double scale, double inv_h2) {
+  __shared__ double tile[2][32][33];  // [line of the pair][row r][mode kk]
+  const int o = DIM == 3 ? m : 1;
+  const size_t lines = (size_t)m * o;
+  const size_t N = 2 * (size_t)(m + 1);
+  const size_t ncl = (size_t)((m + 1) / 2) * o;
   const int k0 = 1 + blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int r = ty; r < 32; r += 8) {
-    const size_t line = l0 + r;
+    size_t c;
+    bool ok;
+    if (DIM == 3) {
+      const int sx = blockIdx.y * 32 + r;
+      c = (size_t)blockIdx.z * o + sx;
+      ok = sx < o;
+    } else {
+      c = (size_t)blockIdx.y * 32 + r;
+      ok = c < ncl;
+    }
     const int k = k0 + tx;
-    tile[r][tx] = (line < lines && k <= m) ? dst_get(Z, m, line, k) : 0.0;
+    const double2 v = (ok && k <= m) ? Z[c * N + k] : make_double2(0.0, 0.0);
+    tile[0][r][tx] = -0.5 * v.y;  // line a: real part of its extension
+    tile[1][r][tx] = 0.5 * v.x;   // line a+1: imaginary part
   }
   __syncthreads();
-  const size_t outer = lines / (size_t)m;  // lines of the next pass per mode
-  for (int r = ty; r < 32; r += 8) {
-    const int k = k0 + r;
-    const size_t line = l0 + tx;
-    if (k > m || line >= lines) continue;
-    double v = tile[tx][r];
-    if (eig) v = v * dst_eig<DIM>(m, line, k, scale, inv_h2);
-    if (EXT)
-      dst_put(dst, m, lines, (size_t)(k - 1) * outer + line / (size_t)m,
-              (int)(line % (size_t)m), v);
-    else
-      dst[(size_t)(k - 1) * lines + line] = v;
+  const int r = tx;
+  for (int j = ty; j < 32; j += 8) {
+    const int ai = j & 1, kk = 2 * (j >> 1);
+    const int a = DIM == 3 ? 2 * (int)blockIdx.z + ai : (int)blockIdx.y * 64 + 2 * r + ai;
+    const int sx = DIM == 3 ? (int)blockIdx.y * 32 + r : 0;
+    const int k = k0 + kk;
+    if (a >= m || sx >= o || k > m) continue;
+    const size_t line = (size_t)a * o + sx;
+    const bool has1 = k + 1 <= m;
+    double v0 = tile[ai][r][kk];
+    double v1 = has1 ? tile[ai][r][kk + 1] : 0.0;
+    if (eig) {
+      v0 *= dst_eig<DIM>(m, line, k, scale, inv_h2);
+      if (has1) v1 *= dst_eig<DIM>(m, line, k + 1, scale, inv_h2);
+    }
+    if (EXT) {
+      // next pass: line (k-1) o + a (3D) / k-1 (2D), element s (3D) / a (2D)
+      const int te = DIM == 3 ? sx : a;
+      double2 *zl = (double2 *)out + ((size_t)((k - 1) >> 1) * o + (DIM == 3 ? a : 0)) * N;
+      zl[te + 1] = make_double2(v0, v1);
+      zl[N - 1 - te] = make_double2(-v0, -v1);
+      if (te == 0) {
+        zl[0] = make_double2(0.0, 0.0);
+        zl[m + 1] = make_double2(0.0, 0.0);
+      }
+    } else {
+      double *d = (double *)out;
+      d[(size_t)(k - 1) * lines + line] = v0;
+      if (has1) d[(size_t)k * lines + line] = v1;
+    }
   }
 }
 
@@ -159,8 +183,8 @@ struct DstSizes {
   size_t E, C;
 };
 size_t dst_pairs(int dim, int m) {
-  const size_t lines = dim == 3 ? (size_t)m * m : (size_t)m;
-  return (lines + 1) / 2;  // complex lines: two real lines each
+  // complex lines: lines a, a+1 of the same s share one
+  return (size_t)((m + 1) / 2) * (dim == 3 ? (size_t)m : 1);
 }
 
 DstSizes dst_sizes(int dim, int m) {
@@ -186,24 +210,26 @@ hipError_t dst_pass(gmg_dst *p, double *out, int eig, double scale) {
   void *o[1] = {p->C};
   if (rocfft_execute(p->plan, in, o, p->info) != rocfft_status_success) return hipErrorUnknown;
   const double h = 1.0 / double(m + 1);
-  const dim3 grid((m + 31) / 32, (unsigned)((p->lines + 31) / 32));
+  const unsigned kt = (m + 31) / 32;
+  const dim3 grid = p->dim == 3 ? dim3(kt, kt, (m + 1) / 2)
+                                : dim3(kt, (unsigned)((dst_pairs(2, m) + 31) / 32), 1);
   const double2 *Z = (const double2 *)p->C;
-  double *dst = out ? out : p->E;
+  void *dst = out ? (void *)out : (void *)p->E;
   const double ih2 = 1.0 / (h * h);
   if (p->dim == 2) {
     if (out)
-      gmg_launch((k_dst_unpack<2, false>), grid, dim3(256), 0, p->stream, Z, dst, m, p->lines, eig,
-                 scale, ih2);
+      gmg_launch((k_dst_unpack<2, false>), grid, dim3(256), 0, p->stream, Z, dst, m, eig, scale,
+                 ih2);
     else
-      gmg_launch((k_dst_unpack<2, true>), grid, dim3(256), 0, p->stream, Z, dst, m, p->lines, eig,
-                 scale, ih2);
+      gmg_launch((k_dst_unpack<2, true>), grid, dim3(256), 0, p->stream, Z, dst, m, eig, scale,
+                 ih2);
   } else {
     if (out)
-      gmg_launch((k_dst_unpack<3, false>), grid, dim3(256), 0, p->stream, Z, dst, m, p->lines, eig,
-                 scale, ih2);
+      gmg_launch((k_dst_unpack<3, false>), grid, dim3(256), 0, p->stream, Z, dst, m, eig, scale,
+                 ih2);
     else
-      gmg_launch((k_dst_unpack<3, true>), grid, dim3(256), 0, p->stream, Z, dst, m, p->lines, eig,
-                 scale, ih2);
+      gmg_launch((k_dst_unpack<3, true>), grid, dim3(256), 0, p->stream, Z, dst, m, eig, scale,
+                 ih2);
   }
   return hipGetLastError();
 }
@@ -268,9 +294,9 @@ gmg_status gmg_dst_solve(gmg_dst *p, double *u, const double *f) {
   if (!p || !u || !f || (const double *)u == f) return GMG_ERR_INVALID_ARG;
   const double scale = std::pow(2.0 / double(p->m + 1), p->dim);
   const int m = p->m;
-  const size_t n = p->lines * (size_t)m;
-  const int nb = (int)std::min<size_t>((n + 255) / 256, 1 << 20);
-  gmg_launch(k_dst_pack, dim3(nb), dim3(256), 0, p->stream, f, p->E, m, p->lines);
+  const dim3 pgrid((m + 1 + 255) / 256, (unsigned)std::min<size_t>(dst_pairs(p->dim, m), 65535));
+  gmg_launch(k_dst_pack, pgrid, dim3(256), 0, p->stream, f, (double2 *)p->E, m,
+             p->dim == 3 ? m : 1);
   if (hipGetLastError() != hipSuccess) return GMG_ERR_HIP;
   // d forward passes (the last divides by lambda), d inverse passes; only the
   // last one writes u
