@@ -69,10 +69,21 @@ __device__ __forceinline__ void update_state(SolveState *st, double tot) {
 // three-plane LDS ring; the next u plane and the next f plane are loaded into
 // registers one step ahead, so global latency overlaps the LDS work.
 // ------------------------------------------------------------------------
+// Argument block of this workgroup: the kernel argument, or (batch mode) table
+// entry e, read through the scalar cache so that the plane resources built
+// from it stay in scalar registers.
+template <typename A>
+__device__ __forceinline__ A uniform_entry(const A &arg, const A *tbl, unsigned e) {
+  if (!tbl) return arg;
+  A r;
+  __builtin_memcpy(&r, (const __attribute__((address_space(4))) A *)tbl + e, sizeof(A));
+  return r;
+}
+
 template <typename T, int DIM, int CX, int CY, int NT>
 __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const RestrictArgs<T> *tbl,
                                                  int ncx, int ncy, int czc, int nblocks) {
-  const RestrictArgs<T> a = tbl ? tbl[blockIdx.y] : arg;  // batch: one entry per blockIdx.y
+  const RestrictArgs<T> a = uniform_entry(arg, tbl, blockIdx.y);  // batch: one entry per blockIdx.y
   if (a.active && *a.active == 0) return;
   if (a.fin_state && blockIdx.x == 0 && threadIdx.x < 64) {
     const double tot = sum_partials(a.fin_partials, a.fin_n);
@@ -99,11 +110,12 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
   const T inv_h2 = T(a.inv_h2);
   const T two_d = T(2 * DIM);
   const int planeS = DIM == 3 ? m * m : m;
-  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u);
-  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
   GMG_GLOBAL T *__restrict__ fcg = gbl(a.fc);
 
-  // u-tile element q -> plane offset (or -1 outside the domain)
+  // u-tile element q -> byte offset in its plane, out of range (kOOB) outside
+  // the domain: loads go through one-plane buffer resources, so the zero
+  // boundary and a missing u (zero start) cost no branches and the next
+  // plane's loads stay in flight across the current plane's work
   int uo[NU];
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
@@ -111,25 +123,28 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
     const int ux = q % UX, uy = q / UX;
     const int x = 2 * A0 - 1 + ux, y = DIM == 3 ? 2 * B0 - 1 + uy : 0;
     const bool in = q < UX * UY && x >= 0 && x < m && y >= 0 && y < m;
-    uo[k] = in ? (DIM == 3 ? y * m + x : x) : -1;
+    uo[k] = in ? (DIM == 3 ? y * m + x : x) * (int)sizeof(T) : kOOB;
   }
   int ro[NR];
+  bool rin[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const int q = threadIdx.x + NT * k;
     const int rx = q % RX, ry = q / RX;
     const int x = 2 * A0 + rx, y = DIM == 3 ? 2 * B0 + ry : 0;
-    const bool in = q < RX * RY && x < m && y < m;
-    ro[k] = in ? (DIM == 3 ? y * m + x : x) : -1;
+    rin[k] = q < RX * RY && x < m && y < m;
+    ro[k] = rin[k] ? (DIM == 3 ? y * m + x : x) * (int)sizeof(T) : kOOB;
   }
   auto load_u = [&](int z, T *v) {
+    // no u: a plane index outside the grid gives a resource with no records
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.u ? a.u : a.f, a.u ? z : -1, m, planeS);
 #pragma unroll
-    for (int k = 0; k < NU; ++k)
-      v[k] = (ug && z >= 0 && z < m && uo[k] >= 0) ? ug[z * planeS + uo[k]] : T(0);
+    for (int k = 0; k < NU; ++k) v[k] = bload<T>(r, uo[k]);
   };
   auto load_f = [&](int z, T *v) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.f, z, m, planeS);
 #pragma unroll
-    for (int k = 0; k < NR; ++k) v[k] = (z >= 0 && z < m && ro[k] >= 0) ? fg[z * planeS + ro[k]] : T(0);
+    for (int k = 0; k < NR; ++k) v[k] = bload<T>(r, ro[k]);
   };
   auto store_u = [&](int z, const T *v) {
     T *dst = su[(z + 3) % 3];
@@ -173,7 +188,7 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
       if (q >= RX * RY) continue;
       const int rx = q % RX, ry = q / RX;
       T r = T(0);
-      if (ro[k] >= 0 && zf < m) {
+      if (rin[k] && zf < m) {
         const int c = (ry + (DIM == 3 ? 1 : 0)) * UX + rx + 1;  // centre in the u tile
         T nb = u0[c - 1] + u0[c + 1];
         if (DIM == 3) {
