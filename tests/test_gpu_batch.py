@@ -67,6 +67,28 @@ def test_batch_matches_single_oracle_solves():
         assert rels[q] <= 1e-10
 
 
+@pytest.mark.parametrize("post_forward", [False, True])
+def test_batch_equals_single_plans_bitwise(post_forward):
+    """A batch runs the small coarse levels through the LDS-tile ascent
+    kernel, single-problem plans through the plane-marching pass: every
+    half-sweep is the same per-point expression, so both give the same cycle
+    count and the same bits."""
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import Plan
+
+    probs = [(3, 63), (2, 255), (3, 31), (3, 127), (2, 511)]
+    flags = capi.GMG_POST_FORWARD if post_forward else 0
+    rhs = [wl.batch_rhs(17, q, d, m) for q, (d, m) in enumerate(probs)]
+    _, us, its, _, sts = run_batch(probs, rhs, flags=flags)
+    for q, (d, m) in enumerate(probs):
+        plan = Plan(d, levels_of(m), flags=flags)
+        ud = torch.zeros((m,) * d, dtype=torch.float64, device="cuda")
+        st, it, _ = plan.solve(ud, dev(rhs[q]), rtol=1e-10)
+        assert (sts[q], its[q]) == (st, it), (q, d, m)
+        assert np.array_equal(us[q], host(ud)), (q, d, m)
+        plan.close()
+
+
 def test_batch_per_problem_stop_tests():
     """A zero RHS stops at once, an easy RHS early, the rest later; the
     batch result of each equals its own solve."""
