@@ -232,7 +232,8 @@ def bench_dst(args, spec):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "dim": d, "side": m, "levels": L,
-                   "method": "DST-I along every axis (rocFFT batched real FFTs), eigenvalue "
+                   "method": "DST-I along every axis (rocFFT batched complex FFTs, two real lines "
+                             "each), eigenvalue "
                              "division, inverse", "l2h_error": err,
                    "workspace_MB": solver.workspace.numel() / 1e6},
     }

@@ -138,8 +138,10 @@ def traffic_table(dim, m):
 
 def copy_calibration(mib, reps=20):
     """A plain device copy of known size (torch's copy kernel): the yardstick
-    that converts the HBM byte counters of a profiler into bytes, and the
-    practical streaming ceiling of the device."""
+    that converts the HBM byte counters of a profiler into bytes.  Also
+    torch's elementwise add of two arrays into a third, the same mix of two
+    reads and one write per point as a smoothing pass: a streaming ceiling
+    for that traffic pattern."""
     n = mib * (1 << 20) // 8
     src = torch.rand(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -147,6 +149,10 @@ def copy_calibration(mib, reps=20):
     row = dict(kernel="copy", bytes_read=n * 8, bytes_written=n * 8, us=us,
                gbs=2 * n * 8 / (us * 1e-6) / 1e9)
     print(json.dumps(row), flush=True)
+    src2 = torch.rand_like(src)
+    us = _time(lambda: torch.add(src, src2, out=dst), reps)
+    print(json.dumps(dict(kernel="elementwise_add", bytes_read=2 * n * 8, bytes_written=n * 8,
+                          us=us, gbs=3 * n * 8 / (us * 1e-6) / 1e9)), flush=True)
     return row
 
 
