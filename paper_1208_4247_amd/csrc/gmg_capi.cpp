@@ -479,7 +479,8 @@ LevelSet<float> &levels_of<float>(gmg_plan *p) {
   return p->s;
 }
 
-// Small coarse levels go through the fused LDS-tile kernels (red-black only).
+// Small coarse levels go through the fused LDS-tile kernels (red-black only;
+// single-problem plans use the descent kernel, batches both).
 bool use_small(const gmg_plan *p, int dim, int m, int nu, size_t elem) {
   return p->cfg.smoother == GMG_SMOOTH_RBGS && !(p->cfg.flags & GMG_NO_FUSED_COARSE) && nu >= 1 &&
          small_level_ok(dim, m, nu, elem);
