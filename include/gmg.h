@@ -19,8 +19,9 @@
  *
  * OWNERSHIP
  *   The caller owns every device buffer (u, f, the workspace) and the stream;
- *   the library never allocates device memory.  The library owns only the
- *   host-side plan object.  Device pointers must be hipMalloc'ed (or
+ *   the library never allocates device memory (one exception: the FFT plan
+ *   of the sine-transform solver, whose twiddle tables rocFFT allocates).
+ *   The library owns only the host-side plan object.  Device pointers must be hipMalloc'ed (or
  *   torch-allocated) memory of the current device, 8-byte aligned.  Arrays
  *   passed to one call must not overlap unless stated.
  *
@@ -264,7 +265,9 @@ typedef struct gmg_dst gmg_dst; /* opaque, host side */
  * holds the odd extensions and the FFT coefficients of every line and the
  * FFT library's work area (about 4 grids in all).  dim 2 (levels <= 14) or 3
  * (levels <= 10).  stream: a hipStream_t (NULL = default).  The batched FFTs
- * are rocFFT's; plan creation may compile FFT kernels on first use.  Errors:
+ * are rocFFT's; plan creation may compile FFT kernels on first use, and the
+ * plan keeps twiddle tables in device memory that rocFFT allocates itself
+ * (released by gmg_dst_destroy).  Errors:
  * GMG_ERR_INVALID_ARG, GMG_ERR_WORKSPACE, GMG_ERR_HIP (FFT library failure). */
 gmg_status gmg_dst_setup(int dim, int levels, void *workspace, size_t *ws_bytes, void *stream,
                          gmg_dst **out);
