@@ -234,37 +234,70 @@ __global__ void __launch_bounds__(CX *CY) k_restrict_fe(FeRestrictArgs a) {
   const int tile = blockIdx.x;
   const int a0 = (tile % a.ntx) * CX, b0 = (tile / a.ntx) * CY;
   const int fx0 = 2 * a0, fy0 = 2 * b0;  // fine storage index of the footprint's corner
-  const size_t plane = (size_t)m * m;
   const double diag = 2.0 * DIM;
   const int ta = t % CX, tb = t / CX;
   const int ca = a0 + ta, cb = b0 + tb;
   // this thread's coarse point in local footprint coordinates
   const int lx = 2 * ta + 1, ly = 2 * tb + 1;
 
-  auto load_u = [&](int slot, int z) {
-    for (int p = t; p < NU; p += NT) {
-      const int x = fx0 - 1 + p % UW, y = fy0 - 1 + p / UW;
-      double v = 0.0;
-      if (a.u && x >= 0 && x < m && y >= 0 && y < m && z >= 0 && z < m)
-        v = gbl(a.u)[(DIM == 3 ? (size_t)z * plane : 0) + (size_t)y * m + x];
-      Us[slot][p] = v;
+  // Byte offsets of this thread's u-footprint and residual elements inside a
+  // plane (the whole grid in 2D), out of range (kOOB) outside the grid.
+  // Loads go through buffer resources, so they need no branches and stay in
+  // flight across the work that does not use them.
+  constexpr int UPT = (NU + NT - 1) / NT;
+  constexpr int RPT = (NR + NT - 1) / NT;
+  int uo[UPT], ro[RPT];
+  bool rin[RPT];
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) {
+    const int p = t + q * NT;
+    const int x = fx0 - 1 + p % UW, y = fy0 - 1 + p / UW;
+    uo[q] = (p < NU && x >= 0 && x < m && y >= 0 && y < m) ? (y * m + x) * 8 : kOOB;
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int p = t + k * NT;
+    const int x = fx0 + p % RW, y = fy0 + p / RW;
+    rin[k] = p < NR && x < m && y < m;
+    ro[k] = rin[k] ? (y * m + x) * 8 : kOOB;
+  }
+  const int mm = m * m;
+  double pre[UPT], fcur[RPT], fnext[RPT];
+  auto fetch_u = [&](int z) {
+    // no u: a plane index outside the grid gives a resource with no records
+    const __amdgpu_buffer_rsrc_t r =
+        plane_rsrc(a.u ? a.u : a.f, a.u ? z : -1, DIM == 3 ? m : 1, mm);
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) pre[q] = bload<double>(r, uo[q]);
+  };
+  auto fetch_f = [&](int z, double *v) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.f, z, DIM == 3 ? m : 1, mm);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) v[k] = bload<double>(r, ro[k]);
+  };
+  auto store_u = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      const int p = t + q * NT;
+      if (p < NU) Us[slot][p] = pre[q];
     }
   };
-  // residual of fine plane z into Rs (ring slots of planes z-1, z, z+1)
+  // residual of fine plane z into Rs (ring slots of planes z-1, z, z+1; f
+  // of plane z in fcur)
   auto residual = [&](int z, int sm, int s0, int sp) {
-    for (int p = t; p < NR; p += NT) {
-      const int rx = p % RW, ry = p / RW;
-      const int x = fx0 + rx, y = fy0 + ry;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int p = t + k * NT;
+      if (p >= NR) continue;
       double r = 0.0;
-      if (x < m && y < m && z >= 0 && z < m) {
-        const double fv = gbl(a.f)[(DIM == 3 ? (size_t)z * plane : 0) + (size_t)y * m + x];
+      if (rin[k] && (DIM == 2 || (z >= 0 && z < m))) {
         if (a.u) {
-          const int q = (ry + 1) * UW + (rx + 1);
+          const int q = (p / RW + 1) * UW + (p % RW + 1);
           double nb = Us[s0][q - 1] + Us[s0][q + 1] + Us[s0][q - UW] + Us[s0][q + UW];
           if (DIM == 3) nb = nb + Us[sm][q] + Us[sp][q];
-          r = fv - (diag * Us[s0][q] - nb) * a.inv_h2;
+          r = fcur[k] - (diag * Us[s0][q] - nb) * a.inv_h2;
         } else {
-          r = fv;
+          r = fcur[k];
         }
       }
       Rs[p] = r;
@@ -274,7 +307,9 @@ __global__ void __launch_bounds__(CX *CY) k_restrict_fe(FeRestrictArgs a) {
   const bool mine = ca < mc && cb < mc;
 
   if (DIM == 2) {
-    load_u(0, 0);
+    fetch_u(0);
+    fetch_f(0, fcur);
+    store_u(0);
     __syncthreads();
     residual(0, 0, 0, 0);
     __syncthreads();
@@ -290,30 +325,21 @@ __global__ void __launch_bounds__(CX *CY) k_restrict_fe(FeRestrictArgs a) {
   const int c1 = min(mc, c0 + a.czc);
   if (c0 >= c1) return;
   const size_t cplane = (size_t)mc * mc;
-  // fine planes 2c0 .. 2c1 (storage); ring slot of plane z is (z + 3) % 3.
-  // The u plane two ahead is loaded into registers while the residual of
-  // plane z is formed, and stored into the slot plane z - 1 frees.
-  constexpr int UPT = (NU + NT - 1) / NT;
-  double pre[UPT];
-  auto fetch = [&](int z) {
-#pragma unroll
-    for (int q = 0; q < UPT; ++q) {
-      const int p = t + q * NT;
-      const int x = fx0 - 1 + p % UW, y = fy0 - 1 + p / UW;
-      double v = 0.0;
-      if (p < NU && a.u && x >= 0 && x < m && y >= 0 && y < m && z >= 0 && z < m)
-        v = gbl(a.u)[(size_t)z * plane + (size_t)y * m + x];
-      pre[q] = v;
-    }
-  };
-  load_u((2 * c0 - 1 + 3) % 3, 2 * c0 - 1);
-  load_u((2 * c0 + 3) % 3, 2 * c0);
-  load_u((2 * c0 + 1 + 3) % 3, 2 * c0 + 1);
+  // Fine planes 2c0 .. 2c1 (storage); ring slot of plane z is (z + 3) % 3.
+  // The u plane two ahead and the f plane one ahead are loaded into
+  // registers while the residual of plane z is formed; the u plane is stored
+  // into the slot plane z - 1 frees.
+  for (int zz = 2 * c0 - 1; zz <= 2 * c0 + 1; ++zz) {
+    fetch_u(zz);
+    store_u((zz + 3) % 3);
+  }
+  fetch_f(2 * c0, fcur);
   __syncthreads();
   double acc = 0.0;
   for (int z = 2 * c0; z <= 2 * c1; ++z) {
     const bool more = z + 2 <= 2 * c1 + 1;
-    if (more) fetch(z + 2);
+    if (more) fetch_u(z + 2);
+    if (z < 2 * c1) fetch_f(z + 1, fnext);
     residual(z, (z - 1 + 3) % 3, (z + 3) % 3, (z + 1 + 3) % 3);
     __syncthreads();
     if (z & 1) {
@@ -329,13 +355,11 @@ __global__ void __launch_bounds__(CX *CY) k_restrict_fe(FeRestrictArgs a) {
       // the plane below coarse plane z / 2: directions with z = -1
       acc = R(0, 0) + R(-1, 0) + R(0, -1) + R(-1, -1);
     }
-    if (more) {
-      // plane z + 2 into the slot of plane z - 1 (no longer read)
+    // plane z + 2 into the slot of plane z - 1 (no longer read)
+    if (more) store_u((z + 2) % 3);
+    if (z < 2 * c1) {
 #pragma unroll
-      for (int q = 0; q < UPT; ++q) {
-        const int p = t + q * NT;
-        if (p < NU) Us[(z + 2) % 3][p] = pre[q];
-      }
+      for (int k = 0; k < RPT; ++k) fcur[k] = fnext[k];
     }
     __syncthreads();  // Rs and the ring are reused
   }
