@@ -514,22 +514,36 @@ __global__ void __launch_bounds__(256) k_prolong_add(const T *in, const T *__res
   const int z = DIM == 3 ? (int)blockIdx.z : 0;
   if (x < m) {
     const size_t p = ((size_t)z * m + y) * m + x;
-    // canonical order: average along x, then y, then z (zero coarse boundary)
+    // canonical order: average along x, then y, then z (zero coarse boundary).
+    // Per axis the two coarse neighbours i0 = (x-1)/2 rounded down and
+    // i1 = x/2 coincide for odd x; all of them are loaded unconditionally
+    // through a buffer resource with out-of-range offsets for the boundary,
+    // and the parity only selects, so the loads issue together.
+    const size_t nc = DIM == 3 ? (size_t)mc * mc * mc : (size_t)mc * mc;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T *>(ec), (short)0, (int)(nc * sizeof(T)), 0x00020000);
     auto cv = [&](int a, int b, int c) -> T {
-      if (a < 0 || b < 0 || a >= mc || b >= mc || (DIM == 3 && (c < 0 || c >= mc))) return T(0);
-      return ec[DIM == 3 ? ((size_t)c * mc + b) * mc + a : (size_t)b * mc + a];
+      const bool ok = a >= 0 && b >= 0 && a < mc && b < mc && (DIM == 2 || (c >= 0 && c < mc));
+      const int off = DIM == 3 ? (c * mc + b) * mc + a : b * mc + a;
+      return bload<T>(rc, ok ? off * (int)sizeof(T) : kOOB);
     };
+    const int x0 = (x - 1) >> 1, x1 = x >> 1;
+    const int y0 = (y - 1) >> 1, y1 = y >> 1;
     auto xs = [&](int b, int c) {
-      return (x & 1) ? cv((x - 1) >> 1, b, c) : T(0.5) * (cv((x >> 1) - 1, b, c) + cv(x >> 1, b, c));
+      const T l = cv(x0, b, c), r = cv(x1, b, c);
+      return (x & 1) ? l : T(0.5) * (l + r);
     };
     auto ys = [&](int c) {
-      return (y & 1) ? xs((y - 1) >> 1, c) : T(0.5) * (xs((y >> 1) - 1, c) + xs(y >> 1, c));
+      const T l = xs(y0, c), r = xs(y1, c);
+      return (y & 1) ? l : T(0.5) * (l + r);
     };
     T s;
-    if (DIM == 3)
-      s = (z & 1) ? ys((z - 1) >> 1) : T(0.5) * (ys((z >> 1) - 1) + ys(z >> 1));
-    else
+    if (DIM == 3) {
+      const T l = ys((z - 1) >> 1), r = ys(z >> 1);
+      s = (z & 1) ? l : T(0.5) * (l + r);
+    } else {
       s = ys(0);
+    }
     out[p] = (in ? in[p] : T(0)) + s;
   }
 }

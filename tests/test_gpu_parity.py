@@ -118,6 +118,26 @@ def test_rb_smooth_zero_start_and_prolong(dim, m, backward):
     assert maxrel(host(out), want) <= 1e-13
 
 
+@pytest.mark.parametrize("dim,m", [(2, 3), (2, 127), (2, 1023), (3, 3), (3, 31), (3, 127),
+                                   (3, 255)])
+@pytest.mark.parametrize("with_in", [False, True])
+def test_prolong_add_parity(dim, m, with_in):
+    """The stand-alone (bi/tri)linear interpolation (full multigrid's
+    interpolation into zero, and u + P e): every fine parity, the zero coarse
+    boundary on all sides, in place and out of place."""
+    plan = Plan(dim, levels_of(m))
+    mc = (m - 1) // 2
+    e = wl.rhs_uniform(dim, mc, seed=140 + m)
+    u = wl.rhs_uniform(dim, m, seed=141 + m) if with_in else np.zeros((m,) * dim)
+    want = oracle.prolong_add(e, u)
+    out = torch.empty((m,) * dim, dtype=torch.float64, device="cuda")
+    plan.op_prolong_add(0, dev(u) if with_in else None, dev(e), out)
+    assert maxrel(host(out), want) <= 1e-15
+    ud = dev(u)
+    plan.op_prolong_add(0, ud, dev(e), ud)
+    assert maxrel(host(ud), want) <= 1e-15
+
+
 @pytest.mark.parametrize("dim,m", [(2, 63), (2, 1023), (3, 31), (3, 127)])
 @pytest.mark.parametrize("nsweeps", [0, 1, 2])
 def test_fused_input_residual_norm(dim, m, nsweeps):
