@@ -379,8 +379,8 @@ def main():
     ap.add_argument("--nu2", type=int, default=None, help="FMG workloads: post-sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the solver runs every level of one "
-              "problem on a single device); run with --gpus 1", file=sys.stderr)
+        print("bench.py: measures one GPU only (the solver runs every level of one problem on "
+              "a single device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

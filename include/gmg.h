@@ -56,7 +56,7 @@ typedef enum {
   GMG_ERR_NONFINITE = -3,   /* a residual norm was NaN or Inf               */
   GMG_ERR_DIVERGED = -4,    /* relative residual grew above 1e3             */
   GMG_ERR_HIP = -5,         /* a HIP runtime call failed                    */
-  GMG_ERR_UNSUPPORTED = -6  /* valid request this build does not provide    */
+  GMG_ERR_UNSUPPORTED = -6  /* valid request the library does not provide   */
 } gmg_status;
 
 /* Smoother (Sec. 3.2, Remark 1; Table 5).  RBGS: red-black Gauss-Seidel,
@@ -136,7 +136,7 @@ gmg_status gmg_config_default(gmg_config *cfg, int dim, int levels);
  * int32 index space, nu1 + nu2 < 1, nu > 8, omega outside (0,1],
  * inner_cycles < 1, nproblems < 1, NULL out/ws_bytes), GMG_ERR_WORKSPACE
  * (workspace smaller than required or not 256-byte aligned),
- * GMG_ERR_UNSUPPORTED (a combination this build does not run, e.g. batch
+ * GMG_ERR_UNSUPPORTED (a combination the library does not run, e.g. batch
  * with mixed precision), GMG_ERR_HIP. */
 gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, const int *levels,
                      void *workspace, size_t *ws_bytes, void *stream, gmg_plan **out);
