@@ -17,16 +17,6 @@ __device__ __forceinline__ int xcd_remap_t(int bid, int n) {
   return xcd * per + min(xcd, rem) + loc;
 }
 
-template <typename T>
-__device__ __forceinline__ T ld0(const GMG_GLOBAL T *__restrict__ p, int m, int x, int y, int z, int dim) {
-  if (x < 0 || y < 0 || x >= m || y >= m) return T(0);
-  if (dim == 3) {
-    if (z < 0 || z >= m) return T(0);
-    return p[((size_t)z * m + y) * m + x];
-  }
-  return p[(size_t)y * m + x];
-}
-
 // ------------------------------------------------------------------------
 // Fixed-order reduction of per-block partial sums (the first 64 threads) and
 // the stop test of the solve loop (Algorithm 3's while condition).
@@ -237,40 +227,91 @@ __global__ void __launch_bounds__(NT) k_restrict(RestrictArgs<T> arg, const Rest
 }
 
 // ------------------------------------------------------------------------
-// Residual (and/or per-block sums of its square), one thread per point.
+// Residual r = f - A u (and/or per-workgroup sums of its square), marching
+// over planes like the refinement step: a workgroup owns a TX x TY tile
+// (TX x 1 rows in 2D) and a chunk of planes; u planes sit in a four-slot LDS
+// ring with a one-point halo, and the next u plane and the current f plane
+// come in through buffer loads that stay in flight across the plane's work.
+// Neighbours are summed in the order x-1, x+1, y-1, y+1, z-1, z+1.
 // ------------------------------------------------------------------------
-template <typename T, int DIM, int NT>
-__global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a) {
-  if (a.active && *a.active == 0) return;
+template <typename T, int DIM, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a, int cz) {
+  if (a.active && *gbl(a.active) == 0) return;
+  constexpr int HX = TX + 2, HY = DIM == 3 ? TY + 2 : 1, HP = HX * HY;
+  constexpr int NL = (HP + NT - 1) / NT;
+  __shared__ T ring[4][HP];
   const int m = a.m;
-  const size_t N = DIM == 3 ? (size_t)m * m * m : (size_t)m * m;
-  double acc = 0.0;
+  const int planeS = DIM == 3 ? m * m : m;
+  const int ntx = (m + TX - 1) / TX, nty = DIM == 3 ? (m + TY - 1) / TY : 1;
+  const int bid = xcd_remap_t(blockIdx.x, gridDim.x);
+  const int tx = bid % ntx;
+  const int rest = bid / ntx;
+  const int ty = DIM == 3 ? rest % nty : 0;
+  const int tzc = DIM == 3 ? rest / nty : rest;
+  const int X0 = tx * TX, Y0 = ty * TY;
+  const int Z0 = tzc * cz, Z1 = min(Z0 + cz, m);
+  // halo-tile elements this thread loads (byte offsets in a plane)
+  int hoff[NL];
+  int hj[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int j = threadIdx.x + NT * k;
+    hj[k] = j < HP ? j : -1;
+    const int hx = j % HX, hy = j / HX;
+    const int x = X0 - 1 + hx, y = DIM == 3 ? Y0 - 1 + hy : 0;
+    const bool in = j < HP && x >= 0 && x < m && (DIM == 2 || (y >= 0 && y < m));
+    hoff[k] = in ? ((DIM == 3 ? y * m : 0) + x) * (int)sizeof(T) : kOOB;
+  }
+  T uv[NL];
+  auto load_plane = [&](int z, T *v) {
+    // no u (zero iterate): a plane index outside the grid gives no records
+    const __amdgpu_buffer_rsrc_t ru = plane_rsrc(a.u ? a.u : a.f, a.u ? z : -1, m, planeS);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) v[k] = bload<T>(ru, hoff[k]);
+  };
+  auto store_plane = [&](int z, const T *v) {
+    T *dst = ring[z & 3];
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+      if (hj[k] >= 0) dst[hj[k]] = v[k];
+  };
+  // this thread's point
+  const int cx = threadIdx.x % TX, cy = threadIdx.x / TX;
+  const int gx = X0 + cx, gy = DIM == 3 ? Y0 + cy : 0;
+  const bool mine = threadIdx.x < TX * TY && gx < m && (DIM == 2 || gy < m);
+  const int ci = (DIM == 3 ? (cy + 1) * HX : 0) + cx + 1;
+  const int coff = (DIM == 3 ? gy * m : 0) + gx;
+  // prologue: planes Z0 - 1, Z0, Z0 + 1 in the ring
+  load_plane(Z0 - 1, uv);
+  store_plane(Z0 - 1, uv);
+  load_plane(Z0, uv);
+  store_plane(Z0, uv);
+  load_plane(Z0 + 1, uv);
+  store_plane(Z0 + 1, uv);
+  __syncthreads();
   const T inv_h2 = T(a.inv_h2);
-  const GMG_GLOBAL T *__restrict__ ug = gbl(a.u);
-  const GMG_GLOBAL T *__restrict__ fg = gbl(a.f);
-  for (size_t p = (size_t)blockIdx.x * NT + threadIdx.x; p < N; p += (size_t)gridDim.x * NT) {
-    const int x = (int)(p % m);
-    const size_t rest = p / m;
-    const int y = (int)(rest % m);
-    const int z = DIM == 3 ? (int)(rest / m) : 0;
-    T nb;
-    T c;
-    if (DIM == 3) {
-      c = ug[p];
-      nb = ld0(ug, m, x - 1, y, z, 3) + ld0(ug, m, x + 1, y, z, 3);
-      nb += ld0(ug, m, x, y - 1, z, 3);
-      nb += ld0(ug, m, x, y + 1, z, 3);
-      nb += ld0(ug, m, x, y, z - 1, 3);
-      nb += ld0(ug, m, x, y, z + 1, 3);
-    } else {
-      c = ug[p];
-      nb = ld0(ug, m, x - 1, y, 0, 2) + ld0(ug, m, x + 1, y, 0, 2);
-      nb += ld0(ug, m, x, y - 1, 0, 2);
-      nb += ld0(ug, m, x, y + 1, 0, 2);
+  double acc = 0.0;
+  for (int z = Z0; z < Z1; ++z) {
+    load_plane(z + 2, uv);  // in flight during this plane's residual
+    const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.f, z, m, planeS);
+    const T fv = bload<T>(rf, mine ? coff * (int)sizeof(T) : kOOB);
+    if (mine) {
+      const T *P = ring[z & 3];
+      const T c = P[ci];
+      T nb = P[ci - 1] + P[ci + 1];
+      if (DIM == 3) {
+        nb += P[ci - HX];
+        nb += P[ci + HX];
+      }
+      nb += ring[(z - 1) & 3][ci];
+      nb += ring[(z + 1) & 3][ci];
+      const T r = fv - (T(2 * DIM) * c - nb) * inv_h2;
+      if (a.r) gbl(a.r)[(size_t)z * planeS + coff] = r;
+      acc += double(r) * double(r);
     }
-    const T r = fg[p] - (T(2 * DIM) * c - nb) * inv_h2;
-    if (a.r) gbl(a.r)[p] = r;
-    acc += double(r) * double(r);
+    // slot (z + 2) & 3 last held plane z - 2, read by nobody in this step
+    store_plane(z + 2, uv);
+    __syncthreads();
   }
   if (a.partials) {
     __shared__ double red[NT / 64];
@@ -279,20 +320,13 @@ __global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a) {
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < NT / 64; ++w) s += red[w];
-      gbl(a.partials)[blockIdx.x] = s;
+      double sum = 0.0;
+      for (int w = 0; w < NT / 64; ++w) sum += red[w];
+      gbl(a.partials)[blockIdx.x] = sum;
     }
   }
 }
 
-int residual_blocks(int dim, int m) {
-  const size_t N = dim == 3 ? (size_t)m * m * m : (size_t)m * m;
-  size_t b = (N + 255) / 256;
-  if (b > 4096) b = 4096;
-  if (b < 1) b = 1;
-  return (int)b;
-}
 
 // ------------------------------------------------------------------------
 // Refinement step: x_out = x + e (FP64), r32 = float(f - A x_out), norm
@@ -424,6 +458,9 @@ int ir_blocks(int dim, int m) {
                               : (long)((m + kIrTX2 - 1) / kIrTX2);
   return (int)(tiles * ((m + cz - 1) / cz));
 }
+
+// the residual kernel uses the refinement step's tiling and plane chunks
+int residual_blocks(int dim, int m) { return ir_blocks(dim, m); }
 
 // The stop test after a kernel that left n partial sums: 1024 threads,
 // fixed order (strided per-thread sums, then a halving tree).
@@ -594,11 +631,15 @@ hipError_t launch_restrict(int dim, RestrictArgs<T> a, hipStream_t s, const Rest
 
 template <typename T>
 hipError_t launch_residual(int dim, ResidArgs<T> a, hipStream_t s) {
-  const int nb = a.nblocks > 0 ? a.nblocks : residual_blocks(dim, a.m);
+  // the grid must be exactly the tiling the partial sums are counted for
+  const int nb = residual_blocks(dim, a.m);
+  if (a.nblocks > 0 && a.nblocks != nb) return hipErrorInvalidValue;
+  const int cz = ir_chunk(dim, a.m);
   if (dim == 3)
-    gmg_launch((k_residual<T, 3, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_residual<T, 3, kIrTX3, kIrTY3, kIrTX3 * kIrTY3>), dim3(nb),
+               dim3(kIrTX3 * kIrTY3), 0, s, a, cz);
   else
-    gmg_launch((k_residual<T, 2, 256>), dim3(nb), dim3(256), 0, s, a);
+    gmg_launch((k_residual<T, 2, kIrTX2, 1, kIrTX2>), dim3(nb), dim3(kIrTX2), 0, s, a, cz);
   return hipGetLastError();
 }
 
