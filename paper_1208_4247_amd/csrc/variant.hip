@@ -387,14 +387,21 @@ __global__ void __launch_bounds__(256) k_prolong_fe(const double *in, const doub
     const int k = DIM == 3 ? zs + 1 : 0;
     const int oi = i & 1, oj = j & 1, ok = k & 1;
     const int I = (i - oi) >> 1, J = (j - oj) >> 1, K = (k - ok) >> 1;
-    auto cv = [&](int ci, int cj, int ck) -> double {  // coarse node value, 0 on the boundary
-      if (ci < 1 || cj < 1 || ci > mc || cj > mc) return 0.0;
-      if (DIM == 3 && (ck < 1 || ck > mc)) return 0.0;
-      return ec[DIM == 3 ? ((size_t)(ck - 1) * mc + (cj - 1)) * mc + (ci - 1)
-                         : (size_t)(cj - 1) * mc + (ci - 1)];
+    // coarse node value, 0 on the boundary: both loads issue unconditionally
+    // through a buffer resource over the coarse grid (out-of-range offsets
+    // read 0); the parity only selects
+    const int nc = DIM == 3 ? mc * mc * mc : mc * mc;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(ec), (short)0, nc * 8, 0x00020000);
+    auto cv = [&](int ci, int cj, int ck) -> double {
+      const bool in = ci >= 1 && cj >= 1 && ci <= mc && cj <= mc &&
+                      (DIM == 2 || (ck >= 1 && ck <= mc));
+      const int o = DIM == 3 ? ((ck - 1) * mc + (cj - 1)) * mc + (ci - 1) : (cj - 1) * mc + (ci - 1);
+      return bload<double>(rc, in ? o * 8 : kOOB);
     };
     const double c0 = cv(I, J, K);
-    const double s = (oi | oj | ok) ? 0.5 * (c0 + cv(I + oi, J + oj, K + ok)) : c0;
+    const double c1 = cv(I + oi, J + oj, K + ok);
+    const double s = (oi | oj | ok) ? 0.5 * (c0 + c1) : c0;
     out[p] = (in ? in[p] : 0.0) + s;
   }
 }
