@@ -292,9 +292,11 @@ __global__ void __launch_bounds__(NT) k_residual(ResidArgs<T> a, int cz) {
   const T inv_h2 = T(a.inv_h2);
   double acc = 0.0;
   for (int z = Z0; z < Z1; ++z) {
-    load_plane(z + 2, uv);  // in flight during this plane's residual
+    // f first: the load counter is in order, so waiting for f then leaves
+    // the next plane's loads in flight during this plane's residual
     const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.f, z, m, planeS);
     const T fv = bload<T>(rf, mine ? coff * (int)sizeof(T) : kOOB);
+    load_plane(z + 2, uv);
     if (mine) {
       const T *P = ring[z & 3];
       const T c = P[ci];
@@ -368,23 +370,25 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
     hoff[k] = in ? ((DIM == 3 ? y * m : 0) + x) : -1;
   }
   const bool use_e = a.e != nullptr;
+  // x and e of a plane stay separate in registers until the plane is stored
+  // (x + e is formed then), so their loads stay in flight meanwhile
   double xv[NL];
-  auto load_plane = [&](int z, double *v) {
+  float ev[NL];
+  auto load_plane = [&](int z, double *v, float *w) {
     const __amdgpu_buffer_rsrc_t rx = plane_rsrc(a.x, z, m, planeS);
     const __amdgpu_buffer_rsrc_t re = plane_rsrc(a.e, use_e ? z : -1, m, planeS);
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const int o = hoff[k];
-      double v0 = bload<double>(rx, o >= 0 ? o * 8 : kOOB);
-      if (use_e) v0 += double(bload<float>(re, o >= 0 ? o * 4 : kOOB));
-      v[k] = v0;
+      v[k] = bload<double>(rx, o >= 0 ? o * 8 : kOOB);
+      w[k] = use_e ? bload<float>(re, o >= 0 ? o * 4 : kOOB) : 0.0f;
     }
   };
-  auto store_plane = [&](int z, const double *v) {
+  auto store_plane = [&](int z, const double *v, const float *w) {
     double *dst = ring[z & 3];
 #pragma unroll
     for (int k = 0; k < NL; ++k)
-      if (hj[k] >= 0) dst[hj[k]] = v[k];
+      if (hj[k] >= 0) dst[hj[k]] = use_e ? v[k] + double(w[k]) : v[k];
   };
   // this thread's point
   const int cx = threadIdx.x % TX, cy = threadIdx.x / TX;
@@ -393,19 +397,21 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
   const int ci = (DIM == 3 ? (cy + 1) * HX : 0) + cx + 1;
   const int coff = (DIM == 3 ? gy * m : 0) + gx;
   // prologue: planes Z0 - 1, Z0, Z0 + 1 in the ring
-  load_plane(Z0 - 1, xv);
-  store_plane(Z0 - 1, xv);
-  load_plane(Z0, xv);
-  store_plane(Z0, xv);
-  load_plane(Z0 + 1, xv);
-  store_plane(Z0 + 1, xv);
+  load_plane(Z0 - 1, xv, ev);
+  store_plane(Z0 - 1, xv, ev);
+  load_plane(Z0, xv, ev);
+  store_plane(Z0, xv, ev);
+  load_plane(Z0 + 1, xv, ev);
+  store_plane(Z0 + 1, xv, ev);
   __syncthreads();
   const double inv_h2 = a.inv_h2;
   double acc = 0.0;
   for (int z = Z0; z < Z1; ++z) {
-    load_plane(z + 2, xv);  // in flight during this plane's residual
+    // f first: the load counter is in order, so waiting for f then leaves
+    // the next plane's loads in flight during this plane's residual
     const __amdgpu_buffer_rsrc_t rf = plane_rsrc(a.f, z, m, planeS);
     const double fv = bload<double>(rf, mine ? coff * 8 : kOOB);
+    load_plane(z + 2, xv, ev);
     if (mine) {
       const double *P = ring[z & 3];
       const double c = P[ci];
@@ -423,7 +429,7 @@ __global__ void __launch_bounds__(NT) k_ir_step(IrArgs a) {
       acc += r * r;
     }
     // slot (z + 2) & 3 last held plane z - 2, read by nobody in this step
-    store_plane(z + 2, xv);
+    store_plane(z + 2, xv, ev);
     __syncthreads();
   }
   __shared__ double red[NT / 64];
