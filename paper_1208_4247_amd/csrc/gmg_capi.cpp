@@ -98,7 +98,7 @@ struct BProblem {
 
 // One launch of the batched cycle; its argument entries live in a device
 // table (byte offset tbl_off in the table region).
-enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3, BO_SMALL_DOWN = 4, BO_SMALL_UP = 5 };
+enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3, BO_SMALL_DOWN = 4 };
 struct BOp {
   int kind = BO_PASS;
   int dim = 3, stages = 0, flags = 0, variant = 0, wj = 0, nent = 0;
@@ -479,8 +479,8 @@ LevelSet<float> &levels_of<float>(gmg_plan *p) {
   return p->s;
 }
 
-// Small coarse levels go through the fused LDS-tile kernels (red-black only;
-// single-problem plans use the descent kernel, batches both).
+// The descent on small coarse levels goes through the fused LDS-tile kernel
+// (red-black only).
 bool use_small(const gmg_plan *p, int dim, int m, int nu, size_t elem) {
   return p->cfg.smoother == GMG_SMOOTH_RBGS && !(p->cfg.flags & GMG_NO_FUSED_COARSE) && nu >= 1 &&
          small_level_ok(dim, m, nu, elem);
@@ -510,7 +510,7 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active, int first = 1) {
       a.h2 = h * h;
       a.inv_h2 = 1.0 / (h * h);
       ProfScope ps(p, PC_PRE_C, (double)npts(p->dim, m) * sizeof(T) * 2);
-      e = launch_small<T>(p->dim, true, a, p->stream);
+      e = launch_small<T>(p->dim, a, p->stream);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -542,7 +542,7 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active, int first = 1) {
   // The ascent of a single problem always takes the plane-marching pass: on
   // every level it beat the LDS-tile kernel (3D 255^3 cycle: 63^3 ascent 15
   // against 24 us, 31^3 14 against 18 us; 2D 4095^2 FMG pass 1.11 against
-  // 1.15 ms).  Batches keep the tile kernel for the ascent.
+  // 1.15 ms); batches take it too (their 256-problem solve 77 -> 62 ms).
   for (int l = B - 1; l >= first; --l) {
     e = smooth_chain<T>(p, l, nu2, bwd, S.w[l], S.u[l + 1], S.f[l], S.u[l], S.t[l], nullptr,
                         active, PC_POST_C, nullptr);
@@ -1595,45 +1595,9 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
         ents.push_back({q, l, pr.w[l], pr.u[l + 1], l == 0 ? nullptr : pr.f[l],
                         l == 0 ? nullptr : pr.u[l], pr.t[l], false, l == 0, l == 0, nullptr});
       }
-      if (use_small(p, dim, m, nu2, sizeof(double))) {
-        std::vector<ChainEnt> top, coarse;
-        for (const ChainEnt &ce : ents) (ce.level == 0 ? top : coarse).push_back(ce);
-        build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, top, PC_POST_C);
-        if (!coarse.empty()) {
-          BOp op;
-          op.kind = BO_SMALL_UP;
-          op.dim = dim;
-          op.nent = (int)coarse.size();
-          op.cls = PC_POST_C;
-          bb.align_tbl();
-          op.tbl_off = b->host_tbl.size();
-          const double h = 1.0 / double(m + 1);
-          const int ct = small_tile_coarse(dim);
-          const int ntile = (m + 2 * ct - 1) / (2 * ct);
-          for (const ChainEnt &ce : coarse) {
-            BProblem &pr = b->pb[ce.q];
-            SmallArgs<double> a{};
-            a.f = pr.f[ce.level];
-            a.w = pr.w[ce.level];
-            a.ec = pr.u[ce.level + 1];
-            a.u = pr.u[ce.level];
-            a.active = &pr.st->active;
-            a.m = m;
-            a.mc = (m - 1) / 2;
-            a.nsweeps = nu2;
-            a.black_first = bwd ? 1 : 0;
-            a.ntile = ntile;
-            a.nblocks = dim == 3 ? ntile * ntile * ntile : ntile * ntile;
-            a.h2 = h * h;
-            a.inv_h2 = 1.0 / (h * h);
-            bb.push(a);
-            op.bytes += (double)npts(dim, m) * 24.0;
-          }
-          b->ops.push_back(op);
-        }
-      } else {
-        build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, ents, PC_POST_C);
-      }
+      // the ascent always takes the plane-marching pass, as for single
+      // problems (faster than the LDS-tile kernel on every level)
+      build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, ents, PC_POST_C);
     }
   }
   bb.align_tbl();
@@ -1669,11 +1633,10 @@ hipError_t batch_enqueue_cycle(gmg_plan *p) {
       case BO_FIN:
         e = launch_finalize_batch((const FinEntry *)tbl, op.nent, p->stream);
         break;
-      case BO_SMALL_DOWN:
-      case BO_SMALL_UP: {
+      case BO_SMALL_DOWN: {
         SmallArgs<double> a;
         std::memcpy(&a, host, sizeof(a));
-        e = launch_small<double>(op.dim, op.kind == BO_SMALL_DOWN, a, p->stream,
+        e = launch_small<double>(op.dim, a, p->stream,
                                  (const SmallArgs<double> *)tbl, op.nent);
         break;
       }

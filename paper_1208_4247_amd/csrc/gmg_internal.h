@@ -180,19 +180,16 @@ struct BottomArgs {
   double omega;
 };
 
-// Fused LDS-tile kernels for small coarse levels (descent: zero start,
-// nsweeps forward sweeps, w = result, fc = FW(f - A w); ascent: u = nsweeps
-// sweeps from w + P ec).  ntile/nblocks are filled by the launcher (batch
-// entries must carry the same values).
+// Fused LDS-tile kernel for the descent on small coarse levels: zero start,
+// nsweeps forward sweeps, w = result, fc = FW(f - A w).  ntile/nblocks are
+// filled by the launcher (batch entries must carry the same values).
 template <typename T>
 struct SmallArgs {
   const T *f;
   T *w;
   T *fc;
-  const T *ec;
-  T *u;
   const int *active;
-  int m, mc, nsweeps, black_first, ntile, nblocks;
+  int m, mc, nsweeps, ntile, nblocks;
   double h2, inv_h2;
 };
 
@@ -255,11 +252,11 @@ hipError_t launch_bottom(int nproblems, BottomArgs<T> a, const BottomArgs<T> *tb
 size_t bottom_lds_bytes(int dim, int L, int smoother, size_t elem);
 hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s);
 bool small_level_ok(int dim, int m, int nsweeps, size_t elem);
-size_t small_lds_bytes(int dim, int nsweeps, bool down, size_t elem);
+size_t small_lds_bytes(int dim, int nsweeps, size_t elem);
 int small_tile_coarse(int dim);
 template <typename T>
-hipError_t launch_small(int dim, bool down, SmallArgs<T> a, hipStream_t s,
-                        const SmallArgs<T> *tbl = nullptr, int nent = 1);
+hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl = nullptr,
+                        int nent = 1);
 int ir_blocks(int dim, int m);
 
 template <typename T>

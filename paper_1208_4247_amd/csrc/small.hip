@@ -1,27 +1,23 @@
-// small.hip -- fused LDS-tile kernels for small coarse levels.
+// small.hip -- fused LDS-tile kernel for the descent on small coarse levels.
 //
 // On a coarse level of side <= 63 (3D) / <= 511 (2D) a z-marching pass is
 // latency bound: every plane step waits on L2 loads and barriers.  Here one
 // workgroup owns a small cube (3D) or square (2D) of fine points, loads it
 // once with a halo wide enough for every fused step, and runs the level's
-// whole descent or ascent work in LDS:
-//
-//  descent:  u = 0; S = 2 nu1 red-black half-sweeps (Algorithm 1's
-//            Relax_forward from the zero coarse start value); write w on the
-//            core; r = f - A w on the core and a one-point ring; full
-//            weighting of r to the coarse points of the tile.
-//  ascent:   u = w + P e (linear interpolation of the coarse correction);
-//            S = 2 nu2 half-sweeps (Relax_backward, or forward with the
-//            textbook order); write u on the core.
+// whole descent in LDS: u = 0; S = 2 nu1 red-black half-sweeps (Algorithm
+// 1's Relax_forward from the zero coarse start value); write w on the core;
+// r = f - A w on the core and a one-point ring; full weighting of r to the
+// coarse points of the tile.  (The ascent always takes the plane-marching
+// pass: an LDS-tile version of it measured slower on every level.)
 //
 // Halo values are recomputed by neighbouring workgroups (the redundancy is
 // cheap at these sizes: everything lives in L2).  Stage s is evaluated on
 // local coordinates [s, E-s), which is exact given exact stage s-1 values on
-// [s-1, E-s+1), so after S stages the box [S, E-S) is exact.  The descent
-// box starts S+1 points before the core and ends S+2 after it: full
-// weighting of the tile's last coarse point needs the residual one point
-// past the core, which needs u one point further.  Results are the same bits
-// as the z-marching passes: every half-sweep evaluates the same per-point
+// [s-1, E-s+1), so after S stages the box [S, E-S) is exact.  The box
+// starts S+1 points before the core and ends S+2 after it: full weighting
+// of the tile's last coarse point needs the residual one point past the
+// core, which needs u one point further.  Results are the same bits as the
+// z-marching passes: every half-sweep evaluates the same per-point
 // expression on the same inputs.
 #include "gmg_internal.h"
 
@@ -186,116 +182,35 @@ __global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const Small
   }
 }
 
-// ------------------------------------------------------------------ ascent
-template <typename T, int DIM, int CT, int NSW, int NT>
-__global__ void __launch_bounds__(NT) k_small_up(SmallArgs<T> arg, const SmallArgs<T> *tbl) {
-  const SmallArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
-  if (a.active && *gbl(a.active) == 0) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int S = 2 * NSW;
-  constexpr int H = S;
-  constexpr int E = 2 * CT + 2 * H;
-  constexpr int N = DIM == 3 ? E * E * E : E * E;
-  constexpr int NPT = (N + NT - 1) / NT;
-  const int m = a.m, mc = a.mc;
-  Box<DIM> b;
-  b.E = E;
-  const int nt = a.ntile;
-  const int bid = xcd_remap_s(blockIdx.x, a.nblocks);
-  const int tx = bid % nt, ty = (bid / nt) % nt, tz = DIM == 3 ? bid / (nt * nt) : 0;
-  const int A0[3] = {tx * CT, ty * CT, tz * CT};
-  for (int k = 0; k < 3; ++k) b.o[k] = 2 * A0[k] - H;
-  T *u = reinterpret_cast<T *>(smem_raw);
-  T *f = u + N;
-  const T h2 = T(a.h2);
-  {
-    T uv[NPT], fv[NPT];
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int i = threadIdx.x + NT * k;
-      int lx, ly, lz;
-      box_coord<DIM, E>(i, lx, ly, lz);
-      T v = T(0), fl = T(0);
-      if (i < N && in_dom<DIM>(b, lx, ly, lz, m)) {
-        const size_t g = gidx<DIM>(b, lx, ly, lz, m);
-        fl = gbl(a.f)[g];
-        // u = w + P e in the canonical order (x, then y, then z averaging)
-        const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = DIM == 3 ? b.o[2] + lz : 0;
-        auto cv = [&](int cx, int cy, int cz) -> T {
-          if (cx < 0 || cx >= mc || cy < 0 || cy >= mc) return T(0);
-          if (DIM == 3) {
-            if (cz < 0 || cz >= mc) return T(0);
-            return gbl(a.ec)[((size_t)cz * mc + cy) * mc + cx];
-          }
-          return gbl(a.ec)[(size_t)cy * mc + cx];
-        };
-        auto xs = [&](int cy, int cz) {
-          return (gx & 1) ? cv((gx - 1) >> 1, cy, cz)
-                          : T(0.5) * (cv((gx >> 1) - 1, cy, cz) + cv(gx >> 1, cy, cz));
-        };
-        auto ys = [&](int cz) {
-          return (gy & 1) ? xs((gy - 1) >> 1, cz)
-                          : T(0.5) * (xs((gy >> 1) - 1, cz) + xs(gy >> 1, cz));
-        };
-        T pe;
-        if (DIM == 3)
-          pe = (gz & 1) ? ys((gz - 1) >> 1) : T(0.5) * (ys((gz >> 1) - 1) + ys(gz >> 1));
-        else
-          pe = ys(0);
-        v = gbl(a.w)[g] + pe;
-      }
-      uv[k] = v;
-      fv[k] = fl;
-    }
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int i = threadIdx.x + NT * k;
-      if (i < N) {
-        u[i] = uv[k];
-        f[i] = fv[k];
-      }
-    }
-  }
-  __syncthreads();
-  lds_sweeps<T, DIM>(b, u, f, S, a.black_first ? 1 : 0, m, h2);
-  box_for<DIM>(E, H, H + 2 * CT, [&](int i, int lx, int ly, int lz) {
-    if (in_dom<DIM>(b, lx, ly, lz, m)) gbl(a.u)[gidx<DIM>(b, lx, ly, lz, m)] = u[i];
-  });
-}
-
 // ------------------------------------------------------------------ launchers
 namespace {
 constexpr int kCT3 = 4, kCT2 = 16;
 constexpr int kNT3 = 1024, kNT2 = 512;
 
 template <typename T, int DIM, int NSW>
-hipError_t run_small(bool down, SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl, int nent,
+hipError_t run_small(SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl, int nent,
                      size_t lds) {
   constexpr int CT = DIM == 3 ? kCT3 : kCT2;
   constexpr int NT = DIM == 3 ? kNT3 : kNT2;
-  const void *k = down ? (const void *)k_small_down<T, DIM, CT, NSW, NT>
-                       : (const void *)k_small_up<T, DIM, CT, NSW, NT>;
-  static bool attr[2] = {false, false};
-  if (!attr[down ? 1 : 0]) {
-    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_small_down<T, DIM, CT, NSW, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
     if (e != hipSuccess) return e;
-    attr[down ? 1 : 0] = true;
+    attr = true;
   }
   dim3 grid(a.nblocks, nent);
-  if (down)
-    gmg_launch((k_small_down<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
-  else
-    gmg_launch((k_small_up<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
+  gmg_launch((k_small_down<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
   return hipGetLastError();
 }
 }  // namespace
 
 int small_tile_coarse(int dim) { return dim == 3 ? kCT3 : kCT2; }
 
-size_t small_lds_bytes(int dim, int nsweeps, bool down, size_t elem) {
+size_t small_lds_bytes(int dim, int nsweeps, size_t elem) {
   const int S = 2 * nsweeps;
   const int ct = dim == 3 ? kCT3 : kCT2;
-  const size_t E = down ? 2 * ct + 2 * S + 3 : 2 * ct + 2 * S;
+  const size_t E = 2 * ct + 2 * S + 3;
   const size_t N = dim == 3 ? E * E * E : E * E;
   return 2 * N * elem;
 }
@@ -303,36 +218,36 @@ size_t small_lds_bytes(int dim, int nsweeps, bool down, size_t elem) {
 bool small_level_ok(int dim, int m, int nsweeps, size_t elem) {
   if (nsweeps < 1 || nsweeps > 3) return false;
   if (dim == 3 ? m > 63 : m > 511) return false;
-  return small_lds_bytes(dim, nsweeps, true, elem) <= 120 * 1024;
+  return small_lds_bytes(dim, nsweeps, elem) <= 120 * 1024;
 }
 
 template <typename T>
-hipError_t launch_small(int dim, bool down, SmallArgs<T> a, hipStream_t s,
-                        const SmallArgs<T> *tbl, int nent) {
+hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl,
+                        int nent) {
   const int ct = dim == 3 ? kCT3 : kCT2;
   // tiles of ct coarse points; their fine cores (2 ct points) cover all
   // m = 2 mc + 1 fine points
   a.ntile = (a.m + 2 * ct - 1) / (2 * ct);
   a.nblocks = dim == 3 ? a.ntile * a.ntile * a.ntile : a.ntile * a.ntile;
-  const size_t lds = small_lds_bytes(dim, a.nsweeps, down, sizeof(T));
+  const size_t lds = small_lds_bytes(dim, a.nsweeps, sizeof(T));
   if (dim == 3) {
     switch (a.nsweeps) {
-      case 1: return run_small<T, 3, 1>(down, a, s, tbl, nent, lds);
-      case 2: return run_small<T, 3, 2>(down, a, s, tbl, nent, lds);
+      case 1: return run_small<T, 3, 1>(a, s, tbl, nent, lds);
+      case 2: return run_small<T, 3, 2>(a, s, tbl, nent, lds);
       default: return hipErrorInvalidValue;
     }
   }
   switch (a.nsweeps) {
-    case 1: return run_small<T, 2, 1>(down, a, s, tbl, nent, lds);
-    case 2: return run_small<T, 2, 2>(down, a, s, tbl, nent, lds);
-    case 3: return run_small<T, 2, 3>(down, a, s, tbl, nent, lds);
+    case 1: return run_small<T, 2, 1>(a, s, tbl, nent, lds);
+    case 2: return run_small<T, 2, 2>(a, s, tbl, nent, lds);
+    case 3: return run_small<T, 2, 3>(a, s, tbl, nent, lds);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_small<double>(int, bool, SmallArgs<double>, hipStream_t,
+template hipError_t launch_small<double>(int, SmallArgs<double>, hipStream_t,
                                          const SmallArgs<double> *, int);
-template hipError_t launch_small<float>(int, bool, SmallArgs<float>, hipStream_t,
+template hipError_t launch_small<float>(int, SmallArgs<float>, hipStream_t,
                                         const SmallArgs<float> *, int);
 
 }  // namespace gmg

@@ -69,10 +69,10 @@ def test_batch_matches_single_oracle_solves():
 
 @pytest.mark.parametrize("post_forward", [False, True])
 def test_batch_equals_single_plans_bitwise(post_forward):
-    """A batch runs the small coarse levels through the LDS-tile ascent
-    kernel, single-problem plans through the plane-marching pass: every
-    half-sweep is the same per-point expression, so both give the same cycle
-    count and the same bits."""
+    """A batch runs every level through table-driven launches shared by all
+    its problems, a single-problem plan through launches of its own (tiles
+    tuned per plan): every half-sweep is the same per-point expression, so
+    both give the same cycle count and the same bits."""
     from paper_1208_4247_amd import capi
     from paper_1208_4247_amd.solver import Plan
 
