@@ -98,7 +98,7 @@ struct BProblem {
 
 // One launch of the batched cycle; its argument entries live in a device
 // table (byte offset tbl_off in the table region).
-enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3, BO_SMALL_DOWN = 4 };
+enum BOpKind { BO_PASS = 0, BO_RESTRICT = 1, BO_FIN = 2, BO_BOTTOM = 3 };
 struct BOp {
   int kind = BO_PASS;
   int dim = 3, stages = 0, flags = 0, variant = 0, wj = 0, nent = 0;
@@ -479,8 +479,8 @@ LevelSet<float> &levels_of<float>(gmg_plan *p) {
   return p->s;
 }
 
-// The descent on small coarse levels goes through the fused LDS-tile kernel
-// (red-black only).
+// The descent on small coarse levels of a single problem goes through the
+// fused LDS-tile kernel (red-black only; batches use the passes).
 bool use_small(const gmg_plan *p, int dim, int m, int nu, size_t elem) {
   return p->cfg.smoother == GMG_SMOOTH_RBGS && !(p->cfg.flags & GMG_NO_FUSED_COARSE) && nu >= 1 &&
          small_level_ok(dim, m, nu, elem);
@@ -542,7 +542,7 @@ hipError_t enqueue_coarse(gmg_plan *p, const int *active, int first = 1) {
   // The ascent of a single problem always takes the plane-marching pass: on
   // every level it beat the LDS-tile kernel (3D 255^3 cycle: 63^3 ascent 15
   // against 24 us, 31^3 14 against 18 us; 2D 4095^2 FMG pass 1.11 against
-  // 1.15 ms); batches take it too (their 256-problem solve 77 -> 62 ms).
+  // 1.15 ms); batches take it too (their 256-problem solve 77 -> 61 ms).
   for (int l = B - 1; l >= first; --l) {
     e = smooth_chain<T>(p, l, nu2, bwd, S.w[l], S.u[l + 1], S.f[l], S.u[l], S.t[l], nullptr,
                         active, PC_POST_C, nullptr);
@@ -1487,42 +1487,13 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
         for (int q : tops) bb.push(FinEntry{b->pb[q].partials, b->pb[q].npart, b->pb[q].st});
         b->ops.push_back(op);
       }
-      const bool small = use_small(p, dim, m, nu1, sizeof(double));
-      if (small && !coarse.empty()) {
-        BOp op;
-        op.kind = BO_SMALL_DOWN;
-        op.dim = dim;
-        op.nent = (int)coarse.size();
-        op.cls = PC_PRE_C;
-        bb.align_tbl();
-        op.tbl_off = b->host_tbl.size();
-        const double h = 1.0 / double(m + 1);
-        const int ct = small_tile_coarse(dim);
-        const int ntile = (m + 2 * ct - 1) / (2 * ct);
-        for (const ChainEnt &ce : coarse) {
-          BProblem &pr = b->pb[ce.q];
-          SmallArgs<double> a{};
-          a.f = pr.f[ce.level];
-          a.w = pr.w[ce.level];
-          a.fc = pr.f[ce.level + 1];
-          a.active = &pr.st->active;
-          a.m = m;
-          a.mc = (m - 1) / 2;
-          a.nsweeps = nu1;
-          a.ntile = ntile;
-          a.nblocks = dim == 3 ? ntile * ntile * ntile : ntile * ntile;
-          a.h2 = h * h;
-          a.inv_h2 = 1.0 / (h * h);
-          bb.push(a);
-          op.bytes += (double)npts(dim, m) * 16.0;
-        }
-        b->ops.push_back(op);
-      } else {
-        build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C);
-      }
+      // the coarse descent takes the plane-marching passes as well: in a
+      // batch the LDS-tile descent kernel is slower (256-problem batch 61
+      // against 52 ms)
+      build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C);
       // residual + restriction for every entry of this size
       std::vector<ChainEnt> all = top;
-      if (!small) all.insert(all.end(), coarse.begin(), coarse.end());
+      all.insert(all.end(), coarse.begin(), coarse.end());
       if (!all.empty()) {
         BOp op;
         op.kind = BO_RESTRICT;
@@ -1633,13 +1604,6 @@ hipError_t batch_enqueue_cycle(gmg_plan *p) {
       case BO_FIN:
         e = launch_finalize_batch((const FinEntry *)tbl, op.nent, p->stream);
         break;
-      case BO_SMALL_DOWN: {
-        SmallArgs<double> a;
-        std::memcpy(&a, host, sizeof(a));
-        e = launch_small<double>(op.dim, a, p->stream,
-                                 (const SmallArgs<double> *)tbl, op.nent);
-        break;
-      }
       case BO_BOTTOM: {
         BottomArgs<double> a{};
         a.dim = op.bottom_dim;
