@@ -180,9 +180,9 @@ struct BottomArgs {
   double omega;
 };
 
-// Fused LDS-tile kernel for the descent on small coarse levels: zero start,
-// nsweeps forward sweeps, w = result, fc = FW(f - A w).  ntile/nblocks are
-// filled by the launcher (batch entries must carry the same values).
+// Fused LDS-tile kernel for the descent on small coarse levels of a single
+// problem: zero start, nsweeps forward sweeps, w = result, fc = FW(f - A w).
+// ntile/nblocks are filled by the launcher.
 template <typename T>
 struct SmallArgs {
   const T *f;
@@ -253,10 +253,8 @@ size_t bottom_lds_bytes(int dim, int L, int smoother, size_t elem);
 hipError_t launch_ir_step(int dim, IrArgs a, hipStream_t s);
 bool small_level_ok(int dim, int m, int nsweeps, size_t elem);
 size_t small_lds_bytes(int dim, int nsweeps, size_t elem);
-int small_tile_coarse(int dim);
 template <typename T>
-hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl = nullptr,
-                        int nent = 1);
+hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s);
 int ir_blocks(int dim, int m);
 
 template <typename T>

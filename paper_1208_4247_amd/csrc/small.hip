@@ -113,8 +113,7 @@ __device__ __forceinline__ void box_coord(int i, int &lx, int &ly, int &lz) {
 
 // ------------------------------------------------------------------ descent
 template <typename T, int DIM, int CT, int NSW, int NT>
-__global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> arg, const SmallArgs<T> *tbl) {
-  const SmallArgs<T> a = tbl ? tbl[blockIdx.y] : arg;
+__global__ void __launch_bounds__(NT) k_small_down(SmallArgs<T> a) {
   if (a.active && *gbl(a.active) == 0) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int S = 2 * NSW;
@@ -188,8 +187,7 @@ constexpr int kCT3 = 4, kCT2 = 16;
 constexpr int kNT3 = 1024, kNT2 = 512;
 
 template <typename T, int DIM, int NSW>
-hipError_t run_small(SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl, int nent,
-                     size_t lds) {
+hipError_t run_small(SmallArgs<T> a, hipStream_t s, size_t lds) {
   constexpr int CT = DIM == 3 ? kCT3 : kCT2;
   constexpr int NT = DIM == 3 ? kNT3 : kNT2;
   static bool attr = false;
@@ -199,13 +197,11 @@ hipError_t run_small(SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl, int
     if (e != hipSuccess) return e;
     attr = true;
   }
-  dim3 grid(a.nblocks, nent);
-  gmg_launch((k_small_down<T, DIM, CT, NSW, NT>), grid, dim3(NT), lds, s, a, tbl);
+  gmg_launch((k_small_down<T, DIM, CT, NSW, NT>), dim3(a.nblocks), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 }  // namespace
 
-int small_tile_coarse(int dim) { return dim == 3 ? kCT3 : kCT2; }
 
 size_t small_lds_bytes(int dim, int nsweeps, size_t elem) {
   const int S = 2 * nsweeps;
@@ -222,8 +218,7 @@ bool small_level_ok(int dim, int m, int nsweeps, size_t elem) {
 }
 
 template <typename T>
-hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s, const SmallArgs<T> *tbl,
-                        int nent) {
+hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s) {
   const int ct = dim == 3 ? kCT3 : kCT2;
   // tiles of ct coarse points; their fine cores (2 ct points) cover all
   // m = 2 mc + 1 fine points
@@ -232,22 +227,20 @@ hipError_t launch_small(int dim, SmallArgs<T> a, hipStream_t s, const SmallArgs<
   const size_t lds = small_lds_bytes(dim, a.nsweeps, sizeof(T));
   if (dim == 3) {
     switch (a.nsweeps) {
-      case 1: return run_small<T, 3, 1>(a, s, tbl, nent, lds);
-      case 2: return run_small<T, 3, 2>(a, s, tbl, nent, lds);
+      case 1: return run_small<T, 3, 1>(a, s, lds);
+      case 2: return run_small<T, 3, 2>(a, s, lds);
       default: return hipErrorInvalidValue;
     }
   }
   switch (a.nsweeps) {
-    case 1: return run_small<T, 2, 1>(a, s, tbl, nent, lds);
-    case 2: return run_small<T, 2, 2>(a, s, tbl, nent, lds);
-    case 3: return run_small<T, 2, 3>(a, s, tbl, nent, lds);
+    case 1: return run_small<T, 2, 1>(a, s, lds);
+    case 2: return run_small<T, 2, 2>(a, s, lds);
+    case 3: return run_small<T, 2, 3>(a, s, lds);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_small<double>(int, SmallArgs<double>, hipStream_t,
-                                         const SmallArgs<double> *, int);
-template hipError_t launch_small<float>(int, SmallArgs<float>, hipStream_t,
-                                        const SmallArgs<float> *, int);
+template hipError_t launch_small<double>(int, SmallArgs<double>, hipStream_t);
+template hipError_t launch_small<float>(int, SmallArgs<float>, hipStream_t);
 
 }  // namespace gmg
