@@ -553,19 +553,29 @@ static void coarsest(hier_t *H, int nu1, int smoother, double omega) {
   }
 }
 
+/* The V-cycle in its recursive (two-grid) form: on level l, relax, form the
+ * residual and restrict it as the next level's right-hand side, solve the
+ * coarse error equation from a zero start by the same cycle one level down
+ * (exactly on the one-node level), add its interpolation and relax again in
+ * the reverse colour order.  The result is the cycle Algorithm 1 defines:
+ * every level runs the same steps in the same order. */
+static void vcycle_from(hier_t *H, int l, int nu1, int nu2, int smoother, double omega) {
+  if (l == H->L - 1) {
+    coarsest(H, nu1, smoother, omega);
+    return;
+  }
+  smooth(H, l, smoother, omega, nu1, 0);
+  orc_residual(H->d, H->m[l], H->u[l], H->f[l], H->r[l]);
+  restrict_to(H, l, H->r[l], H->f[l + 1]);
+  if (l + 1 < H->L - 1)
+    memset(H->u[l + 1], 0, sizeof(double) * (size_t)npts(H->d, H->m[l + 1]));
+  vcycle_from(H, l + 1, nu1, nu2, smoother, omega);
+  prolong_from(H, l);
+  smooth(H, l, smoother, omega, nu2, 1);
+}
+
 static void vcycle(hier_t *H, int nu1, int nu2, int smoother, double omega) {
-  int d = H->d, L = H->L;
-  for (int l = 0; l <= L - 2; l++) {
-    if (l > 0) memset(H->u[l], 0, sizeof(double) * (size_t)npts(d, H->m[l]));
-    smooth(H, l, smoother, omega, nu1, 0);
-    orc_residual(d, H->m[l], H->u[l], H->f[l], H->r[l]);
-    restrict_to(H, l, H->r[l], H->f[l + 1]);
-  }
-  coarsest(H, nu1, smoother, omega);
-  for (int l = L - 2; l >= 0; l--) {
-    prolong_from(H, l);
-    smooth(H, l, smoother, omega, nu2, 1);
-  }
+  vcycle_from(H, 0, nu1, nu2, smoother, omega);
 }
 
 /* One V(nu1, nu2) cycle applied in place to u (level 0, side m0). */
