@@ -1,11 +1,15 @@
 """Benchmark: fine-grid unknowns/s of the GMG Poisson solve to 1e-10 relative
 residual on one MI355X, plus the smoother's achieved HBM bandwidth.
 
-Default workload: 3D 7-point Poisson, 255^3 interior (h = 1/256), zero
-Dirichlet data, f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) + 1e-3 U[-1,1]
-(SplitMix64 seed 2), FP64 V(2,2) red-black Gauss-Seidel, full weighting /
-trilinear interpolation, one-node coarsest level, u0 = 0, rtol = 1e-10.
-A step = one gmg_solve from u = 0 with f already in HBM.
+Default workload: 3D 7-point Poisson, 1023^3 interior (h = 1/1024, about
+1.07e9 unknowns), zero Dirichlet data, f = sum of eight sine modes
+a_m prod_i sin(k_{m,i} pi x_i) with a_m ~ N(0,1), k ~ U{1..32} (SplitMix64
+seed 5), FP64 V(1,1) red-black Gauss-Seidel, full weighting / trilinear
+interpolation, one-node coarsest level, u0 = 0, rtol = 1e-10.  A step = one
+gmg_solve from u = 0 with f already in HBM.  The same line also carries the
+mixed-precision solve of the same problem (FP32 V(1,1) cycles inside FP64
+refinement) and the 256-problem uneven batch, each timed against plain FP64
+single-problem solves.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -32,7 +36,10 @@ WORKLOADS = {
     "poisson3d_511_uniform_fp64_v22": dict(dim=3, L=9, rhs="uniform", prec="fp64"),
     "poisson3d_511_uniform_mixed_v22": dict(dim=3, L=9, rhs="uniform", prec="mixed"),
     "poisson3d_511_uniform_mixed2_v22": dict(dim=3, L=9, rhs="uniform", prec="mixed", inner=2),
-    "poisson3d_1023_sine_modes_fp64_v11": dict(dim=3, L=10, rhs="sine_modes", prec="fp64", nu=1),
+    # the headline: its line also carries the mixed-precision solve of the same
+    # problem and the 256-problem batch, each against plain FP64 solves
+    "poisson3d_1023_sine_modes_fp64_v11": dict(dim=3, L=10, rhs="sine_modes", prec="fp64", nu=1,
+                                               extras=True),
     "poisson3d_1023_sine_modes_mixed_v11": dict(dim=3, L=10, rhs="sine_modes", prec="mixed",
                                                 nu=1),
     "poisson3d_1023_sine_modes_mixed2_v11": dict(dim=3, L=10, rhs="sine_modes", prec="mixed",
@@ -60,7 +67,7 @@ WORKLOADS = {
     "poisson3d_255_sine_dst": dict(dim=3, L=8, rhs="dst", prec="fp64", paper_s=0.1893),
     "poisson3d_1023_sine_dst": dict(dim=3, L=10, rhs="dst", prec="fp64"),
 }
-DEFAULT = "poisson3d_255_sine_noise_fp64_v22"
+DEFAULT = "poisson3d_1023_sine_modes_fp64_v11"
 
 
 def make_rhs(spec):
@@ -84,7 +91,9 @@ def make_rhs(spec):
 def cpu_baseline(spec, f, gpu_iters, budget_s=30.0):
     """The FP64 CPU oracle (untuned) solving the same workload with the same
     cycle on the host cores, bounded in time: the full solve when it fits,
-    else a few V-cycles scaled to unknowns/s at the GPU's cycle count."""
+    else the oracle's solve loop cut after a few cycles (initial residual
+    norm, then per cycle a V-cycle and the stop test's residual norm), scaled
+    to unknowns/s at the GPU's cycle count."""
     import oracle
 
     oracle.build()
@@ -99,13 +108,13 @@ def cpu_baseline(spec, f, gpu_iters, budget_s=30.0):
     kw = dict(nu1=nu, nu2=nu, smoother=smoother, omega=omega, variant=variant)
     rtol = spec.get("rtol", 1e-10)
     t0 = time.perf_counter()
-    u = oracle.vcycle(f * 0.0, f, **kw)
-    t_cycle = time.perf_counter() - t0
-    if t_cycle * gpu_iters <= budget_s:
+    oracle.solve(f, rtol=rtol, maxit=1, **kw)
+    t_one = time.perf_counter() - t0
+    if t_one * gpu_iters <= budget_s:
         # the median of up to three full solves on every host thread, then
         # one on a single thread when it fits the budget
         ts = []
-        while not ts or (len(ts) < 3 and sum(ts) + t_cycle * gpu_iters <= budget_s / 2):
+        while not ts or (len(ts) < 3 and sum(ts) + t_one * gpu_iters <= budget_s / 2):
             t0 = time.perf_counter()
             _, it, rel, st, _ = oracle.solve(f, rtol=rtol, **kw)
             ts.append(time.perf_counter() - t0)
@@ -122,15 +131,15 @@ def cpu_baseline(spec, f, gpu_iters, budget_s=30.0):
             out["single_thread_value"] = N / t1
             out["sample"] += "; one thread: %.2f s" % t1
         return out
-    ncyc = max(1, min(int(budget_s / t_cycle), 20))
+    k = max(1, min(int(budget_s / t_one), gpu_iters))
     t0 = time.perf_counter()
-    for _ in range(ncyc):
-        u = oracle.vcycle(u, f, **kw)
-    t = (time.perf_counter() - t0) / ncyc
-    return dict(value=N / (t * gpu_iters), unit="unknowns/s", cores=oracle.num_threads(),
+    oracle.solve(f, rtol=rtol, maxit=k, **kw)
+    t = time.perf_counter() - t0
+    return dict(value=N / (t * gpu_iters / k), unit="unknowns/s", cores=oracle.num_threads(),
                 kind="oracle",
-                sample="%d V-cycles of the same workload at %.3f s each, scaled to the GPU's %d "
-                "cycles" % (ncyc, t, gpu_iters))
+                sample="the oracle's solve loop on the same workload cut after %d of the GPU's "
+                "%d cycles (initial residual norm, then per cycle a V-cycle and the stop test's "
+                "residual norm): %.1f s, scaled to %d cycles" % (k, gpu_iters, t, gpu_iters))
 
 
 def measured_traffic(workload, cls, tile):
@@ -262,32 +271,33 @@ def cycle_name(smoother, spec):
     return "weighted Jacobi" if smoother == "wj" else "red-black GS"
 
 
-def bench_batch(args):
+def run_batch(args, steps, warmup):
     """256 independent problems of uneven size (128 2D with side 2^k-1,
     k ~ U{6..10}; 128 3D with k ~ U{5..7}; U[-1,1] right-hand sides, seed 4),
-    FP64 V(2,2) RB-GS to 1e-10 each; value = total unknowns / solve time."""
+    FP64 V(2,2) RB-GS to 1e-10 each, by one batch plan (graph-captured
+    cycles, autotuned tiles), and the same 256 solves run one after another
+    by autotuned single-problem plans.  Returns the timings."""
     import torch
 
     from paper_1208_4247_amd import capi
     from paper_1208_4247_amd import workloads as wl
-    from paper_1208_4247_amd.solver import BatchPlan
+    from paper_1208_4247_amd.solver import BatchPlan, Plan
 
     probs = wl.batch_problems(4)
     N = sum(m ** d for d, m in probs)
-    torch.cuda.set_device(0)
     fs = [torch.from_numpy(wl.batch_rhs(4, q, d, m)).cuda() for q, (d, m) in enumerate(probs)]
     us = [torch.zeros_like(f) for f in fs]
     flags = args.flags | capi.GMG_USE_GRAPH
     if not args.no_autotune:
         flags |= capi.GMG_AUTOTUNE  # the warm-up solve tunes one problem per shape
     plan = BatchPlan([(d, (m + 1).bit_length() - 1) for d, m in probs], flags=flags)
-    for _ in range(args.warmup):
+    for _ in range(max(1, warmup)):
         for u in us:
             u.zero_()
         plan.solve(us, fs)
     torch.cuda.synchronize()
     t_total = 0.0
-    for _ in range(args.steps):
+    for _ in range(steps):
         for u in us:
             u.zero_()
         torch.cuda.synchronize()
@@ -295,11 +305,7 @@ def bench_batch(args):
         s, its, rels, sts = plan.solve(us, fs)
         torch.cuda.synchronize()
         t_total += time.perf_counter() - t0
-    value = N / (t_total / args.steps)
-    # the same 256 problems solved one after another by single-problem plans
-    # (one plan per distinct size, autotuned during a warm-up pass)
-    from paper_1208_4247_amd.solver import Plan
-
+    batch_ms = 1e3 * t_total / steps
     plans = {}
     for d, m in sorted(set(probs)):
         plans[(d, m)] = Plan(d, (m + 1).bit_length() - 1, flags=args.flags | capi.GMG_AUTOTUNE)
@@ -308,7 +314,7 @@ def bench_batch(args):
         plans[(d, m)].solve(us[q], fs[q], rtol=1e-10)
     torch.cuda.synchronize()
     seq = []
-    for _ in range(max(1, min(args.steps, 3))):
+    for _ in range(max(1, min(steps, 3))):
         for u in us:
             u.zero_()
         torch.cuda.synchronize()
@@ -318,18 +324,65 @@ def bench_batch(args):
         torch.cuda.synchronize()
         seq.append(time.perf_counter() - t0)
     seq_ms = 1e3 * sum(seq) / len(seq)
+    return {"problems": len(probs), "unknowns": N, "batch_ms_per_solve": batch_ms,
+            "max_cycles": max(its), "min_cycles": min(its),
+            "all_converged": all(x == 0 for x in sts),
+            "sequential_single_solves_ms": seq_ms, "speedup_vs_sequential": seq_ms / batch_ms}
+
+
+def bench_batch(args):
+    """The 256-problem batch on its own: value = total unknowns / solve time."""
+    import torch
+
+    torch.cuda.set_device(0)
+    b = run_batch(args, args.steps, args.warmup)
     line = {
         "metric": "fine-grid unknowns/s to 1e-10 rel. residual (batch of 256 uneven problems)",
-        "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * t_total / args.steps,
+        "value": b["unknowns"] / (b["batch_ms_per_solve"] * 1e-3), "unit": "unknowns/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": b["batch_ms_per_solve"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "batch256_uneven_fp64_v22", "problems": len(probs),
-                   "unknowns": N, "max_cycles": max(its), "min_cycles": min(its),
-                   "sequential_single_solves_ms": seq_ms,
-                   "speedup_vs_sequential": seq_ms / (1e3 * t_total / args.steps)},
+        "config": dict({"workload": "batch256_uneven_fp64_v22"}, **b),
     }
     print(json.dumps(line), flush=True)
+
+
+def mixed_vs_fp64(args, spec, f, u64, ms64, steps):
+    """The mixed-precision solve (FP32 V-cycles inside FP64 refinement, the
+    library's default inner-cycle count) of the same problem, timed like the
+    FP64 solve it is compared with: its time, its FP64 residual (by the FP64
+    residual kernel) and its distance from the FP64 iterate u64."""
+    import torch
+
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import Plan
+
+    d, L, nu = spec["dim"], spec["L"], spec.get("nu", 2)
+    flags = args.flags | (0 if args.no_autotune else capi.GMG_AUTOTUNE)
+    pm = Plan(d, L, flags=flags, nu1=nu, nu2=nu, precision="mixed", inner_cycles=0)
+    um = torch.zeros_like(f)
+    pm.solve(um, f, rtol=1e-10)  # warm-up (autotunes)
+    ts = []
+    for _ in range(max(1, steps)):
+        um.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, it, rel = pm.solve(um, f, rtol=1e-10)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ms = 1e3 * sum(ts) / len(ts)
+    inner = pm.cfg.inner_cycles
+    del pm
+    p64 = Plan(d, L, nu1=nu, nu2=nu)
+    nrm = p64.op_residual(0, um, f, None, want_norm=True)
+    res0 = float(torch.linalg.vector_norm(f))
+    diff = float(torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64))
+    del p64, um
+    return {"mixed_ms_per_solve": ms, "mixed_steps": it, "mixed_status": st,
+            "mixed_inner_cycles": inner, "mixed_speedup_vs_fp64": ms64 / ms,
+            "mixed_fp64_relres": (nrm / res0) if res0 > 0 else 0.0,
+            "mixed_vs_fp64_rel_diff": diff}
 
 
 def compare_fp64(args, spec, plan, u_mixed, f, mixed_ms):
@@ -373,6 +426,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload: skip the mixed-precision and batch comparisons")
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--nu1", type=int, default=None, help="FMG workloads: pre-sweeps")
@@ -399,7 +454,7 @@ def main():
         sys.exit("bench.py: --nu1/--nu2 apply to the FMG workloads only")
     d, L = spec["dim"], spec["L"]
     nu = spec.get("nu", 2)
-    inner = spec.get("inner", 1)
+    inner = spec.get("inner")  # None: the library's default inner-cycle count
     m = (1 << L) - 1
     N = m ** d
     f_host = make_rhs(spec)
@@ -507,8 +562,25 @@ def main():
         line["config"]["paper_gtx480_s"] = spec["paper_s"]
     if spec["prec"] == "mixed":
         line["config"].update(compare_fp64(args, spec, plan, u, f, ms_per_step))
-        line["config"]["inner_cycles"] = inner
-    if not args.no_cpu_baseline and f_host is not None:
+        line["config"]["inner_cycles"] = plan.cfg.inner_cycles
+    if spec.get("extras") and not args.no_extras:
+        # u holds the FP64 solve's result (last breakdown solve)
+        line["config"].update(mixed_vs_fp64(args, spec, f, u, ms_per_step,
+                                            min(args.steps, 5)))
+        print("# mixed: %(mixed_ms_per_solve).3f ms, %(mixed_steps)d steps of "
+              "%(mixed_inner_cycles)d FP32 cycles, %(mixed_speedup_vs_fp64).2fx FP64, FP64 relres "
+              "%(mixed_fp64_relres).2e, distance %(mixed_vs_fp64_rel_diff).2e" % line["config"],
+              flush=True)
+        b = run_batch(args, min(args.steps, 10), 1)
+        line["config"]["batch256"] = b
+        print("# batch: %.3f ms, %.2fx the sequential single solves (%.3f ms)" % (
+            b["batch_ms_per_solve"], b["speedup_vs_sequential"],
+            b["sequential_single_solves_ms"]), flush=True)
+    if not args.no_cpu_baseline:
+        if f_host is None:
+            del plan, u
+            torch.cuda.synchronize()
+            f_host = f.cpu().numpy()
         line["cpu_baseline"] = cpu_baseline(spec, f_host, iters[-1])
     print(json.dumps(line), flush=True)
 

@@ -120,7 +120,8 @@ typedef struct {
 
 typedef struct gmg_plan gmg_plan; /* opaque, host side */
 
-/* Fill *cfg with defaults: RBGS V(2,2), FP64, one inner cycle, no flags. */
+/* Fill *cfg with defaults: RBGS V(2,2), FP64, two inner cycles (used by
+ * MIXED_FP32_IR plans), no flags. */
 gmg_status gmg_config_default(gmg_config *cfg, int dim, int levels);
 
 /* Create a plan (Algorithm 3's set-up: level table, workspace carving).
@@ -208,6 +209,17 @@ gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, in
  * batch plan, or a role without sweeps. */
 gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages, int *variant,
                              int *tz);
+
+/* Check an autotuner cache file (the file GMG_TUNE_CACHE names; one JSON
+ * line per tuned level and role, appended by the tuner).  Counts the lines
+ * the tuner would use (*n_valid) and those it skips and re-tunes
+ * (*n_invalid): lines that do not parse, keys written for another build's
+ * tile tables, and choices that cannot run (sweeps per pass above the cap,
+ * a tile index outside the table, a negative z-chunk, or more workgroups
+ * than the norm-partials buffer holds).  Blank lines are ignored.  Host only
+ * (no HIP call); GMG_ERR_INVALID_ARG for NULL arguments or a file that
+ * cannot be opened. */
+gmg_status gmg_tune_cache_check(const char *path, int *n_valid, int *n_invalid);
 
 /* ---------------------------------------------------------------------- */
 /* Operator primitives.  Each runs exactly the kernels the cycle runs for  */

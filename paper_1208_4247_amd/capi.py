@@ -46,7 +46,7 @@ EXPORTED = [
     "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
     "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg", "gmg_dst_setup", "gmg_dst_solve",
-    "gmg_dst_destroy",
+    "gmg_dst_destroy", "gmg_tune_cache_check",
 ]
 
 
@@ -122,6 +122,7 @@ def lib():
     L.gmg_profile_set_mask.argtypes = [vp, ctypes.c_uint]
     ip = ctypes.POINTER(ctypes.c_int)
     L.gmg_plan_get_tile.argtypes = [vp, i, i, ip, ip, ip]
+    L.gmg_tune_cache_check.argtypes = [ctypes.c_char_p, ip, ip]
     for name in EXPORTED:
         if name not in ("gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
                         "gmg_profile_count", "gmg_tile_variant_count"):
@@ -138,6 +139,14 @@ def check(s: int, where: str) -> int:
     if s < 0:
         raise GmgError(s, where)
     return s
+
+
+def tune_cache_check(path: str) -> tuple[int, int]:
+    """(usable, skipped) line counts of an autotuner cache file."""
+    nv, ni = ctypes.c_int(0), ctypes.c_int(0)
+    check(lib().gmg_tune_cache_check(path.encode(), ctypes.byref(nv), ctypes.byref(ni)),
+          "gmg_tune_cache_check")
+    return nv.value, ni.value
 
 
 def config_default(dim: int, levels: int) -> GmgConfig:

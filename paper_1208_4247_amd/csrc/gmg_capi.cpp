@@ -1095,15 +1095,72 @@ std::vector<int> tune_z_chunks(int dim, int m, int stages, const PassTile &t) {
   return v;
 }
 
+// The key names the device, the level's shape and role, the options that
+// change which passes run, and a hash of the tile tables, so an entry written
+// for another build's tables is never applied.
 std::string tune_key(const gmg_plan &p, int l, int role, size_t elem) {
-  char buf[160];
-  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d|z4", arch_name().c_str(),
-                p.dim, p.m[l], (int)(elem * 8), p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs",
-                role == 0 ? p.cfg.nu1 : p.cfg.nu2, role, p.smax_cap,
-                (p.cfg.flags & GMG_NO_FUSED_RESTRICT) ? 0 : 1);
+  char buf[192];
+  std::snprintf(buf, sizeof(buf), "%s|d%d|m%d|f%d|%s|nu%d|r%d|cap%d|fr%d|z4|t%08x",
+                arch_name().c_str(), p.dim, p.m[l], (int)(elem * 8),
+                p.cfg.smoother == GMG_SMOOTH_WJ ? "wj" : "rbgs", role == 0 ? p.cfg.nu1 : p.cfg.nu2,
+                role, p.smax_cap, (p.cfg.flags & GMG_NO_FUSED_RESTRICT) ? 0 : 1,
+                (unsigned)tile_table_hash());
   return buf;
 }
 
+// Whether a pass choice can be launched on a level of side m: sweeps per
+// pass within the plan's cap, every stage count's tile index inside the tile
+// table, a non-negative z-chunk, and no pass with more workgroups than the
+// norm-partials buffer holds.  (The folded restriction re-checks its own,
+// larger geometry and LDS before every use.)
+bool choice_ok(int dim, int m, int smax_cap, bool wj, const PassChoice &c) {
+  if (c.smax < 1 || c.smax > smax_cap || (c.fuse != 0 && c.fuse != 1)) return false;
+  for (int st = 1; st <= 4; ++st) {
+    const int nv = pass_variant_count(dim, st, wj ? 1 : 0);
+    if (nv == 0) continue;
+    if (c.var[st] < 0 || c.var[st] >= nv || c.tz[st] < 0) return false;
+    const PassTile t = pass_variant(dim, st, wj ? 1 : 0, c.var[st]);
+    if (pass_geometry(dim, m, st, t, c.tz[st]).nblocks > kMaxPartials) return false;
+  }
+  return true;
+}
+
+// One line of the on-disk cache: key, sweeps per pass, stage count, tile
+// index, z-chunk, fold flag.  False for a line that does not parse.
+bool parse_cache_line(const char *line, std::string &key, PassChoice &c, int &st) {
+  char kb[256];
+  int v = 0, tz = 0, fz = 1;
+  st = 0;
+  if (std::sscanf(line,
+                  "{\"key\": \"%255[^\"]\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, "
+                  "\"fuse\": %d",
+                  kb, &c.smax, &st, &v, &tz, &fz) != 6 || st < 1 || st > 4)
+    return false;
+  key = kb;
+  c.var[st] = v;
+  c.tz[st] = tz;
+  c.fuse = fz;
+  return true;
+}
+
+// The level shape a key describes (dimension, side, Jacobi or not, sweep cap)
+// and whether the key carries this build's tile-table hash.
+bool key_shape(const std::string &key, int &dim, int &m, bool &wj, int &cap) {
+  const size_t bar = key.find('|');
+  if (bar == std::string::npos) return false;
+  char smooth[16] = {0};
+  int f = 0, nu = 0, r = 0, fr = 0, z = 0;
+  unsigned th = 0;
+  if (std::sscanf(key.c_str() + bar, "|d%d|m%d|f%d|%15[a-z]|nu%d|r%d|cap%d|fr%d|z%d|t%x", &dim, &m,
+                  &f, smooth, &nu, &r, &cap, &fr, &z, &th) != 10)
+    return false;
+  wj = std::strcmp(smooth, "wj") == 0;
+  return th == tile_table_hash() && (dim == 2 || dim == 3) && m >= 1 && cap >= 1;
+}
+
+// Loads GMG_TUNE_CACHE once per process.  Lines that do not parse, name
+// another build's tile tables or a choice that cannot run are skipped (that
+// level is tuned again).
 void tune_cache_load() {
   static bool loaded = false;
   if (loaded) return;
@@ -1114,21 +1171,17 @@ void tune_cache_load() {
   if (!fh) return;
   char line[512];
   while (std::fgets(line, sizeof(line), fh)) {
-    char key[256];
+    std::string key;
     PassChoice c;
-    int st = 0, v = 0, tz = 0, fz = 1;
-    if (std::sscanf(line,
-                    "{\"key\": \"%255[^\"]\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, "
-                    "\"fuse\": %d",
-                    key, &c.smax, &st, &v, &tz, &fz) == 6 && st >= 1 && st <= 4) {
-      c.fuse = fz;
-      auto it = tune_cache().find(key);
-      PassChoice &d = it == tune_cache().end() ? (tune_cache()[key] = c) : it->second;
-      d.smax = c.smax;
-      d.var[st] = v;
-      d.tz[st] = tz;
-      d.fuse = c.fuse;
-    }
+    int st = 0, dim = 0, m = 0, cap = 0;
+    bool wj = false;
+    if (!parse_cache_line(line, key, c, st) || !key_shape(key, dim, m, wj, cap)) continue;
+    auto it = tune_cache().find(key);
+    PassChoice &d = it == tune_cache().end() ? (tune_cache()[key] = c) : it->second;
+    d.smax = c.smax;
+    d.var[st] = c.var[st];
+    d.tz[st] = c.tz[st];
+    d.fuse = c.fuse;
   }
   std::fclose(fh);
 }
@@ -1156,12 +1209,15 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
   const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;
   if (nu == 0) return hipSuccess;
   const std::string key = tune_key(*p, l, role, elem);
+  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
   auto it = tune_cache().find(key);
   if (it != tune_cache().end()) {
-    p->ch[l][role] = it->second;
-    return hipSuccess;
+    if (choice_ok(p->dim, p->m[l], p->smax_cap, wj, it->second)) {
+      p->ch[l][role] = it->second;
+      return hipSuccess;
+    }
+    tune_cache().erase(it);  // unusable cached choice: tune this level again
   }
-  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
   const int m = p->m[l];
   hipEvent_t e0, e1;
   hipError_t err = hipEventCreate(&e0);
@@ -1785,7 +1841,7 @@ gmg_status gmg_config_default(gmg_config *cfg, int dim, int levels) {
   cfg->nu2 = 2;
   cfg->omega = 0.0;
   cfg->precision = GMG_FP64;
-  cfg->inner_cycles = 1;
+  cfg->inner_cycles = 2;
   cfg->flags = 0;
   return validate_cfg(cfg);
 }
@@ -2122,6 +2178,28 @@ gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages
   if (variant) *variant = c.var[st];
   if (tz) *tz = c.tz[st] > 0 ? std::min(c.tz[st], p->m[level])
                              : auto_tz(p->dim, p->m[level], st, t);
+  return GMG_OK;
+}
+
+gmg_status gmg_tune_cache_check(const char *path, int *n_valid, int *n_invalid) {
+  if (!path || !n_valid || !n_invalid) return GMG_ERR_INVALID_ARG;
+  FILE *fh = std::fopen(path, "r");
+  if (!fh) return GMG_ERR_INVALID_ARG;
+  *n_valid = *n_invalid = 0;
+  char line[512];
+  while (std::fgets(line, sizeof(line), fh)) {
+    bool blank = true;
+    for (const char *c = line; *c; ++c) blank = blank && (*c == ' ' || *c == '\n' || *c == '\r');
+    if (blank) continue;
+    std::string key;
+    PassChoice c;
+    int st = 0, dim = 0, m = 0, cap = 0;
+    bool wj = false;
+    const bool ok = parse_cache_line(line, key, c, st) && key_shape(key, dim, m, wj, cap) &&
+                    cap <= 2 && choice_ok(dim, m, cap, wj, c);
+    ++(ok ? *n_valid : *n_invalid);
+  }
+  std::fclose(fh);
   return GMG_OK;
 }
 

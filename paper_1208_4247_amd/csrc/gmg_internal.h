@@ -65,6 +65,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, int 
                                            in ? plane * (int)sizeof(T) : 0, 0x00020000);
 }
 
+// raw buffer over plane z when `on`, else one with no records (its loads
+// return 0 and its stores are dropped).  Lets a store that applies to some
+// steps only be issued on every step, with no branch around it, so the
+// compiler's count of outstanding memory operations stays exact and a wait
+// for an older load never has to include younger loads.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_if(const T *base, int z, bool on,
+                                                                int plane) {
+  const T *p = base + (on ? (size_t)z * plane : 0);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0,
+                                           on ? plane * (int)sizeof(T) : 0, 0x00020000);
+}
+
 template <typename T>
 __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off) {
   if constexpr (sizeof(T) == 8)
@@ -228,6 +241,9 @@ PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz,
 constexpr size_t kMaxPassLds = 160 * 1024;
 size_t rb_pass_lds_bytes(int dim, int stages, int exp_, int ey, int flags, size_t elem);
 bool rb_pass_fits(int dim, int stages, int variant, int flags, size_t elem);
+// FNV-1a hash of the tile tables (shape of every variant index): part of the
+// autotuner's cache key, so a cached variant index never names another shape
+uint32_t tile_table_hash();
 
 // Launchers.  Batch mode: tbl != NULL points to nent device-resident argument
 // entries (one problem each, all with the same level size); the grid gets a

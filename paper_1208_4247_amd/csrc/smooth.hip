@@ -36,6 +36,19 @@
 
 namespace gmg {
 
+// Compiler-only fences for the load pipelines of the passes (no instruction
+// is emitted).  pin_value: v is computed here, not sunk below this point,
+// and no memory access moves across; compiler_fence: only the latter.  A
+// load issued after the fence into registers whose previous contents were
+// consumed before it can reuse those registers, so a value loaded for a
+// later step is carried around the loop without a copy, and nothing waits
+// on it until it is used.
+template <typename T>
+__device__ __forceinline__ void pin_value(T &v) {
+  asm volatile("" : "+v"(v) : : "memory");
+}
+__device__ __forceinline__ void compiler_fence() { asm volatile("" : : : "memory"); }
+
 __device__ __forceinline__ int xcd_remap(int bid, int n) {
   const int xcd = bid & 7, loc = bid >> 3;
   const int per = n >> 3, rem = n & 7;
@@ -261,21 +274,49 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   // only touches planes outside the exact region
   const int t0 = (Z0 - S - (RST ? 2 : 0)) & ~1;
   const int t1 = RST ? 2 * CZ1 + S + 3 : Z1 + S;
-  auto load_u = [&](int t, T *v0, T *v1) {
-    if (ZERO) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) v0[i] = v1[i] = T(0);
-      return;
-    }
+
+  // Loads run two steps ahead of their use: plane t + 2's start value and
+  // right-hand side are issued during step t, right after plane t's raw
+  // loads have been consumed, into the same registers (uR / fR, indexed by
+  // plane parity, which is a compile-time index in the pair of steps).  Two
+  // planes of loads are then in flight per workgroup while one is computed;
+  // one plane's worth does not cover the memory latency.  The raw pairs are
+  // only unpacked (element choice, zero boundary) when their plane is used,
+  // so nothing waits on a load early.
+  PairOf<T> uR[2][ZERO ? 1 : NS], fR[2][NS];
+  auto issue_u = [&](int t, PairOf<T> *v) {
+    if (ZERO) return;
     const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.u_in, t, m, planeS);
 #pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] = bload2<T>(r, o2[i]);
+  };
+  auto take_u = [&](const PairOf<T> *v, T *v0, T *v1) {
+#pragma unroll
     for (int i = 0; i < NS; ++i) {
-      const PairOf<T> v = bload2<T>(r, o2[i]);
-      v0[i] = kP[i] ? (hP[i] ? v.hi : v.lo) : T(0);
-      v1[i] = kQ[i] ? (hQ[i] ? v.hi : v.lo) : T(0);
+      if (ZERO) {
+        v0[i] = v1[i] = T(0);
+      } else {
+        v0[i] = kP[i] ? (hP[i] ? v[i].hi : v[i].lo) : T(0);
+        v1[i] = kQ[i] ? (hQ[i] ? v[i].hi : v[i].lo) : T(0);
+      }
     }
   };
-  load_u(t0, pu0, pu1);
+  auto issue_f = [&](int z, PairOf<T> *v) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.f, z, m, planeS);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] = bload2<T>(r, o2[i]);
+  };
+  auto take_f = [&](const PairOf<T> *v, T *vP, T *vQ) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      vP[i] = hP[i] ? v[i].hi : v[i].lo;
+      vQ[i] = hQ[i] ? v[i].hi : v[i].lo;
+    }
+  };
+  issue_u(t0, uR[0]);
+  issue_f(t0, fR[0]);
+  issue_u(t0 + 1, uR[1]);
+  issue_f(t0 + 1, fR[1]);
 
   // PRO geometry: tile origin (X0 - S, Y0 - S) is even in both axes, so pair
   // p reads coarse columns p (left) and p + 1 (right); an odd row r of the
@@ -331,22 +372,16 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   }
 
   // right-hand side window: fP[j] / fQ[j] hold elements P / Q of f on plane
-  // t - j (j = 0 .. S) during step t; stage s reads plane t - s.  Plane t + 1
-  // is loaded during step t (one step of latency hidden), with the next
-  // plane's start value and (odd steps) the next coarse plane.
-  auto load_f = [&](int z, T *vP, T *vQ) {
-    const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.f, z, m, planeS);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      const PairOf<T> v = bload2<T>(r, o2[i]);
-      vP[i] = hP[i] ? v.hi : v.lo;
-      vQ[i] = hQ[i] ? v.hi : v.lo;
-    }
-  };
+  // t - j (j = 0 .. NF - 1) during step t; stage s reads plane t - s.  Plane
+  // t enters the window at the top of step t from its raw loads.
   constexpr int NF = S + 1 + (RST ? 1 : 0);  // RST: plane t-S-1 for the residual
   T fP[NF][NS], fQ[NF][NS];
 #pragma unroll
-  for (int j = 0; j < NF; ++j) load_f(t0 - j, fP[j], fQ[j]);
+  for (int j = 1; j < NF; ++j) {
+    PairOf<T> v[NS];
+    issue_f(t0 - j, v);
+    take_f(v, fP[j], fQ[j]);
+  }
   // RST: final values (elements 0 / 1) of planes t-S, t-S-1, t-S-2, and the
   // full-weighting accumulator of this thread's coarse point
   T fw0[RST ? NS : 1][3], fw1[RST ? NS : 1][3];
@@ -359,9 +394,10 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   const bool cown = RST && (int)threadIdx.x < NCC && cgx < mc && (DIM == 2 || cgy < mc);
   const int cq = (DIM == 3 ? (HY + 2 * ccy + 1) * EXP : 0) + HP + ccx;  // slot of the centre
   T cacc = T(0);
-  GMG_GLOBAL T *__restrict__ fcg = gbl(a.f_c);
   static_assert(!RST || NCC <= NT, "one thread per coarse point");
-  T cnext[NCP];  // PRO: coarse plane (t + 1) / 2 for the odd step t, loaded at step t - 1
+  // PRO: coarse plane (t + 1) / 2 for the odd step t, loaded at the odd step
+  // before it (right after that step staged its own plane in LDS)
+  T cnext[NCP];
   if (PRO) load_c((t0 + 2) >> 1, cnext);
 
   auto step = [&](int t, auto tp_tag) {
@@ -370,40 +406,55 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     constexpr bool B0P = ((C0 + TP - 1) & 1) == 0;  // colour-C0 element of plane t-1 is P
     const int zr = t - 1;
     const bool rin = NORM && zr >= Z0 && zr < Z1;
-    T nu0[NS], nu1[NS];
-    load_u(t + 1, nu0, nu1);
-    T fnP[NS], fnQ[NS];
-    load_f(t + 1, fnP, fnQ);
-    T cnn[NCP];
-    if (PRO && TP == 1) load_c((t + 3) >> 1, cnn);
+    // plane t: start value and right-hand side from the raw loads of step
+    // t - 2, then plane t + 2's loads into the same registers
+    take_u(uR[TP], pu0, pu1);
+#pragma unroll
+    for (int j = NF - 1; j >= 1; --j)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        fP[j][i] = fP[j - 1][i];
+        fQ[j][i] = fQ[j - 1][i];
+      }
+    take_f(fR[TP], fP[0], fQ[0]);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      pin_value(pu0[i]);
+      pin_value(pu1[i]);
+      pin_value(fP[0][i]);
+      pin_value(fQ[0][i]);
+    }
+    issue_u(t + 2, uR[TP]);
+    issue_f(t + 2, fR[TP]);
     const T *Lprev = lds + (1 - TP) * NB * PL;  // planes published at step t-1
 
     // ---- RST: full weighting of the residual plane t-S-2 (published at step
     // t-1) onto this thread's coarse point: in-plane x, then y, then the
     // three fine planes of a coarse plane (1/4, 1/2, 1/4)
     if (RST) {
-      const int zf = t - S - 2;
-      if (cown && zf >= 2 * CZ0 && zf <= 2 * CZ1) {
+      const int zf = t - S - 2;  // zf & 1 == (TP + S) & 1: a compile-time choice
+      const bool use = cown && zf >= 2 * CZ0 && zf <= 2 * CZ1;
+      T sxy = T(0);
+      if (use) {
         const T *R0 = rl + (1 - TP) * 2 * PL, *R1 = R0 + PL;
         auto row = [&](int q) {
           return T(0.25) * R0[q] + T(0.5) * R1[q] + T(0.25) * R0[q + 1];
         };
-        T sxy;
         if (DIM == 3)
           sxy = T(0.25) * row(cq - EXP) + T(0.5) * row(cq) + T(0.25) * row(cq + EXP);
         else
           sxy = row(cq);
-        if (zf & 1) {
-          cacc += T(0.5) * sxy;
-        } else {
-          const int c = zf / 2 - 1;
-          if (c >= CZ0 && c < CZ1) {
-            cacc += T(0.25) * sxy;
-            const size_t o = DIM == 3 ? ((size_t)c * mc + cgy) * mc + cgx : (size_t)c * mc + cgx;
-            fcg[o] = cacc;
-          }
-          cacc = T(0.25) * sxy;
-        }
+      }
+      if constexpr (((TP + S) & 1) != 0) {
+        if (use) cacc += T(0.5) * sxy;
+      } else {
+        // a coarse plane is complete: store it (every lane issues the store;
+        // it lands only for coarse points of this tile and chunk)
+        const int c = zf / 2 - 1;
+        const bool cin = zf >= 2 * CZ0 && zf <= 2 * CZ1 && c >= CZ0 && c < CZ1;
+        const __amdgpu_buffer_rsrc_t rc = plane_rsrc_if(a.f_c, c, cin, cplane);
+        bstore<T>(rc, use ? (cgy * mc + cgx) * (int)sizeof(T) : kOOB, cacc + T(0.25) * sxy);
+        if (use) cacc = T(0.25) * sxy;
       }
     }
 
@@ -492,8 +543,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     }
     // ---- output plane t-S: last stage's colour from newS, the other from S-1
     const int zo = t - S;
-    if (zo >= Z0 && zo < Z1) {
-      const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.u_out, zo, m, planeS);
+    {
+      const __amdgpu_buffer_rsrc_t r = plane_rsrc_if(a.u_out, zo, zo >= Z0 && zo < Z1, planeS);
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         const T o_new = newS[i], o_old = W[S - 1][i][1];
@@ -555,24 +606,12 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
       for (int s = 0; s < S; ++s) Lnow[s * PL + lq[i]] = W[s][i][0];
       if (NORM) Lnow[S * PL + lq[i]] = WB[i][0];
     }
-    if (PRO && TP == 1) store_c((t + 1) >> 1, cnext);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      pu0[i] = nu0[i];
-      pu1[i] = nu1[i];
-#pragma unroll
-      for (int j = NF - 1; j >= 1; --j) {
-        fP[j][i] = fP[j - 1][i];
-        fQ[j][i] = fQ[j - 1][i];
-      }
-      fP[0][i] = fnP[i];
-      fQ[0][i] = fnQ[i];
-    }
     if (PRO && TP == 1) {
-#pragma unroll
-      for (int k = 0; k < NCP; ++k) cnext[k] = cnn[k];
+      store_c((t + 1) >> 1, cnext);
+      compiler_fence();
+      load_c((t + 3) >> 1, cnext);
     }
+    __syncthreads();
   };
   for (int t = t0; t < t1; t += 2) {
     step(t, IntC<0>());
@@ -949,6 +988,24 @@ PassTile pass_variant(int dim, int stages, int wj, int v) {
   t.ey = r.ey;
   t.nt = r.nt;
   return t;
+}
+
+uint32_t tile_table_hash() {
+  uint32_t h = 2166136261u;
+  auto mix = [&](int v) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (uint32_t)(v >> (8 * b)) & 0xffu;
+      h *= 16777619u;
+    }
+  };
+  for (const TileRow &r : kRbTiles) {
+    mix(r.dim); mix(r.s); mix(r.exp_); mix(r.ey); mix(r.nt);
+  }
+  mix(-1);
+  for (const TileRow &r : kWjTiles) {
+    mix(r.dim); mix(r.s); mix(r.exp_); mix(r.ey); mix(r.nt);
+  }
+  return h;
 }
 
 size_t rb_pass_lds_bytes(int dim, int stages, int exp_, int ey, int flags, size_t elem) {

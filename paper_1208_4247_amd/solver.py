@@ -31,7 +31,7 @@ def _stream():
 
 class Plan:
     def __init__(self, dim: int, levels: int, smoother: str = "rbgs", nu1: int = 2, nu2: int = 2,
-                 omega: float = 0.0, precision: str = "fp64", inner_cycles: int = 1,
+                 omega: float = 0.0, precision: str = "fp64", inner_cycles: int | None = None,
                  flags: int = 0):
         L = capi.lib()
         cfg = capi.config_default(dim, levels)
@@ -40,7 +40,8 @@ class Plan:
         cfg.nu1, cfg.nu2 = int(nu1), int(nu2)
         cfg.omega = float(omega)
         cfg.precision = {"fp64": capi.GMG_FP64, "mixed": capi.GMG_MIXED_FP32_IR}[precision]
-        cfg.inner_cycles = int(inner_cycles)
+        if inner_cycles is not None:
+            cfg.inner_cycles = int(inner_cycles)
         cfg.flags = int(flags)
         self.cfg = cfg
         self.dim, self.levels = dim, levels

@@ -45,7 +45,7 @@ def test_status_strings(capi):
 
 def test_config_default(capi):
     c = capi.config_default(3, 8)
-    assert (c.dim, c.levels, c.nu1, c.nu2, c.smoother, c.precision, c.inner_cycles) == (3, 8, 2, 2, 0, 0, 1)
+    assert (c.dim, c.levels, c.nu1, c.nu2, c.smoother, c.precision, c.inner_cycles) == (3, 8, 2, 2, 0, 0, 2)
 
 
 @pytest.mark.parametrize("field,value", [("dim", 1), ("dim", 4), ("levels", 0), ("levels", 11),
@@ -127,3 +127,60 @@ def test_paper_variant_rejected_where_unsupported(capi):
     cfg = capi.config_default(2, 5)
     cfg.smoother = 3
     assert capi.workspace_bytes(cfg)[0] == capi.GMG_ERR_INVALID_ARG
+
+
+def _tile_table_hash():
+    """FNV-1a over the tile tables of smooth.hip, in the library's order
+    (red-black tables, a -1 separator, Jacobi tables), as the tuner keys its
+    cache."""
+    src = open(os.path.join(ROOT, "paper_1208_4247_amd", "csrc", "smooth.hip")).read()
+
+    def rows(name):
+        body = re.search(r"#define %s\(X\)(.*?)\n(?!\s)" % name, src, flags=re.S).group(1)
+        return [tuple(int(v) for v in r.split(",")) for r in re.findall(r"X\(([^)]*)\)", body)]
+
+    h = 2166136261
+
+    def mix(v):
+        nonlocal h
+        for b in range(4):
+            h ^= (v >> (8 * b)) & 0xFF
+            h = (h * 16777619) & 0xFFFFFFFF
+
+    for name in ("GMG_RB3_S2", "GMG_RB3_S4", "GMG_RB2_S2", "GMG_RB2_S4"):
+        for r in rows(name):
+            for v in r:
+                mix(v)
+    mix(-1 & 0xFFFFFFFF)
+    for name in ("GMG_WJ3_S1", "GMG_WJ3_S2", "GMG_WJ2_S1", "GMG_WJ2_S2"):
+        for r in rows(name):
+            for v in r:
+                mix(v)
+    return h
+
+
+def _cache_line(m, smax, stages, var, tz, th, dim=3, cap=2):
+    key = "gfx950|d%d|m%d|f64|rbgs|nu2|r0|cap%d|fr1|z4|t%08x" % (dim, m, cap, th)
+    return ('{"key": "%s", "smax": %d, "stages": %d, "var": %d, "tz": %d, "fuse": 1, '
+            '"us": 1.0}\n' % (key, smax, stages, var, tz))
+
+
+def test_tune_cache_check_rejects_unusable_lines(capi, tmp_path):
+    th = _tile_table_hash()
+    good = _cache_line(255, 2, 4, 3, 64, th)
+    bad = [
+        _cache_line(255, 2, 4, 3, 64, th ^ 1),   # another build's tile tables
+        _cache_line(255, 2, 4, 9, 64, th),       # tile index beyond the table
+        _cache_line(255, 5, 4, 3, 64, th),       # sweeps per pass above the cap
+        _cache_line(255, 2, 4, 3, -8, th),       # negative z-chunk
+        _cache_line(1023, 1, 2, 1, 4, th),       # 262144 workgroups > partials buffer
+        good.replace("|z4|t%08x" % th, "|z4"),   # key without the table hash
+        "not a cache line\n",
+    ]
+    p = tmp_path / "tune.jsonl"
+    p.write_text(good + "\n" + "".join(bad))
+    assert capi.tune_cache_check(str(p)) == (1, len(bad))
+    p.write_text(good + _cache_line(1023, 2, 2, 0, 0, th))
+    assert capi.tune_cache_check(str(p)) == (2, 0)
+    with pytest.raises(capi.GmgError):
+        capi.tune_cache_check(str(tmp_path / "missing.jsonl"))

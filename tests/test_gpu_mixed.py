@@ -115,17 +115,21 @@ def test_mixed_solve_odd_and_even_step_counts_land_in_u():
         assert abs(r - rel) <= 1e-6 * rel
 
 
-def test_mixed_vcycle_is_one_refinement_step():
-    """gmg_vcycle on a mixed plan: x <- x + V32(f - A x); compare with the
-    FP64 oracle's cycle from the same x (equal to FP32 accuracy of the
-    correction)."""
+@pytest.mark.parametrize("inner", [1, 2])
+def test_mixed_vcycle_is_one_refinement_step(inner):
+    """gmg_vcycle on a mixed plan: one refinement step x <- x + e with e
+    from `inner` FP32 cycles on A e = f - A x started at zero; the cycle is
+    affine, so this equals `inner` FP64 oracle cycles from the same x (to
+    FP32 accuracy of the correction)."""
     f = wl.rhs_uniform(3, 31, seed=96)
     x = wl.rhs_uniform(3, 31, seed=97) * 1e-3
-    plan = Plan(3, 5, precision="mixed")
+    plan = Plan(3, 5, precision="mixed", inner_cycles=inner)
     xd = dev(x)
     plan.vcycle(xd, dev(f))
     got = host(xd)
-    want = oracle.vcycle(x, f)
+    want = x
+    for _ in range(inner):
+        want = oracle.vcycle(want, f)
     corr = want - x
     assert float(np.max(np.abs(got - want))) <= 1e-5 * float(np.max(np.abs(corr)))
 

@@ -286,6 +286,40 @@ def test_solve_nonfinite_rhs():
     assert ei.value.status == capi.GMG_ERR_NONFINITE
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_reports_divergence(precision):
+    """Algorithm 3's loop with a resumed reference norm far below the
+    residual of the start value: after the first cycle the residual is still
+    above 1e3 times that reference, so the solve stops with
+    GMG_ERR_DIVERGED and still reports its cycle count and relative
+    residual.  Ordinary inputs; the stop test is what is exercised."""
+    import ctypes
+
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import _ptr
+
+    f = wl.rhs_uniform(3, 31, seed=84)
+    plan = Plan(3, 5, precision=precision)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    it, rel = ctypes.c_int(-1), ctypes.c_double(-1.0)
+    res0 = ctypes.c_double(1e-30)
+    s = capi.lib().gmg_solve(plan.handle, _ptr(ud), _ptr(fd), 1e-10, 50, ctypes.byref(res0),
+                             ctypes.byref(it), ctypes.byref(rel))
+    torch.cuda.synchronize()
+    assert s == capi.GMG_ERR_DIVERGED, capi.status_string(s)
+    assert it.value == 1
+    # relres = ||f - A u_1|| / 1e-30 with u_1 the first iterate: one cycle
+    # from zero, or (mixed) one refinement step of inner_cycles FP32 cycles,
+    # which equals that many cycles up to FP32 rounding of the correction
+    u1 = np.zeros_like(f)
+    for _ in range(1 if precision == "fp64" else plan.cfg.inner_cycles):
+        u1 = oracle.vcycle(u1, f, 2, 2)
+    want = oracle.norm2(oracle.residual(u1, f)) / 1e-30
+    assert abs(rel.value / want - 1.0) < (1e-9 if precision == "fp64" else 1e-3)
+    assert plan.solve(torch.zeros_like(fd), fd, rtol=1e-10)[0] == capi.GMG_OK
+
+
 def test_run_to_run_bitwise():
     f = dev(wl.rhs_uniform(3, 63, seed=83))
     plan = Plan(3, 6)
@@ -403,7 +437,7 @@ def test_profile_counts_only_launches_that_ran(precision):
         assert prof["bottom"]["launches"] == it
     else:
         assert prof["ir_step"]["launches"] == it + 1
-        assert prof["bottom"]["launches"] == it
+        assert prof["bottom"]["launches"] == it * plan.cfg.inner_cycles
     # a second solve accumulates the same counts again
     u.zero_()
     plan.solve(u, f, rtol=1e-10)
