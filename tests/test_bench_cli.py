@@ -22,7 +22,7 @@ def test_workloads_name_known_cycles():
 
     assert bench.DEFAULT in bench.WORKLOADS
     d = bench.WORKLOADS[bench.DEFAULT]
-    assert (d["dim"], d["L"], d["prec"]) == (3, 8, "fp64")  # 255^3, FP64
+    assert (d["dim"], d["L"], d["prec"], d.get("nu")) == (3, 10, "fp64", 1)  # 1023^3 FP64 V(1,1)
     for name, spec in bench.WORKLOADS.items():
         # dim 0: the batch of problems of several sizes
         assert spec["dim"] in ((0,) if spec["rhs"] == "batch" else (2, 3)), name
