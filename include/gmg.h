@@ -105,6 +105,10 @@ typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
                                        sweeps from zero (Algorithm 1 as printed)
                                        instead of solved exactly; differs only
                                        for WJ                                  */
+#define GMG_NO_CROSS_CYCLE 0x200u   /* FP64 red-black V(1,1) solves: run each
+                                       cycle's level-0 post-smoothing and the
+                                       next cycle's pre-smoothing as two passes
+                                       instead of one (same iterates)         */
 
 typedef struct {
   int dim;                 /* 2 or 3                                            */
@@ -192,21 +196,25 @@ int gmg_level_side(const gmg_plan *p, int problem, int level);
 
 /* Tile shapes of the fused smoothing passes.  A pass applies `stages`
  * stages in one sweep over memory (red-black: 2 per sweep; weighted Jacobi:
- * 1 per sweep); each stage count has a few tile shapes.  Returns the number
- * of shapes (0: that stage count is not provided). */
+ * 1 per sweep; red-black 3: the cross-cycle pass of FP64 V(1,1) solves,
+ * which ends one cycle's post-smoothing and starts the next cycle's
+ * pre-smoothing); each stage count has a few tile shapes.  Returns the
+ * number of shapes (0: that stage count is not provided). */
 int gmg_tile_variant_count(int dim, gmg_smoother smoother, int stages);
 
 /* Override the tile shape (index < gmg_tile_variant_count) and the z-chunk
  * (output planes per workgroup; 0 = automatic) used on level `level` of
- * problem 0 for passes with `stages` stages.  Results do not depend on the
- * choice (tests check this bitwise); only speed does.  Host only. */
+ * problem 0 for passes with `stages` stages (red-black 3: the cross-cycle
+ * pass, level 0 only).  Results do not depend on the choice (tests check
+ * this bitwise); only speed does.  Host only. */
 gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, int tz);
 
 /* The tile choice in use (after autotuning, if any) for the first pass of
  * the pre- (role 0) or post-smoothing (role 1) on level `level` of problem 0:
- * its stage count, tile index and z-chunk (resolved, > 0).  Host only; any
- * output pointer may be NULL.  GMG_ERR_INVALID_ARG for a bad level/role, a
- * batch plan, or a role without sweeps. */
+ * its stage count, tile index and z-chunk (resolved, > 0).  Role 2: the
+ * cross-cycle pass of level 0 (plans that run it).  Host only; any output
+ * pointer may be NULL.  GMG_ERR_INVALID_ARG for a bad level/role, a batch
+ * plan, or a role without sweeps. */
 gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages, int *variant,
                              int *tz);
 

@@ -38,6 +38,7 @@ GMG_NO_FUSED_COARSE = 0x20
 GMG_NO_FUSED_RESTRICT = 0x40
 GMG_FE_TRANSFER = 0x80
 GMG_COARSE_RELAX = 0x100
+GMG_NO_CROSS_CYCLE = 0x200
 
 EXPORTED = [
     "gmg_config_default", "gmg_setup", "gmg_vcycle", "gmg_solve", "gmg_batch_solve",

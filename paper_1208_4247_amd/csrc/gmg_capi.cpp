@@ -155,7 +155,12 @@ struct gmg_plan {
   // per level and role (0: descent / pre-smoothing, 1: ascent / post-smoothing
   // with the fused prolongation): sweeps per pass and the tile shape and
   // z-chunk for each stage count
-  std::vector<std::array<PassChoice, 2>> ch;
+  std::vector<std::array<PassChoice, 3>> ch;  // role 2: the cross-cycle pass (level 0)
+  // FP64 red-black V(1,1) with Algorithm 1's backward post-smoothing: the
+  // solve loop runs the cross-cycle schedule (one level-0 pass per cycle that
+  // ends the cycle's post-smoothing and starts the next cycle's
+  // pre-smoothing)
+  bool cross = false;
 
   // profiling
   bool profile = false;
@@ -197,12 +202,13 @@ enum ProfClass {
   PC_FIN,
   PC_IR,
   PC_MISC,
+  PC_CROSS0,
   PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {"smooth_pre_l0", "smooth_post_l0", "resid_restrict_l0",
                                     "smooth_pre_coarse", "smooth_post_coarse",
                                     "resid_restrict_coarse", "bottom", "finalize", "ir_step",
-                                    "misc"};
+                                    "misc", "smooth_cross_l0"};
 
 hipEvent_t get_event(gmg_plan *p) {
   if (!p->evpool.empty()) {
@@ -304,11 +310,10 @@ int stages_of(const gmg_plan *p, int sweeps) {
 }
 
 template <typename T>
-hipError_t one_pass(gmg_plan *p, int level, int role, int sweeps, int flags, const T *src,
-                    const T *ec, const T *f, T *dst, double *partials, const int *active,
-                    int cls, T *fc = nullptr) {
+hipError_t one_pass_st(gmg_plan *p, int level, int role, int st, int flags, const T *src,
+                       const T *ec, const T *f, T *dst, double *partials, const int *active,
+                       int cls, T *fc = nullptr) {
   const int dim = p->dim, m = p->m[level];
-  const int st = stages_of(p, sweeps);
   const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
   const PassChoice &c = p->ch[level][role];
   const int v = c.var[st];
@@ -333,10 +338,19 @@ hipError_t one_pass(gmg_plan *p, int level, int role, int sweeps, int flags, con
   a.inv_h2 = 1.0 / (h * h);
   a.omega = p->cfg.omega;
   double bytes = (double)npts(dim, m) * sizeof(T) * ((flags & F_ZERO_IN) ? 2 : 3);
-  if (flags & (F_PROLONG | F_RESTRICT)) bytes += (double)npts(dim, a.mc) * sizeof(T);
+  if (flags & F_PROLONG) bytes += (double)npts(dim, a.mc) * sizeof(T);
+  if (flags & F_RESTRICT) bytes += (double)npts(dim, a.mc) * sizeof(T);
   ProfScope ps(p, cls, bytes);
   return wj ? launch_wj_pass<T>(dim, st, flags, v, a, p->stream)
             : launch_rb_pass<T>(dim, st, flags, v, a, p->stream);
+}
+
+template <typename T>
+hipError_t one_pass(gmg_plan *p, int level, int role, int sweeps, int flags, const T *src,
+                    const T *ec, const T *f, T *dst, double *partials, const int *active,
+                    int cls, T *fc = nullptr) {
+  return one_pass_st<T>(p, level, role, stages_of(p, sweeps), flags, src, ec, f, dst, partials,
+                        active, cls, fc);
 }
 
 int pass_blocks(const gmg_plan *p, int level, int role, int sweeps, bool rst = false) {
@@ -467,6 +481,45 @@ hipError_t restrict_level(gmg_plan *p, int level, const T *u, const T *f, T *fc,
   ProfScope ps(p, cls, (double)npts(p->dim, m) * sizeof(T) * 2 + (double)npts(p->dim, a.mc) * sizeof(T));
   return launch_restrict<T>(p->dim, a, p->stream);
 }
+
+// ------------------------------------------------------------------ cross-cycle pass
+// The level-0 pass between two V(1,1) cycles of an FP64 red-black solve
+// (Algorithm 1's cycle with its backward post-smoothing, repeated by
+// Algorithm 3's loop).  From w_k + P e_k -- cycle k's pre-smoothed iterate
+// and the interpolated coarse correction -- it runs the post-smoothing sweep
+// (black, then red), which gives u_k and the partial sums of its residual
+// norm for the stop test, and then cycle k+1's forward pre-smoothing sweep.
+// That sweep's red half-sweep would recompute the red values just formed,
+// from the same black neighbours, so it is left out: its black half-sweep is
+// the third and last stage, and the pass writes w_{k+1}.  The residual of
+// w_{k+1} and its full weighting (the next cycle's coarse right-hand side)
+// are folded in when the tile allows it; otherwise the caller restricts.
+// u_k itself is never stored: the solve forms it once, after its last cycle,
+// with an ordinary post-smoothing pass from w_k + P e_k.
+bool can_fuse_cross(const gmg_plan *p) {
+  const PassChoice &c = p->ch[0][2];
+  if (!c.fuse || (p->cfg.flags & GMG_NO_FUSED_RESTRICT)) return false;
+  const PassTile t = pass_variant(p->dim, 3, 0, c.var[3]);
+  if (pass_geometry(p->dim, p->m[0], 3, t, c.tz[3], true).nblocks > kMaxPartials) return false;
+  return rb_pass_fits(p->dim, 3, c.var[3], F_PROLONG | F_RESTRICT, sizeof(double));
+}
+
+hipError_t cross_pass(gmg_plan *p, const double *w, const double *ec, const double *f,
+                      double *w_next, double *partials, const int *active, double *fc,
+                      bool *fused, int *nparts) {
+  const bool fz = can_fuse_cross(p);
+  *fused = fz;
+  const PassChoice &c = p->ch[0][2];
+  *nparts = pass_geometry(p->dim, p->m[0], 3, pass_variant(p->dim, 3, 0, c.var[3]), c.tz[3], fz)
+                .nblocks;
+  const int flags = F_PROLONG | F_BLACK_FIRST | F_NORM_MID | (fz ? F_RESTRICT : 0);
+  return one_pass_st<double>(p, 0, 2, 3, flags, w, ec, f, w_next, partials, active, PC_CROSS0,
+                             fz ? fc : nullptr);
+}
+
+// Level-0 buffers of the cross-cycle schedule: w_k (the pre-smoothed
+// iterate of cycle k) lives in buffer k & 1.
+double *cross_buf(gmg_plan *p, int k) { return (k & 1) ? p->d.t[0] : p->d.w[0]; }
 
 template <typename T>
 LevelSet<T> &levels_of(gmg_plan *p);
@@ -648,6 +701,35 @@ hipError_t enqueue_vcycle(gmg_plan *p, const T *u0_in, const T *f0, T *u0_out,
   if (e != hipSuccess) return e;
   return smooth_chain<T>(p, 0, nu2, bwd, w0, S.u[1], f0, u0_out, S.t[0], nullptr, active,
                          PC_POST0, nullptr);
+}
+
+// Body k of the cross-cycle solve loop (Algorithm 3 with V(1,1) cycles).
+// Body 0: cycle 1's pre-smoothing of u into w_1 with the norm of u's
+// residual, the stop test, cycle 1's coarse part.  Body k >= 1: the
+// cross-cycle pass (u_k's norm, w_{k+1}, f_1 for cycle k+1), the stop test
+// on u_k, cycle k+1's coarse part.  After the loop the solve forms u_K.
+hipError_t enqueue_cross_body(gmg_plan *p, int k, const double *u, const double *f,
+                              const int *active) {
+  LevelSet<double> &S = p->d;
+  bool fused = false;
+  int nparts = 0;
+  double *wn = cross_buf(p, k + 1);
+  hipError_t e;
+  if (k == 0)
+    e = smooth_chain<double>(p, 0, 1, false, u, nullptr, f, wn, nullptr, p->partials, active,
+                             PC_PRE0, &nparts, S.f[1], &fused);
+  else
+    e = cross_pass(p, cross_buf(p, k), S.u[1], f, wn, p->partials, active, S.f[1], &fused,
+                   &nparts);
+  if (e != hipSuccess) return e;
+  if (fused) {
+    ProfScope ps(p, PC_FIN, 0.0);
+    e = launch_finalize(p->partials, nparts, p->state, p->stream);
+  } else {
+    e = restrict_level<double>(p, 0, wn, f, S.f[1], active, PC_RES0, p->partials, nparts);
+  }
+  if (e != hipSuccess) return e;
+  return run_coarse<double>(p, active);
 }
 
 // ------------------------------------------------------------------ FMG
@@ -889,7 +971,7 @@ Layout make_layout(const gmg_plan &p) {
       const size_t n = npts(dim, p.m[l]) * elem;
       if (l == 0) {
         W[0] = take(cur, n);
-        if (p.need_tmp) Tt[0] = take(cur, n);
+        if (p.need_tmp || p.cross) Tt[0] = take(cur, n);
         if (elem == sizeof(float)) {  // mixed: the FP32 cycle's own RHS and result
           F[0] = take(cur, n);
           U[0] = take(cur, n);
@@ -990,7 +1072,7 @@ PassChoice default_choice(const gmg_plan &p, int l, int role) {
 void default_tiles(gmg_plan &p) {
   p.ch.resize(p.L);
   for (int l = 0; l < p.L; ++l)
-    for (int role = 0; role < 2; ++role) p.ch[l][role] = default_choice(p, l, role);
+    for (int role = 0; role < 3; ++role) p.ch[l][role] = default_choice(p, l, role);
 }
 
 gmg_status validate_cfg(const gmg_config *c) {
@@ -1034,6 +1116,9 @@ gmg_status init_plan_shape(gmg_plan &p, const gmg_config *cfg) {
   // chained passes need a scratch array whenever a level may run more than
   // one pass (any choice of sweeps per pass, so tuning never changes layout)
   p.need_tmp = std::max(cfg->nu1, cfg->nu2) >= 2;
+  p.cross = cfg->precision == GMG_FP64 && cfg->smoother == GMG_SMOOTH_RBGS &&
+            !cfg_variant(p.cfg) && cfg->nu1 == 1 && cfg->nu2 == 1 && p.L >= 2 &&
+            !(cfg->flags & (GMG_POST_FORWARD | GMG_NO_CROSS_CYCLE));
   p.profile = (cfg->flags & GMG_PROFILE) != 0;
   return GMG_OK;
 }
@@ -1294,6 +1379,81 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
   return err;
 }
 
+// The cross-cycle pass (role 2 of level 0) is tuned like the other roles:
+// every three-stage tile and z-chunk, with the restriction folded in where
+// the tile allows it and as a kernel of its own, each timed together with
+// the step that follows it in the solve (the stop test as a kernel of its
+// own, or the restriction whose workgroup 0 runs it).
+hipError_t tune_cross(gmg_plan *p, const double *w, const double *ec, const double *f, double *wn,
+                      double *fc) {
+  const std::string key = tune_key(*p, 0, 2, sizeof(double));
+  auto it = tune_cache().find(key);
+  if (it != tune_cache().end()) {
+    if (choice_ok(p->dim, p->m[0], p->smax_cap, false, it->second)) {
+      p->ch[0][2] = it->second;
+      return hipSuccess;
+    }
+    tune_cache().erase(it);
+  }
+  const int m = p->m[0];
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) return err;
+  const size_t N = npts(p->dim, m);
+  const int reps = N > (1u << 24) ? 2 : (N > (1u << 20) ? 4 : 10);
+  const PassChoice base = p->ch[0][2];
+  PassChoice best[2] = {base, base};
+  double best_us[2] = {1e30, 1e30};
+  const int nv = pass_variant_count(p->dim, 3, 0);
+  for (int v = 0; v < nv && err == hipSuccess; ++v) {
+    const PassTile t = pass_variant(p->dim, 3, 0, v);
+    for (const int tzv : tune_z_chunks(p->dim, m, 3, t)) {
+      if (pass_geometry(p->dim, m, 3, t, tzv).nblocks > kMaxPartials) continue;
+      if (!rb_pass_fits(p->dim, 3, v, F_PROLONG, sizeof(double))) continue;
+      for (int fz = 1; fz >= 0 && err == hipSuccess; --fz) {
+        PassChoice c = base;
+        c.var[3] = v;
+        c.tz[3] = tzv;
+        c.fuse = fz;
+        p->ch[0][2] = c;
+        if (fz && !can_fuse_cross(p)) continue;
+        auto run = [&]() -> hipError_t {
+          bool fused = false;
+          int nparts = 0;
+          hipError_t e2 =
+              cross_pass(p, w, ec, f, wn, p->partials, nullptr, fc, &fused, &nparts);
+          if (e2 != hipSuccess) return e2;
+          if (fused) return launch_finalize(p->partials, nparts, p->state, p->stream);
+          return restrict_level<double>(p, 0, wn, f, fc, nullptr, PC_MISC, p->partials, nparts);
+        };
+        err = run();
+        if (err == hipSuccess) err = hipEventRecord(e0, p->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = run();
+        if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) break;
+        const double us = 1e3 * ms / reps;
+        if (us < best_us[fz]) {
+          best_us[fz] = us;
+          best[fz] = c;
+        }
+      }
+      if (err != hipSuccess) break;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int pick = best_us[1] < 0.97 * best_us[0] ? 1 : 0;
+  p->ch[0][2] = best[pick];
+  if (err == hipSuccess && best_us[pick] < 1e30)
+    tune_cache_store(key, best[pick], 3, best_us[pick]);
+  return err;
+}
+
 // Tune every pass-kernel level of the plan in precision T.  src0/f0: level-0
 // start value and right-hand side (read only); the workspace arrays are used
 // as outputs and scratch.
@@ -1305,7 +1465,8 @@ hipError_t tune_plan(gmg_plan *p, const T *src0, const T *f0, double *partials0)
   p->profile = false;
   // the timed level-0 steps update the solve state like a solve does; give
   // it defined contents (the solve initialises it again afterwards)
-  hipError_t e = partials0 ? launch_state_init(p->state, 1, 1.0, -1.0, p->stream) : hipSuccess;
+  hipError_t e = (partials0 || p->cross) ? launch_state_init(p->state, 1, 1.0, -1.0, p->stream)
+                                         : hipSuccess;
   if (e != hipSuccess) {
     p->profile = prof;
     return e;
@@ -1320,6 +1481,9 @@ hipError_t tune_plan(gmg_plan *p, const T *src0, const T *f0, double *partials0)
     const T *src = l == 0 ? (src0 ? src0 : S.w[0]) : S.w[l];
     T *dst = l == 0 ? (src0 ? S.w[0] : S.u[0]) : S.u[l];
     e = tune_role<T>(p, l, 1, src, S.u[l + 1], f, dst, S.t[l], nullptr, sizeof(T));
+    if (e == hipSuccess && l == 0 && p->cross) {
+      if constexpr (sizeof(T) == 8) e = tune_cross(p, S.w[0], S.u[1], f, S.t[0], S.f[1]);
+    }
   }
   p->profile = prof;
   p->tuned = true;
@@ -1720,6 +1884,7 @@ gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int 
   }
   gmg_plan tmp;
   init_plan_shape(tmp, &c);
+  tmp.cross = false;
   Batch tw;  // the most launches any tile choice can give sizes the table region
   tw.worst = true;
   batch_build(&tmp, &tw, n, dims, levels, nullptr);
@@ -1736,6 +1901,7 @@ gmg_status batch_setup(const gmg_config *cfg, int n, const int *dims, const int 
   if (((uintptr_t)workspace) % kAlign) return GMG_ERR_WORKSPACE;
   gmg_plan *p = new gmg_plan();
   init_plan_shape(*p, &c);
+  p->cross = false;  // batches run the two-pass schedule on every problem
   p->nproblems = n;
   p->stream = (hipStream_t)stream;
   p->ws = (char *)workspace;
@@ -1784,6 +1950,7 @@ hipError_t batch_tune(gmg_plan *p, double *const *u, const double *const *f) {
     c.flags = (c.flags & ~(unsigned)GMG_PROFILE) | GMG_NO_FUSED_RESTRICT;
     gmg_plan v;
     init_plan_shape(v, &c);
+    v.cross = false;
     if (v.B != pr.B) continue;
     v.stream = p->stream;
     v.profile = false;
@@ -2023,6 +2190,8 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
       p->prof_tag = enq;
       if (is_variant(p)) {
         HIPCHK(var_cycle(p, 0, u, f, u, p->partials, act));
+      } else if (p->cross) {
+        HIPCHK(enqueue_cross_body(p, enq, u, f, act));
       } else if (!mixed) {
         HIPCHK(enqueue_vcycle<double>(p, u, f, u, p->partials, act));
       } else {
@@ -2068,7 +2237,16 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
   if (p->profile)
     prune_profile(p, st.iter,
                   is_variant(p) ? (1u << PC_FIN)
-                                : (1u << PC_FIN) | (1u << (mixed ? PC_IR : PC_PRE0)));
+                                : (1u << PC_FIN) | (1u << (mixed ? PC_IR : PC_PRE0)) |
+                                      (1u << PC_CROSS0));
+  if (p->cross && st.iter >= 1) {
+    // u = u_K, the iterate the loop stopped at, from w_K + P e_K (both left
+    // in place: every launch after the stop test returned at once)
+    const int K = st.iter;
+    HIPCHK(smooth_chain<double>(p, 0, 1, true, cross_buf(p, K), p->d.u[1], f, u, nullptr,
+                                nullptr, nullptr, PC_POST0, nullptr));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
   if (mixed && (st.iter % 2 == 1)) {
     // the final iterate x_iter sits in the workspace copy
     HIPCHK(launch_copy(p->x2, u, N0 * sizeof(double), nullptr, p->stream));
@@ -2149,12 +2327,19 @@ gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, in
   const int wj = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
   const int nv = pass_variant_count(p->dim, stages, wj);
   if (variant < 0 || variant >= nv) return GMG_ERR_INVALID_ARG;
-  const int sweeps = wj ? stages : stages / 2;
-  if (sweeps < 1 || sweeps > p->smax_cap) return GMG_ERR_INVALID_ARG;
   const PassTile t = pass_variant(p->dim, stages, wj, variant);
   const int tzv = tz > 0 ? std::min(tz, p->m[level]) : auto_tz(p->dim, p->m[level], stages, t);
   if (pass_geometry(p->dim, p->m[level], stages, t, tzv).nblocks > kMaxPartials)
     return GMG_ERR_INVALID_ARG;
+  if (!wj && stages == 3) {  // the cross-cycle pass of level 0
+    if (level != 0) return GMG_ERR_INVALID_ARG;
+    PassChoice &c = p->ch[0][2];
+    c.var[3] = variant;
+    c.tz[3] = tzv;
+    return GMG_OK;
+  }
+  const int sweeps = wj ? stages : stages / 2;
+  if (sweeps < 1 || sweeps > p->smax_cap) return GMG_ERR_INVALID_ARG;
   for (int role = 0; role < 2; ++role) {
     PassChoice &c = p->ch[level][role];
     c.var[stages] = variant;
@@ -2166,13 +2351,19 @@ gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, in
 
 gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages, int *variant,
                              int *tz) {
-  if (!p || p->batch || level < 0 || level >= p->L || role < 0 || role > 1)
+  if (!p || p->batch || level < 0 || level >= p->L || role < 0 || role > 2)
     return GMG_ERR_INVALID_ARG;
-  const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;
-  if (nu < 1) return GMG_ERR_INVALID_ARG;
-  const PassChoice &c = p->ch[level][role];
-  const int st = stages_of(p, std::min(c.smax, nu));
   const int wj = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+  int st;
+  if (role == 2) {
+    if (level != 0 || !p->cross) return GMG_ERR_INVALID_ARG;
+    st = 3;
+  } else {
+    const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;
+    if (nu < 1) return GMG_ERR_INVALID_ARG;
+    st = stages_of(p, std::min(p->ch[level][role].smax, nu));
+  }
+  const PassChoice &c = p->ch[level][role];
   const PassTile t = pass_variant(p->dim, st, wj, c.var[st]);
   if (stages) *stages = st;
   if (variant) *variant = c.var[st];

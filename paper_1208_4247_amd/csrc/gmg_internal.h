@@ -119,6 +119,8 @@ enum PassFlags : int {
   F_BLACK_FIRST = 8, // red-black order black -> red (backward sweep)
   F_RESTRICT = 16,   // red-black: also form f_c = R (f - A u_out), the residual's
                      // full weighting onto the next coarser grid
+  F_NORM_MID = 32,   // red-black, S = 2q - 1 stages: emit per-workgroup partial
+                     // sums of |f - A u_q|^2, u_q the iterate after stage q
 };
 
 // Device-resident state of one solve (one per problem in batch mode).

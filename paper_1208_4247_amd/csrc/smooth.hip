@@ -151,12 +151,18 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr bool PRO = (FL & F_PROLONG) != 0;
   constexpr bool NORM = (FL & F_NORM_IN) != 0;
   constexpr bool RST = (FL & F_RESTRICT) != 0;
-  static_assert(!(PRO && RST), "a pass prolongs or restricts, not both");
+  // NMID: the norm of the residual of the iterate after stage QN = (S+1)/2
+  // (a pass that ends one sweep -- Algorithm 1's backward post-smoothing --
+  // and starts the next cycle's forward sweep, whose first half-sweep would
+  // repeat the red one just done and is left out)
+  constexpr bool NMID = (FL & F_NORM_MID) != 0;
+  constexpr int QN = (S + 1) / 2;
+  static_assert(!NMID || (S % 2 == 1 && S >= 3 && !NORM), "mid-pass norm: odd S >= 3");
   // halo: S points for the stages; RST adds two, so the result is exact one
   // point past the output tile (the residual there) and the residual one
   // point past it on the high side (full weighting of the edge coarse points)
-  constexpr int HP = S / 2 + (RST ? 1 : 0);     // halo in pairs
-  constexpr int HY = S + (RST ? 2 : 0);         // halo in rows (3D)
+  constexpr int HP = (S + 1) / 2 + (RST ? 1 : 0);  // halo in pairs
+  constexpr int HY = 2 * HP;                       // halo in rows (3D)
   constexpr int TXP = EXP - 2 * HP;             // output pairs per row
   constexpr int TY = DIM == 3 ? EY - 2 * HY : 1;
   static_assert(TXP > 0 && TY > 0 && (DIM == 2 || TY % 2 == 0), "tile too small");
@@ -531,7 +537,15 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         nb += W[s - 1][i][2];  // marching axis - 1
         nb += W[s - 1][i][0];  // marching axis + 1
         const bool in = zin && (isP(s) ? kP[i] : kQ[i]);
-        const T v = in ? fma(h2, isP(s) ? fP[s][i] : fQ[s][i], nb) * inv2d : T(0);
+        const T fv = isP(s) ? fP[s][i] : fQ[s][i];
+        const T v = in ? fma(h2, fv, nb) * inv2d : T(0);
+        if (NMID && s == QN) {
+          // the updated colour's residual after stage QN, from the same
+          // neighbour sum: plane t - QN
+          const double r = double(fv) - (double(T(2 * DIM) * v) - double(nb)) * a.inv_h2;
+          const bool use = zs >= Z0 && zs < Z1 && (isP(s) ? nP[i] : nQ[i]);
+          acc += use ? r * r : 0.0;
+        }
         if (s < S) {
           W[s][i][2] = W[s][i][1];
           W[s][i][1] = W[s][i][0];
@@ -539,6 +553,31 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         } else {
           newS[i] = v;
         }
+      }
+    }
+    // ---- NMID: the other colour's residual after stage QN on plane
+    // t - QN - 1: its value from stage QN - 1, its neighbours (all of the
+    // colour stage QN updated) from stage QN's window and published plane;
+    // neighbour order x-1, x+1, y-1, y+1, z-1, z+1 as in the stages
+    if (NMID) {
+      const int zb = t - QN - 1;
+      const bool bin = zb >= Z0 && zb < Z1;
+      const T *Lq = Lprev + QN * PL;  // stage QN's plane zb (published at step t-1)
+      constexpr bool EP = isP(QN - 1);     // the colour of stage QN - 1 is element P
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        T nb = W[QN][i][1] + Lq[EP ? lP[i] : lQ[i]];
+        if (DIM == 3) {
+          nb += Lq[lu[i]];
+          nb += Lq[ld[i]];
+        }
+        nb += W[QN][i][2];
+        nb += W[QN][i][0];
+        const T fv = EP ? fP[QN + 1][i] : fQ[QN + 1][i];
+        const double r =
+            double(fv) - (double(T(2 * DIM) * W[QN - 1][i][2]) - double(nb)) * a.inv_h2;
+        const bool use = bin && (EP ? nP[i] : nQ[i]);
+        acc += use ? r * r : 0.0;
       }
     }
     // ---- output plane t-S: last stage's colour from newS, the other from S-1
@@ -617,7 +656,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     step(t, IntC<0>());
     step(t + 1, IntC<1>());
   }
-  if (NORM) block_sum_store<NT>(acc, gbl(a.partials));
+  if (NORM || NMID) block_sum_store<NT>(acc, gbl(a.partials));
 }
 
 // ------------------------------------------------------------------------
@@ -945,6 +984,12 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
 #define GMG_RB3_S2(X) \
   X(3, 2, 66, 30, 1024) X(3, 2, 34, 20, 256) X(3, 2, 66, 14, 512) X(3, 2, 34, 30, 1024)
 #define GMG_RB3_S4(X) X(3, 4, 36, 28, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512) X(3, 4, 36, 24, 896)
+// Three stages (black, red, black): the pass that ends one cycle's backward
+// V(1,1) post-smoothing and starts the next cycle's forward sweep.
+#define GMG_RB3_S3(X) \
+  X(3, 3, 34, 30, 1024) X(3, 3, 36, 28, 1024) X(3, 3, 66, 30, 1024) X(3, 3, 34, 30, 512) \
+  X(3, 3, 66, 14, 512)
+#define GMG_RB2_S3(X) X(2, 3, 64, 1, 64) X(2, 3, 128, 1, 128)
 #define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 #define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
 #define GMG_WJ3_S1(X) X(3, 1, 34, 30, 1024) X(3, 1, 66, 14, 1024) X(3, 1, 34, 14, 512)
@@ -958,7 +1003,7 @@ struct TileRow {
 };
 #define GMG_ROW(D, S, E, Y, N) {D, S, E, Y, N},
 const TileRow kRbTiles[] = {GMG_RB3_S2(GMG_ROW) GMG_RB3_S4(GMG_ROW) GMG_RB2_S2(GMG_ROW)
-                                GMG_RB2_S4(GMG_ROW)};
+                                GMG_RB2_S4(GMG_ROW) GMG_RB3_S3(GMG_ROW) GMG_RB2_S3(GMG_ROW)};
 const TileRow kWjTiles[] = {GMG_WJ3_S1(GMG_ROW) GMG_WJ3_S2(GMG_ROW) GMG_WJ2_S1(GMG_ROW)
                                 GMG_WJ2_S2(GMG_ROW)};
 #undef GMG_ROW
@@ -1097,6 +1142,18 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
   }
 }  // namespace
 
+// The three-stage pass runs in two forms only: interpolated correction in,
+// mid-pass norm, with or without the folded restriction (FP64).
+#define GMG_CROSS_SWITCH(RUN, T, D, S, E, Y, N)                                        \
+  switch (flags) {                                                                  \
+    case F_PROLONG | F_BLACK_FIRST | F_NORM_MID:                                    \
+      return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST | F_NORM_MID>(a, st, tbl, nent); \
+    case F_PROLONG | F_BLACK_FIRST | F_NORM_MID | F_RESTRICT:                       \
+      return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST | F_NORM_MID | F_RESTRICT>(   \
+          a, st, tbl, nent);                                                        \
+    default: return hipErrorInvalidValue;                                           \
+  }
+
 template <typename T>
 hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<T> a,
                           hipStream_t st, const PassArgs<T> *tbl, int nent) {
@@ -1108,6 +1165,14 @@ hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<
   }
   GMG_RB3_S2(GMG_TRY) GMG_RB3_S4(GMG_TRY) GMG_RB2_S2(GMG_TRY) GMG_RB2_S4(GMG_TRY)
 #undef GMG_TRY
+  if constexpr (sizeof(T) == 8) {
+#define GMG_TRY(D, S, E, Y, N)                                       \
+  if (dim == D && stages == S && t.exp_ == E && t.ey == Y && t.nt == N) { \
+    GMG_CROSS_SWITCH(run_rb, T, D, S, E, Y, N)                        \
+  }
+    GMG_RB3_S3(GMG_TRY) GMG_RB2_S3(GMG_TRY)
+#undef GMG_TRY
+  }
   return hipErrorInvalidValue;
 }
 

@@ -150,7 +150,7 @@ class Plan:
 
     PROFILE_CLASSES = ["smooth_pre_l0", "smooth_post_l0", "resid_restrict_l0", "smooth_pre_coarse",
                        "smooth_post_coarse", "resid_restrict_coarse", "bottom", "finalize",
-                       "ir_step", "misc"]
+                       "ir_step", "misc", "smooth_cross_l0"]
 
     def profile_only(self, names):
         mask = 0

@@ -80,11 +80,15 @@ def test_workspace_size_model(capi):
     stored, and the workspace holds the coarse u, w (pre-smoothed), f
     (3 * N0 / (2^d - 1)) plus the level-0 pre-smoothed copy w0 (N0); with
     nu >= 2 every level also carries one scratch array for chained passes
-    (+N0 + N0 / (2^d - 1))."""
+    (+N0 + N0 / (2^d - 1)).  FP64 V(1,1) plans run the cross-cycle schedule,
+    whose pre-smoothed iterates alternate between two level-0 arrays (+N0);
+    with GMG_NO_CROSS_CYCLE they keep one."""
     for d, L in [(2, 10), (3, 8)]:
-        for nu, arrays0, arrays_c in [(1, 1, 3), (2, 2, 4)]:
+        for nu, flags, arrays0, arrays_c in [(1, capi.GMG_NO_CROSS_CYCLE, 1, 3), (1, 0, 2, 3),
+                                              (2, 0, 2, 4)]:
             c = capi.config_default(d, L)
             c.nu1 = c.nu2 = nu
+            c.flags = flags
             s, n = capi.workspace_bytes(c)
             assert s == 0
             N0 = ((1 << L) - 1) ** d
@@ -147,7 +151,7 @@ def _tile_table_hash():
             h ^= (v >> (8 * b)) & 0xFF
             h = (h * 16777619) & 0xFFFFFFFF
 
-    for name in ("GMG_RB3_S2", "GMG_RB3_S4", "GMG_RB2_S2", "GMG_RB2_S4"):
+    for name in ("GMG_RB3_S2", "GMG_RB3_S4", "GMG_RB2_S2", "GMG_RB2_S4", "GMG_RB3_S3", "GMG_RB2_S3"):
         for r in rows(name):
             for v in r:
                 mix(v)
