@@ -209,6 +209,15 @@ int gmg_tile_variant_count(int dim, gmg_smoother smoother, int stages);
  * this bitwise); only speed does.  Host only. */
 gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, int tz);
 
+/* Order in which the workgroups of a pass with `stages` stages on level
+ * `level` take their tiles: strips `strip` tiles wide (filled row by row),
+ * or whole rows of tiles (strip = 0, the default).  Each XCD runs a
+ * contiguous run of tiles at a time, so narrow strips make that run a
+ * compact block whose halos its L2 shares.  Only speed depends on it (the
+ * autotuner picks it).  Host only; GMG_ERR_INVALID_ARG for a bad level,
+ * stage count or strip. */
+gmg_status gmg_plan_set_tile_order(gmg_plan *p, int level, int stages, int strip);
+
 /* The tile choice in use (after autotuning, if any) for the first pass of
  * the pre- (role 0) or post-smoothing (role 1) on level `level` of problem 0:
  * its stage count, tile index and z-chunk (resolved, > 0).  Role 2: the

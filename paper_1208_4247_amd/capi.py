@@ -47,7 +47,7 @@ EXPORTED = [
     "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
     "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg", "gmg_dst_setup", "gmg_dst_solve",
-    "gmg_dst_destroy", "gmg_tune_cache_check",
+    "gmg_dst_destroy", "gmg_tune_cache_check", "gmg_plan_set_tile_order",
 ]
 
 
@@ -124,6 +124,7 @@ def lib():
     ip = ctypes.POINTER(ctypes.c_int)
     L.gmg_plan_get_tile.argtypes = [vp, i, i, ip, ip, ip]
     L.gmg_tune_cache_check.argtypes = [ctypes.c_char_p, ip, ip]
+    L.gmg_plan_set_tile_order.argtypes = [vp, i, i, i]
     for name in EXPORTED:
         if name not in ("gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
                         "gmg_profile_count", "gmg_tile_variant_count"):

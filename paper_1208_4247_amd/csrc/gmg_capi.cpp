@@ -73,6 +73,7 @@ struct PassChoice {
   int smax = 2;
   std::array<int, 5> var{{0, 0, 0, 0, 0}};
   std::array<int, 5> tz{{0, 0, 0, 0, 0}};
+  std::array<int, 5> sw{{0, 0, 0, 0, 0}};  // tile order: strip width in tiles (0: rows)
   int fuse = 1;  // pre-smoothing: fold the residual + restriction into the last pass
 };
 
@@ -333,6 +334,7 @@ hipError_t one_pass_st(gmg_plan *p, int level, int role, int st, int flags, cons
   a.nty = g.nty;
   a.tz = g.tz;
   a.nblocks = g.nblocks;
+  a.sw = c.sw[st];
   const double h = 1.0 / double(m + 1);
   a.h2 = h * h;
   a.inv_h2 = 1.0 / (h * h);
@@ -1203,7 +1205,7 @@ bool choice_ok(int dim, int m, int smax_cap, bool wj, const PassChoice &c) {
   for (int st = 1; st <= 4; ++st) {
     const int nv = pass_variant_count(dim, st, wj ? 1 : 0);
     if (nv == 0) continue;
-    if (c.var[st] < 0 || c.var[st] >= nv || c.tz[st] < 0) return false;
+    if (c.var[st] < 0 || c.var[st] >= nv || c.tz[st] < 0 || c.sw[st] < 0) return false;
     const PassTile t = pass_variant(dim, st, wj ? 1 : 0, c.var[st]);
     if (pass_geometry(dim, m, st, t, c.tz[st]).nblocks > kMaxPartials) return false;
   }
@@ -1214,16 +1216,17 @@ bool choice_ok(int dim, int m, int smax_cap, bool wj, const PassChoice &c) {
 // index, z-chunk, fold flag.  False for a line that does not parse.
 bool parse_cache_line(const char *line, std::string &key, PassChoice &c, int &st) {
   char kb[256];
-  int v = 0, tz = 0, fz = 1;
+  int v = 0, tz = 0, fz = 1, sw = 0;
   st = 0;
   if (std::sscanf(line,
                   "{\"key\": \"%255[^\"]\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, "
-                  "\"fuse\": %d",
-                  kb, &c.smax, &st, &v, &tz, &fz) != 6 || st < 1 || st > 4)
+                  "\"fuse\": %d, \"sw\": %d",
+                  kb, &c.smax, &st, &v, &tz, &fz, &sw) < 6 || st < 1 || st > 4)
     return false;
   key = kb;
   c.var[st] = v;
   c.tz[st] = tz;
+  c.sw[st] = sw;
   c.fuse = fz;
   return true;
 }
@@ -1266,6 +1269,7 @@ void tune_cache_load() {
     d.smax = c.smax;
     d.var[st] = c.var[st];
     d.tz[st] = c.tz[st];
+    d.sw[st] = c.sw[st];
     d.fuse = c.fuse;
   }
   std::fclose(fh);
@@ -1279,9 +1283,78 @@ void tune_cache_store(const std::string &key, const PassChoice &c, int st, doubl
   if (!fh) return;
   std::fprintf(fh,
                "{\"key\": \"%s\", \"smax\": %d, \"stages\": %d, \"var\": %d, \"tz\": %d, "
-               "\"fuse\": %d, \"us\": %.2f}\n",
-               key.c_str(), c.smax, st, c.var[st], c.tz[st], c.fuse, us);
+               "\"fuse\": %d, \"sw\": %d, \"us\": %.2f}\n",
+               key.c_str(), c.smax, st, c.var[st], c.tz[st], c.fuse, c.sw[st], us);
   std::fclose(fh);
+}
+
+// Mean time in microseconds of reps launches of run() after one warm-up.
+template <typename F>
+hipError_t time_runs(gmg_plan *p, hipEvent_t e0, hipEvent_t e1, int reps, F &&run, double &us) {
+  hipError_t err = run();
+  if (err == hipSuccess) err = hipEventRecord(e0, p->stream);
+  for (int r = 0; r < reps && err == hipSuccess; ++r) err = run();
+  if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  us = 1e3 * ms / reps;
+  return err;
+}
+
+// One timed candidate of the autotuner.
+struct Cand {
+  PassChoice c;
+  int st = 0;
+  double us = 1e30;
+};
+
+// Sweeps time each candidate over a few launches only; the fastest few of a
+// sweep are timed again over three times as many launches (in the same
+// order), so timing noise does not decide between near-equal candidates.
+// Returns the fastest of them; run() launches with p->ch[l][role].
+template <typename F>
+hipError_t refine_best(gmg_plan *p, int l, int role, std::vector<Cand> &cands, hipEvent_t e0,
+                       hipEvent_t e1, int reps, F &&run, Cand &best) {
+  std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.us < b.us; });
+  if (cands.size() > 4) cands.resize(4);
+  best = Cand();
+  for (Cand &c : cands) {
+    p->ch[l][role] = c.c;
+    double us = 0.0;
+    hipError_t err = time_runs(p, e0, e1, 3 * reps, run, us);
+    if (err != hipSuccess) return err;
+    c.us = us;
+    if (us < best.us) best = c;
+  }
+  return hipSuccess;
+}
+
+// Tile order of the chosen candidate (3D): strips 1..8 tiles wide instead of
+// whole rows of tiles; a width is kept when it is at least 2% faster.  run()
+// launches with p->ch[l][role].
+template <typename F>
+hipError_t tune_strips(gmg_plan *p, int l, int role, int st, bool rst, PassChoice &c, double &us,
+                       hipEvent_t e0, hipEvent_t e1, int reps, F &&run) {
+  if (p->dim != 3 || us >= 1e30) return hipSuccess;
+  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
+  const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, c.var[st]);
+  const int ntx = pass_geometry(p->dim, p->m[l], st, t, c.tz[st], rst).ntx;
+  for (const int w : {1, 2, 3, 4, 6, 8}) {
+    if (w >= ntx) break;
+    PassChoice cs = c;
+    cs.sw[st] = w;
+    p->ch[l][role] = cs;
+    double u = 0.0;
+    hipError_t err = time_runs(p, e0, e1, reps, run, u);
+    if (err != hipSuccess) return err;
+    if (u < 0.98 * us) {
+      us = u;
+      c = cs;
+    }
+  }
+  p->ch[l][role] = c;
+  return hipSuccess;
 }
 
 // fc (pre-smoothing): the next coarser level's right-hand side.  Each
@@ -1312,10 +1385,21 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
   const size_t N = npts(p->dim, m);
   const int reps = N > (1u << 24) ? 2 : (N > (1u << 20) ? 4 : 10);
   const PassChoice base = p->ch[l][role];
-  // the best candidate with and without the folded restriction
-  PassChoice best[2] = {base, base};
-  double best_us[2] = {1e30, 1e30};
-  int best_st[2] = {stages_of(p, std::min(base.smax, nu)), stages_of(p, std::min(base.smax, nu))};
+  // exactly the cycle's launches for this step (with p->ch[l][role]): with a
+  // folded restriction the solve's stop test follows as a kernel of its own,
+  // otherwise it runs in workgroup 0 of the restriction
+  auto run = [&]() -> hipError_t {
+    bool fused = false;
+    int nparts = 0;
+    hipError_t e2 = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials, nullptr,
+                                    PC_MISC, &nparts, fc, &fused);
+    if (e2 != hipSuccess || !fc) return e2;
+    if (fused)
+      return partials ? launch_finalize(partials, nparts, p->state, p->stream) : hipSuccess;
+    return restrict_level<T>(p, l, dst, f, fc, nullptr, PC_MISC, partials, nparts);
+  };
+  // candidates with and without the folded restriction
+  std::vector<Cand> cands[2];
   for (int sm = 1; sm <= std::min(p->smax_cap, nu); ++sm) {
     const int st = stages_of(p, sm);
     const int nv = pass_variant_count(p->dim, st, wj ? 1 : 0);
@@ -1332,35 +1416,10 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
           c.fuse = fz;
           p->ch[l][role] = c;
           if (fz && !can_fuse_restrict(p, l, nu, elem)) continue;
-          // exactly the cycle's launches for this step: with a folded
-          // restriction the solve's stop test follows as a kernel of its own,
-          // otherwise it runs in workgroup 0 of the restriction
-          auto run = [&]() -> hipError_t {
-            bool fused = false;
-            int nparts = 0;
-            hipError_t e2 = smooth_chain<T>(p, l, nu, role == 1, src, ec, f, dst, tmp, partials,
-                                            nullptr, PC_MISC, &nparts, fc, &fused);
-            if (e2 != hipSuccess || !fc) return e2;
-            if (fused)
-              return partials ? launch_finalize(partials, nparts, p->state, p->stream)
-                              : hipSuccess;
-            return restrict_level<T>(p, l, dst, f, fc, nullptr, PC_MISC, partials, nparts);
-          };
-          err = run();
+          double us = 0.0;
+          err = time_runs(p, e0, e1, reps, run, us);
           if (err != hipSuccess) break;
-          err = hipEventRecord(e0, p->stream);
-          for (int r = 0; r < reps && err == hipSuccess; ++r) err = run();
-          if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
-          if (err == hipSuccess) err = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-          if (err != hipSuccess) break;
-          const double us = 1e3 * ms / reps;
-          if (us < best_us[fz]) {
-            best_us[fz] = us;
-            best[fz] = c;
-            best_st[fz] = st;
-          }
+          cands[fz].push_back(Cand{c, st, us});
         }
         if (err != hipSuccess) break;
       }
@@ -1368,13 +1427,28 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
     }
     if (err != hipSuccess) break;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  PassChoice best[2] = {base, base};
+  double best_us[2] = {1e30, 1e30};
+  int best_st[2] = {stages_of(p, std::min(base.smax, nu)), stages_of(p, std::min(base.smax, nu))};
+  for (int fz = 0; fz < 2 && err == hipSuccess; ++fz) {
+    Cand b;
+    err = refine_best(p, l, role, cands[fz], e0, e1, reps, run, b);
+    if (b.us < 1e30) {
+      best[fz] = b.c;
+      best_us[fz] = b.us;
+      best_st[fz] = b.st;
+    }
+  }
   // the folded restriction enlarges the pass's halo and LDS: keep the plain
   // pass and the separate restriction unless folding is clearly faster
   // (timing noise of a few percent would otherwise flip the choice)
   const int pick = best_us[1] < 0.97 * best_us[0] ? 1 : 0;
   p->ch[l][role] = best[pick];
+  if (err == hipSuccess)
+    err = tune_strips(p, l, role, best_st[pick], pick == 1, best[pick], best_us[pick], e0, e1,
+                      3 * reps, run);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (err == hipSuccess) tune_cache_store(key, best[pick], best_st[pick], best_us[pick]);
   return err;
 }
@@ -1404,8 +1478,16 @@ hipError_t tune_cross(gmg_plan *p, const double *w, const double *ec, const doub
   const size_t N = npts(p->dim, m);
   const int reps = N > (1u << 24) ? 2 : (N > (1u << 20) ? 4 : 10);
   const PassChoice base = p->ch[0][2];
-  PassChoice best[2] = {base, base};
-  double best_us[2] = {1e30, 1e30};
+  // the pass and the step after it in the solve, with p->ch[0][2]
+  auto run = [&]() -> hipError_t {
+    bool fused = false;
+    int nparts = 0;
+    hipError_t e2 = cross_pass(p, w, ec, f, wn, p->partials, nullptr, fc, &fused, &nparts);
+    if (e2 != hipSuccess) return e2;
+    if (fused) return launch_finalize(p->partials, nparts, p->state, p->stream);
+    return restrict_level<double>(p, 0, wn, f, fc, nullptr, PC_MISC, p->partials, nparts);
+  };
+  std::vector<Cand> cands[2];
   const int nv = pass_variant_count(p->dim, 3, 0);
   for (int v = 0; v < nv && err == hipSuccess; ++v) {
     const PassTile t = pass_variant(p->dim, 3, 0, v);
@@ -1419,36 +1501,30 @@ hipError_t tune_cross(gmg_plan *p, const double *w, const double *ec, const doub
         c.fuse = fz;
         p->ch[0][2] = c;
         if (fz && !can_fuse_cross(p)) continue;
-        auto run = [&]() -> hipError_t {
-          bool fused = false;
-          int nparts = 0;
-          hipError_t e2 =
-              cross_pass(p, w, ec, f, wn, p->partials, nullptr, fc, &fused, &nparts);
-          if (e2 != hipSuccess) return e2;
-          if (fused) return launch_finalize(p->partials, nparts, p->state, p->stream);
-          return restrict_level<double>(p, 0, wn, f, fc, nullptr, PC_MISC, p->partials, nparts);
-        };
-        err = run();
-        if (err == hipSuccess) err = hipEventRecord(e0, p->stream);
-        for (int r = 0; r < reps && err == hipSuccess; ++r) err = run();
-        if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        double us = 0.0;
+        err = time_runs(p, e0, e1, reps, run, us);
         if (err != hipSuccess) break;
-        const double us = 1e3 * ms / reps;
-        if (us < best_us[fz]) {
-          best_us[fz] = us;
-          best[fz] = c;
-        }
+        cands[fz].push_back(Cand{c, 3, us});
       }
       if (err != hipSuccess) break;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  PassChoice best[2] = {base, base};
+  double best_us[2] = {1e30, 1e30};
+  for (int fz = 0; fz < 2 && err == hipSuccess; ++fz) {
+    Cand b;
+    err = refine_best(p, 0, 2, cands[fz], e0, e1, reps, run, b);
+    if (b.us < 1e30) {
+      best[fz] = b.c;
+      best_us[fz] = b.us;
+    }
+  }
   const int pick = best_us[1] < 0.97 * best_us[0] ? 1 : 0;
   p->ch[0][2] = best[pick];
+  if (err == hipSuccess)
+    err = tune_strips(p, 0, 2, 3, pick == 1, best[pick], best_us[pick], e0, e1, 3 * reps, run);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (err == hipSuccess && best_us[pick] < 1e30)
     tune_cache_store(key, best[pick], 3, best_us[pick]);
   return err;
@@ -1981,6 +2057,38 @@ hipError_t batch_tune(gmg_plan *p, double *const *u, const double *const *f) {
 
 }  // namespace
 
+namespace {
+// Binds a single-problem plan to its workspace: the solve state, norm
+// partials and level arrays carved as the layout says, default tile choices,
+// and the host copy of the solve state (hstate: room for the state and one
+// double after it).
+void bind_single(gmg_plan &p, const gmg_config &c, const Layout &Y, void *workspace,
+                 hipStream_t stream, SolveState *hstate) {
+  init_plan_shape(p, &c);
+  p.nproblems = 1;
+  p.stream = stream;
+  p.ws = (char *)workspace;
+  p.ws_bytes = Y.total;
+  p.state = reinterpret_cast<SolveState *>(p.ws + Y.off_state);
+  p.partials = reinterpret_cast<double *>(p.ws + Y.off_partials);
+  p.scalar = reinterpret_cast<double *>(p.ws + Y.off_scalar);
+  if (c.precision == GMG_MIXED_FP32_IR) {
+    p.x2 = reinterpret_cast<double *>(p.ws + Y.off_x2);
+    bind<float>(p.s, p.ws, Y.fs, Y.ws, Y.us, Y.ts);
+    bind<double>(p.d, p.ws, Y.f, Y.w, Y.u, Y.t);
+  } else {
+    bind<double>(p.d, p.ws, Y.f, Y.w, Y.u, Y.t);
+    std::vector<size_t> none(p.L, (size_t)-1);
+    bind<float>(p.s, p.ws, none, none, none, none);
+  }
+  default_tiles(p);
+  p.prof.resize(PC_COUNT);
+  for (int i = 0; i < PC_COUNT; ++i) p.prof[i].name = kProfNames[i];
+  p.hstate = hstate;
+  p.hscalar = reinterpret_cast<double *>(reinterpret_cast<char *>(hstate) + sizeof(SolveState));
+}
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -2036,32 +2144,12 @@ gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, cons
   if (*ws_bytes < Y.total) return GMG_ERR_WORKSPACE;
   if (((uintptr_t)workspace) % kAlign) return GMG_ERR_WORKSPACE;
   gmg_plan *p = new gmg_plan();
-  init_plan_shape(*p, &c);
-  p->nproblems = 1;
-  p->stream = (hipStream_t)stream;
-  p->ws = (char *)workspace;
-  p->ws_bytes = Y.total;
-  p->state = reinterpret_cast<SolveState *>(p->ws + Y.off_state);
-  p->partials = reinterpret_cast<double *>(p->ws + Y.off_partials);
-  p->scalar = reinterpret_cast<double *>(p->ws + Y.off_scalar);
-  if (c.precision == GMG_MIXED_FP32_IR) {
-    p->x2 = reinterpret_cast<double *>(p->ws + Y.off_x2);
-    bind<float>(p->s, p->ws, Y.fs, Y.ws, Y.us, Y.ts);
-    bind<double>(p->d, p->ws, Y.f, Y.w, Y.u, Y.t);
-  } else {
-    bind<double>(p->d, p->ws, Y.f, Y.w, Y.u, Y.t);
-    std::vector<size_t> none(p->L, (size_t)-1);
-    bind<float>(p->s, p->ws, none, none, none, none);
-  }
-  default_tiles(*p);
-  p->prof.resize(PC_COUNT);
-  for (int i = 0; i < PC_COUNT; ++i) p->prof[i].name = kProfNames[i];
-  if (hipHostMalloc((void **)&p->hstate, sizeof(SolveState) + 64, hipHostMallocDefault) !=
-      hipSuccess) {
+  SolveState *hs = nullptr;
+  if (hipHostMalloc((void **)&hs, sizeof(SolveState) + 64, hipHostMallocDefault) != hipSuccess) {
     delete p;
     return GMG_ERR_HIP;
   }
-  p->hscalar = reinterpret_cast<double *>(reinterpret_cast<char *>(p->hstate) + sizeof(SolveState));
+  bind_single(*p, c, Y, workspace, (hipStream_t)stream, hs);
   *out = p;
   return GMG_OK;
 }
@@ -2346,6 +2434,20 @@ gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, in
     c.tz[stages] = tzv;
     c.smax = sweeps;
   }
+  return GMG_OK;
+}
+
+gmg_status gmg_plan_set_tile_order(gmg_plan *p, int level, int stages, int strip) {
+  if (!p || p->batch || level < 0 || level >= p->L || stages < 1 || stages > 4 || strip < 0)
+    return GMG_ERR_INVALID_ARG;
+  const int wj = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
+  if (pass_variant_count(p->dim, stages, wj) == 0) return GMG_ERR_INVALID_ARG;
+  if (!wj && stages == 3) {
+    if (level != 0) return GMG_ERR_INVALID_ARG;
+    p->ch[0][2].sw[3] = strip;
+    return GMG_OK;
+  }
+  for (int role = 0; role < 2; ++role) p->ch[level][role].sw[stages] = strip;
   return GMG_OK;
 }
 

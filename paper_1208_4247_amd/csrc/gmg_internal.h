@@ -147,6 +147,7 @@ struct PassArgs {
   int m, mc;            // fine / coarse interior side
   int ntx, nty, tz;     // tiles along x, y; output planes per z-chunk
   int nblocks;          // grid size (for the XCD remap)
+  int sw;               // tile order: strips of sw tiles along x (0: whole rows)
   double h2;            // h^2 of the fine level
   double inv_h2;
   double omega;         // weighted Jacobi

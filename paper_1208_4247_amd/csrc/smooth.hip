@@ -55,6 +55,32 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return xcd * per + min(xcd, rem) + loc;
 }
 
+// Tile (tx, ty) and z-chunk tz of tile index j.  Chunks are outermost; a
+// chunk's tiles run down vertical strips sw tiles wide (row by row inside a
+// strip; sw = 0 or >= ntx: whole rows).  With the XCD remap each XCD takes
+// a contiguous run of indices, so the workgroups one XCD runs at a time
+// cover a compact block of neighbouring tiles rather than a thin band of
+// rows, and more of their halos are shared in that XCD's L2.
+template <int DIM>
+__device__ __forceinline__ void tile_coords(int j, int ntx, int nty, int sw, int &tx, int &ty,
+                                            int &tz) {
+  if (DIM == 2) {
+    tx = j % ntx;
+    ty = 0;
+    tz = j / ntx;
+    return;
+  }
+  const int per = ntx * nty;
+  tz = j / per;
+  const int r = j - tz * per;
+  const int bw = (sw > 0 && sw < ntx) ? sw : ntx;
+  const int s = r / (bw * nty);
+  const int q = r - s * bw * nty;
+  const int w = min(bw, ntx - s * bw);  // the last strip may be narrower
+  ty = q / w;
+  tx = s * bw + (q - ty * w);
+}
+
 template <int NT>
 __device__ __forceinline__ void block_sum_store(double acc, GMG_GLOBAL double *out) {
   __shared__ double red[NT / 64];
@@ -185,11 +211,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   T *cring = lds + 2 * NB * PL + (RST ? 8 * PL : 0);
 
   const int m = a.m;
-  const int bid = xcd_remap(blockIdx.x, a.nblocks);
-  const int tx = bid % a.ntx;
-  const int rest = bid / a.ntx;
-  const int ty = DIM == 3 ? rest % a.nty : 0;
-  const int tzc = DIM == 3 ? rest / a.nty : rest;
+  int tx, ty, tzc;
+  tile_coords<DIM>(xcd_remap(blockIdx.x, a.nblocks), a.ntx, a.nty, a.sw, tx, ty, tzc);
   const int X0 = tx * 2 * TXP;
   const int Y0 = ty * TY;
   const int Z0 = tzc * a.tz;
@@ -690,11 +713,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
   T *cring = lds + 4 * S * PL;
 
   const int m = a.m;
-  const int bid = xcd_remap(blockIdx.x, a.nblocks);
-  const int tx = bid % a.ntx;
-  const int rest = bid / a.ntx;
-  const int ty = DIM == 3 ? rest % a.nty : 0;
-  const int tzc = DIM == 3 ? rest / a.nty : rest;
+  int tx, ty, tzc;
+  tile_coords<DIM>(xcd_remap(blockIdx.x, a.nblocks), a.ntx, a.nty, a.sw, tx, ty, tzc);
   const int X0 = tx * 2 * TXP;
   const int Y0 = ty * TY;
   const int Z0 = tzc * a.tz;

@@ -136,6 +136,47 @@ def traffic_table(dim, m):
     plan.close()
 
 
+def cross_sweep(dim, m, strips=(0, 1, 2, 3, 4, 6, 8), variants=None, tzs=None):
+    """The cross-cycle pass of FP64 red-black V(1,1) solves (three stages,
+    interpolated correction in, mid-pass norm, with and without the folded
+    restriction) for every tile, z-chunk and tile order, timed inside short
+    solves (three cross passes each) by the plan's dispatch events: one JSON
+    row per candidate with the mean pass time and the algorithmic rate."""
+    from . import capi
+
+    L = (m + 1).bit_length() - 1
+    g = torch.Generator(device="cuda").manual_seed(0)
+    f = torch.rand((m,) * dim, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    u = torch.zeros_like(f)
+    for fold in (True, False):
+        flags = capi.GMG_PROFILE | (0 if fold else capi.GMG_NO_FUSED_RESTRICT)
+        plan = Plan(dim, L, nu1=1, nu2=1, flags=flags)
+        plan.profile_only(["smooth_cross_l0", "resid_restrict_l0"])
+        for v in range(plan.tile_variants(3)):
+            if variants is not None and v not in variants:
+                continue
+            for tz in (tzs or tuner_tz(m)):
+                try:
+                    plan.set_tile(0, 3, v, tz)
+                except capi.GmgError:
+                    continue
+                for sw in strips:
+                    plan.set_tile_order(0, 3, sw)
+                    plan.profile_reset()
+                    u.zero_()
+                    plan.solve(u, f, rtol=1e-30, maxit=4)
+                    pr = plan.profile()
+                    c, r = pr["smooth_cross_l0"], pr["resid_restrict_l0"]
+                    us = 1e3 * c["ms"] / max(c["launches"], 1)
+                    rus = 1e3 * r["ms"] / max(r["launches"], 1) if r["launches"] else 0.0
+                    print(json.dumps(dict(kernel="cross_pass", fold=fold, variant=v,
+                                          tz=plan.get_tile(0, 2)[2], strip=sw, us=us,
+                                          restrict_us=rus, step_us=us + rus,
+                                          gbs=c["bytes"] / max(c["ms"], 1e-9) / 1e6)),
+                          flush=True)
+        plan.close()
+
+
 def copy_calibration(mib, reps=20):
     """A plain device copy of known size (torch's copy kernel): the yardstick
     that converts the HBM byte counters of a profiler into bytes.  Also
@@ -171,10 +212,18 @@ def main():
     ap.add_argument("--variants", type=int, nargs="+", default=None)
     ap.add_argument("--kinds", nargs="+", default=["plain", "zero", "prolong", "prolong_bwd"])
     ap.add_argument("--no-transfers", action="store_true")
+    ap.add_argument("--cross-sweep", action="store_true",
+                    help="time the cross-cycle pass over tiles, z-chunks and tile orders")
+    ap.add_argument("--strips", type=int, nargs="+", default=[0, 1, 2, 3, 4, 6, 8])
     ap.add_argument("--traffic-table", action="store_true",
                     help="launch every autotuner candidate of the level-0 passes twice "
                     "(for a counter profiler)")
     a = ap.parse_args()
+    if a.cross_sweep:
+        for m in a.m:
+            cross_sweep(a.dim, m, tuple(a.strips), a.variants,
+                        None if a.tz == [0] else a.tz)
+        return
     if a.traffic_table:
         for m in a.m:
             traffic_table(a.dim, m)

@@ -97,6 +97,10 @@ class Plan:
         capi.check(capi.lib().gmg_plan_set_tile(self._plan, int(level), int(stages), int(variant),
                                                 int(tz)), "gmg_plan_set_tile")
 
+    def set_tile_order(self, level: int, stages: int, strip: int) -> None:
+        capi.check(capi.lib().gmg_plan_set_tile_order(self._plan, int(level), int(stages),
+                                                      int(strip)), "gmg_plan_set_tile_order")
+
     def get_tile(self, level, role):
         """(stages, variant, tz) of the first pre- (role 0) or post-smoothing
         (role 1) pass on `level` after autotuning."""
