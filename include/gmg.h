@@ -181,6 +181,30 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
 gmg_status gmg_batch_solve(gmg_plan *p, double *const *u, const double *const *f, double rtol,
                            int maxit, int *iters, double *relres, gmg_status *st);
 
+/* Bytes of the device array gmg_solve_scratch works in (one per GPU). */
+#define GMG_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid hipMalloc): the solve of gmg_solve on a problem set up by cfg, with
+ * no plan or workspace from the caller.  Its workspace is a device array of
+ * GMG_SCRATCH_BYTES that the library keeps per GPU (allocated with the
+ * library's code on that GPU, held until the process ends); the call itself
+ * allocates no device or pinned host memory and creates no events, streams
+ * or graphs.  u (initial guess in, result out) and f are the caller's device
+ * arrays, as for gmg_solve; stream as for gmg_setup.  Same arithmetic,
+ * results and outputs as gmg_setup + gmg_solve with the same configuration
+ * and default tiles.  Synchronises like gmg_solve.  Every call on one GPU
+ * uses that GPU's one array, so calls that overlap on a GPU (from several
+ * host threads or streams) race; the array keeps the last call's contents,
+ * and every value a solve reads from it is written first by that solve.
+ * Errors: as gmg_solve and gmg_setup; GMG_ERR_WORKSPACE when the problem's
+ * workspace (gmg_setup's size query) exceeds GMG_SCRATCH_BYTES (e.g. 3D
+ * FP64 beyond 127^3), checked before any launch; GMG_ERR_UNSUPPORTED with
+ * GMG_AUTOTUNE, GMG_PROFILE or GMG_USE_GRAPH. */
+gmg_status gmg_solve_scratch(const gmg_config *cfg, double *u, const double *f, double rtol,
+                             int maxit, const double *res0_opt, int *iters, double *relres,
+                             void *stream);
+
 /* Release the plan (host memory only; the workspace stays the caller's). */
 gmg_status gmg_destroy(gmg_plan *p);
 

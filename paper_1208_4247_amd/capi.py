@@ -39,6 +39,7 @@ GMG_NO_FUSED_RESTRICT = 0x40
 GMG_FE_TRANSFER = 0x80
 GMG_COARSE_RELAX = 0x100
 GMG_NO_CROSS_CYCLE = 0x200
+GMG_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = [
     "gmg_config_default", "gmg_setup", "gmg_vcycle", "gmg_solve", "gmg_batch_solve",
@@ -47,7 +48,7 @@ EXPORTED = [
     "gmg_profile_count",
     "gmg_profile_get", "gmg_profile_reset", "gmg_tile_variant_count", "gmg_plan_set_tile",
     "gmg_profile_set_mask", "gmg_plan_get_tile", "gmg_fmg", "gmg_dst_setup", "gmg_dst_solve",
-    "gmg_dst_destroy", "gmg_tune_cache_check", "gmg_plan_set_tile_order",
+    "gmg_dst_destroy", "gmg_tune_cache_check", "gmg_plan_set_tile_order", "gmg_solve_scratch",
 ]
 
 
@@ -125,6 +126,7 @@ def lib():
     L.gmg_plan_get_tile.argtypes = [vp, i, i, ip, ip, ip]
     L.gmg_tune_cache_check.argtypes = [ctypes.c_char_p, ip, ip]
     L.gmg_plan_set_tile_order.argtypes = [vp, i, i, i]
+    L.gmg_solve_scratch.argtypes = [cfgp, vp, vp, d, i, dp, ip, dp, vp]
     for name in EXPORTED:
         if name not in ("gmg_status_string", "gmg_plan_workspace_bytes", "gmg_level_side",
                         "gmg_profile_count", "gmg_tile_variant_count"):

@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2089,6 +2090,36 @@ void bind_single(gmg_plan &p, const gmg_config &c, const Layout &Y, void *worksp
 }
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// The workspace of gmg_solve_scratch: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  On the host
+// the name `scratch` is only a stand-in, never a device address: the address
+// of a device's copy comes from hipGetSymbolAddress, called once per device
+// with that device current and kept in scratch_addr, and only that address is
+// handed to kernels.
+constexpr size_t kScratchBytes = (size_t)GMG_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_addr[kMaxDevices] = {};
+
+// Address of the current device's scratch array (looked up on its first use).
+gmg_status scratch_base(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GMG_ERR_HIP;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GMG_ERR_HIP;
+    scratch_addr[dev] = ptr;
+  }
+  *out = scratch_addr[dev];
+  return GMG_OK;
+}
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -2152,6 +2183,32 @@ gmg_status gmg_setup(const gmg_config *cfg, int nproblems, const int *dims, cons
   bind_single(*p, c, Y, workspace, (hipStream_t)stream, hs);
   *out = p;
   return GMG_OK;
+}
+
+gmg_status gmg_solve_scratch(const gmg_config *cfg, double *u, const double *f, double rtol,
+                             int maxit, const double *res0_opt, int *iters, double *relres,
+                             void *stream) {
+  if (!cfg || !u || !f) return GMG_ERR_INVALID_ARG;
+  if (!(rtol > 0.0) || maxit < 1) return GMG_ERR_INVALID_ARG;
+  if (res0_opt && !(*res0_opt >= 0.0)) return GMG_ERR_INVALID_ARG;
+  gmg_config c = *cfg;
+  gmg_status st = validate_cfg(&c);
+  if (st != GMG_OK) return st;
+  if (cfg_variant(c) && c.precision != GMG_FP64) return GMG_ERR_UNSUPPORTED;
+  // tuning and profiling create events, graphs instantiate device objects
+  if (c.flags & (GMG_AUTOTUNE | GMG_PROFILE | GMG_USE_GRAPH)) return GMG_ERR_UNSUPPORTED;
+  gmg_plan tmp;
+  init_plan_shape(tmp, &c);
+  const Layout Y = make_layout(tmp);
+  if (Y.total > kScratchBytes) return GMG_ERR_WORKSPACE;
+  void *ws = nullptr;
+  st = scratch_base(&ws);
+  if (st != GMG_OK) return st;
+  // the host copy of the solve state: pageable, on this stack frame
+  alignas(64) unsigned char hbuf[sizeof(SolveState) + 64];
+  gmg_plan p;
+  bind_single(p, c, Y, ws, (hipStream_t)stream, reinterpret_cast<SolveState *>(hbuf));
+  return gmg_solve(&p, u, f, rtol, maxit, res0_opt, iters, relres);
 }
 
 gmg_status gmg_destroy(gmg_plan *p) {
