@@ -124,7 +124,7 @@ typedef struct {
 
 typedef struct gmg_plan gmg_plan; /* opaque, host side */
 
-/* Fill *cfg with defaults: RBGS V(2,2), FP64, two inner cycles (used by
+/* Fill *cfg with defaults: RBGS V(2,2), FP64, four inner cycles (used by
  * MIXED_FP32_IR plans), no flags. */
 gmg_status gmg_config_default(gmg_config *cfg, int dim, int levels);
 

@@ -163,6 +163,9 @@ struct gmg_plan {
   // ends the cycle's post-smoothing and starts the next cycle's
   // pre-smoothing)
   bool cross = false;
+  // mixed V(1,1) with the same sweep orders: the FP32 cycles of a refinement
+  // step run that schedule among themselves
+  bool cross32 = false;
 
   // profiling
   bool profile = false;
@@ -499,30 +502,40 @@ hipError_t restrict_level(gmg_plan *p, int level, const T *u, const T *f, T *fc,
 // are folded in when the tile allows it; otherwise the caller restricts.
 // u_k itself is never stored: the solve forms it once, after its last cycle,
 // with an ordinary post-smoothing pass from w_k + P e_k.
-bool can_fuse_cross(const gmg_plan *p) {
+bool can_fuse_cross(const gmg_plan *p, size_t elem) {
   const PassChoice &c = p->ch[0][2];
   if (!c.fuse || (p->cfg.flags & GMG_NO_FUSED_RESTRICT)) return false;
   const PassTile t = pass_variant(p->dim, 3, 0, c.var[3]);
   if (pass_geometry(p->dim, p->m[0], 3, t, c.tz[3], true).nblocks > kMaxPartials) return false;
-  return rb_pass_fits(p->dim, 3, c.var[3], F_PROLONG | F_RESTRICT, sizeof(double));
+  return rb_pass_fits(p->dim, 3, c.var[3], F_PROLONG | F_RESTRICT, elem);
 }
 
-hipError_t cross_pass(gmg_plan *p, const double *w, const double *ec, const double *f,
-                      double *w_next, double *partials, const int *active, double *fc,
-                      bool *fused, int *nparts) {
-  const bool fz = can_fuse_cross(p);
+// partials != NULL (FP64 solves): the pass emits the norm of u_k's residual.
+// The FP32 cycles of a refinement step run it without (no stop test between
+// them).
+template <typename T>
+hipError_t cross_pass(gmg_plan *p, const T *w, const T *ec, const T *f, T *w_next,
+                      double *partials, const int *active, T *fc, bool *fused, int *nparts) {
+  const bool fz = can_fuse_cross(p, sizeof(T));
   *fused = fz;
   const PassChoice &c = p->ch[0][2];
   *nparts = pass_geometry(p->dim, p->m[0], 3, pass_variant(p->dim, 3, 0, c.var[3]), c.tz[3], fz)
                 .nblocks;
-  const int flags = F_PROLONG | F_BLACK_FIRST | F_NORM_MID | (fz ? F_RESTRICT : 0);
-  return one_pass_st<double>(p, 0, 2, 3, flags, w, ec, f, w_next, partials, active, PC_CROSS0,
-                             fz ? fc : nullptr);
+  const int flags =
+      F_PROLONG | F_BLACK_FIRST | (partials ? F_NORM_MID : 0) | (fz ? F_RESTRICT : 0);
+  return one_pass_st<T>(p, 0, 2, 3, flags, w, ec, f, w_next, partials, active, PC_CROSS0,
+                        fz ? fc : nullptr);
 }
 
 // Level-0 buffers of the cross-cycle schedule: w_k (the pre-smoothed
-// iterate of cycle k) lives in buffer k & 1.
-double *cross_buf(gmg_plan *p, int k) { return (k & 1) ? p->d.t[0] : p->d.w[0]; }
+// iterate of cycle k) lives in buffer k & 1 (FP64 solves; the FP32 cycles
+// of a refinement step have their own pair).
+template <typename T>
+T *cross_buf(gmg_plan *p, int k);
+template <>
+double *cross_buf<double>(gmg_plan *p, int k) { return (k & 1) ? p->d.t[0] : p->d.w[0]; }
+template <>
+float *cross_buf<float>(gmg_plan *p, int k) { return (k & 1) ? p->s.t[0] : p->s.w[0]; }
 
 template <typename T>
 LevelSet<T> &levels_of(gmg_plan *p);
@@ -716,14 +729,14 @@ hipError_t enqueue_cross_body(gmg_plan *p, int k, const double *u, const double 
   LevelSet<double> &S = p->d;
   bool fused = false;
   int nparts = 0;
-  double *wn = cross_buf(p, k + 1);
+  double *wn = cross_buf<double>(p, k + 1);
   hipError_t e;
   if (k == 0)
     e = smooth_chain<double>(p, 0, 1, false, u, nullptr, f, wn, nullptr, p->partials, active,
                              PC_PRE0, &nparts, S.f[1], &fused);
   else
-    e = cross_pass(p, cross_buf(p, k), S.u[1], f, wn, p->partials, active, S.f[1], &fused,
-                   &nparts);
+    e = cross_pass<double>(p, cross_buf<double>(p, k), S.u[1], f, wn, p->partials, active,
+                           S.f[1], &fused, &nparts);
   if (e != hipSuccess) return e;
   if (fused) {
     ProfScope ps(p, PC_FIN, 0.0);
@@ -733,6 +746,46 @@ hipError_t enqueue_cross_body(gmg_plan *p, int k, const double *u, const double 
   }
   if (e != hipSuccess) return e;
   return run_coarse<double>(p, active);
+}
+
+// The FP32 cycles of one refinement step (mixed plans): inner_cycles V-cycles
+// on A e = r32 (level-0 right-hand side s.f[0]) from e = 0, result in s.u[0].
+// Plans that run the cross-cycle schedule (V(1,1), Algorithm 1's sweep
+// orders) do it among these cycles: cycle 1's pre-smoothing from zero into
+// w_1, the three-stage pass between consecutive cycles (no norm: the stop
+// test belongs to the refinement step), cycle K's post-smoothing into e, and
+// every cycle's coarse part in between -- the same iterates as K separate
+// cycles.
+hipError_t enqueue_inner(gmg_plan *p, const int *active) {
+  LevelSet<float> &S = p->s;
+  const int K = p->cfg.inner_cycles;
+  if (!p->cross32) {
+    for (int c = 0; c < K; ++c) {
+      hipError_t e = enqueue_vcycle<float>(p, c == 0 ? nullptr : S.u[0], S.f[0], S.u[0], nullptr,
+                                           active);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  for (int c = 1; c <= K; ++c) {
+    float *wn = cross_buf<float>(p, c);
+    bool fused = false;
+    int nparts = 0;
+    hipError_t e =
+        c == 1 ? smooth_chain<float>(p, 0, 1, false, nullptr, nullptr, S.f[0], wn, nullptr,
+                                     nullptr, active, PC_PRE0, &nparts, S.f[1], &fused)
+               : cross_pass<float>(p, cross_buf<float>(p, c - 1), S.u[1], S.f[0], wn, nullptr,
+                                   active, S.f[1], &fused, &nparts);
+    if (e != hipSuccess) return e;
+    if (!fused) {
+      e = restrict_level<float>(p, 0, wn, S.f[0], S.f[1], active, PC_RES0);
+      if (e != hipSuccess) return e;
+    }
+    e = run_coarse<float>(p, active);
+    if (e != hipSuccess) return e;
+  }
+  return smooth_chain<float>(p, 0, 1, true, cross_buf<float>(p, K), S.u[1], S.f[0], S.u[0],
+                             nullptr, nullptr, active, PC_POST0, nullptr);
 }
 
 // ------------------------------------------------------------------ FMG
@@ -974,7 +1027,7 @@ Layout make_layout(const gmg_plan &p) {
       const size_t n = npts(dim, p.m[l]) * elem;
       if (l == 0) {
         W[0] = take(cur, n);
-        if (p.need_tmp || p.cross) Tt[0] = take(cur, n);
+        if (p.need_tmp || p.cross || p.cross32) Tt[0] = take(cur, n);
         if (elem == sizeof(float)) {  // mixed: the FP32 cycle's own RHS and result
           F[0] = take(cur, n);
           U[0] = take(cur, n);
@@ -1119,9 +1172,11 @@ gmg_status init_plan_shape(gmg_plan &p, const gmg_config *cfg) {
   // chained passes need a scratch array whenever a level may run more than
   // one pass (any choice of sweeps per pass, so tuning never changes layout)
   p.need_tmp = std::max(cfg->nu1, cfg->nu2) >= 2;
-  p.cross = cfg->precision == GMG_FP64 && cfg->smoother == GMG_SMOOTH_RBGS &&
-            !cfg_variant(p.cfg) && cfg->nu1 == 1 && cfg->nu2 == 1 && p.L >= 2 &&
-            !(cfg->flags & (GMG_POST_FORWARD | GMG_NO_CROSS_CYCLE));
+  const bool cross_ok = cfg->smoother == GMG_SMOOTH_RBGS && !cfg_variant(p.cfg) &&
+                        cfg->nu1 == 1 && cfg->nu2 == 1 && p.L >= 2 &&
+                        !(cfg->flags & (GMG_POST_FORWARD | GMG_NO_CROSS_CYCLE));
+  p.cross = cross_ok && cfg->precision == GMG_FP64;
+  p.cross32 = cross_ok && cfg->precision == GMG_MIXED_FP32_IR;
   p.profile = (cfg->flags & GMG_PROFILE) != 0;
   return GMG_OK;
 }
@@ -1459,9 +1514,12 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
 // the tile allows it and as a kernel of its own, each timed together with
 // the step that follows it in the solve (the stop test as a kernel of its
 // own, or the restriction whose workgroup 0 runs it).
-hipError_t tune_cross(gmg_plan *p, const double *w, const double *ec, const double *f, double *wn,
-                      double *fc) {
-  const std::string key = tune_key(*p, 0, 2, sizeof(double));
+template <typename T>
+hipError_t tune_cross(gmg_plan *p, const T *w, const T *ec, const T *f, T *wn, T *fc) {
+  const std::string key = tune_key(*p, 0, 2, sizeof(T));
+  // FP64 solves: with the norm and the stop test after it; FP32 inner
+  // cycles: neither
+  double *parts = sizeof(T) == 8 ? p->partials : nullptr;
   auto it = tune_cache().find(key);
   if (it != tune_cache().end()) {
     if (choice_ok(p->dim, p->m[0], p->smax_cap, false, it->second)) {
@@ -1483,10 +1541,10 @@ hipError_t tune_cross(gmg_plan *p, const double *w, const double *ec, const doub
   auto run = [&]() -> hipError_t {
     bool fused = false;
     int nparts = 0;
-    hipError_t e2 = cross_pass(p, w, ec, f, wn, p->partials, nullptr, fc, &fused, &nparts);
+    hipError_t e2 = cross_pass<T>(p, w, ec, f, wn, parts, nullptr, fc, &fused, &nparts);
     if (e2 != hipSuccess) return e2;
-    if (fused) return launch_finalize(p->partials, nparts, p->state, p->stream);
-    return restrict_level<double>(p, 0, wn, f, fc, nullptr, PC_MISC, p->partials, nparts);
+    if (fused) return parts ? launch_finalize(parts, nparts, p->state, p->stream) : hipSuccess;
+    return restrict_level<T>(p, 0, wn, f, fc, nullptr, PC_MISC, parts, parts ? nparts : 0);
   };
   std::vector<Cand> cands[2];
   const int nv = pass_variant_count(p->dim, 3, 0);
@@ -1494,14 +1552,14 @@ hipError_t tune_cross(gmg_plan *p, const double *w, const double *ec, const doub
     const PassTile t = pass_variant(p->dim, 3, 0, v);
     for (const int tzv : tune_z_chunks(p->dim, m, 3, t)) {
       if (pass_geometry(p->dim, m, 3, t, tzv).nblocks > kMaxPartials) continue;
-      if (!rb_pass_fits(p->dim, 3, v, F_PROLONG, sizeof(double))) continue;
+      if (!rb_pass_fits(p->dim, 3, v, F_PROLONG, sizeof(T))) continue;
       for (int fz = 1; fz >= 0 && err == hipSuccess; --fz) {
         PassChoice c = base;
         c.var[3] = v;
         c.tz[3] = tzv;
         c.fuse = fz;
         p->ch[0][2] = c;
-        if (fz && !can_fuse_cross(p)) continue;
+        if (fz && !can_fuse_cross(p, sizeof(T))) continue;
         double us = 0.0;
         err = time_runs(p, e0, e1, reps, run, us);
         if (err != hipSuccess) break;
@@ -1558,9 +1616,8 @@ hipError_t tune_plan(gmg_plan *p, const T *src0, const T *f0, double *partials0)
     const T *src = l == 0 ? (src0 ? src0 : S.w[0]) : S.w[l];
     T *dst = l == 0 ? (src0 ? S.w[0] : S.u[0]) : S.u[l];
     e = tune_role<T>(p, l, 1, src, S.u[l + 1], f, dst, S.t[l], nullptr, sizeof(T));
-    if (e == hipSuccess && l == 0 && p->cross) {
-      if constexpr (sizeof(T) == 8) e = tune_cross(p, S.w[0], S.u[1], f, S.t[0], S.f[1]);
-    }
+    if (e == hipSuccess && l == 0 && (sizeof(T) == 8 ? p->cross : p->cross32))
+      e = tune_cross<T>(p, S.w[0], S.u[1], f, S.t[0], S.f[1]);
   }
   p->profile = prof;
   p->tuned = true;
@@ -2147,7 +2204,7 @@ gmg_status gmg_config_default(gmg_config *cfg, int dim, int levels) {
   cfg->nu2 = 2;
   cfg->omega = 0.0;
   cfg->precision = GMG_FP64;
-  cfg->inner_cycles = 2;
+  cfg->inner_cycles = 4;
   cfg->flags = 0;
   return validate_cfg(cfg);
 }
@@ -2292,9 +2349,7 @@ gmg_status gmg_vcycle(gmg_plan *p, double *u, const double *f) {
     ProfScope ps(p, PC_IR, (double)npts(p->dim, p->m[0]) * 20.0);
     HIPCHK(launch_ir_step(p->dim, a, p->stream));
   }
-  for (int c = 0; c < p->cfg.inner_cycles; ++c)
-    HIPCHK(enqueue_vcycle<float>(p, c == 0 ? nullptr : p->s.u[0], p->s.f[0], p->s.u[0], nullptr,
-                                 nullptr));
+  HIPCHK(enqueue_inner(p, nullptr));
   HIPCHK(launch_axpy_f32(u, p->s.u[0], npts(p->dim, p->m[0]), nullptr, p->stream));
   return GMG_OK;
 }
@@ -2362,9 +2417,7 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
           ProfScope ps(p, PC_FIN, 0.0);
           HIPCHK(launch_finalize(p->partials, a.nblocks, p->state, p->stream));
         }
-        for (int c = 0; c < p->cfg.inner_cycles; ++c)
-          HIPCHK(enqueue_vcycle<float>(p, c == 0 ? nullptr : p->s.u[0], p->s.f[0], p->s.u[0],
-                                       nullptr, act));
+        HIPCHK(enqueue_inner(p, act));
       }
     }
     gmg_status rs = read_state(p);
@@ -2388,7 +2441,7 @@ gmg_status gmg_solve(gmg_plan *p, double *u, const double *f, double rtol, int m
     // u = u_K, the iterate the loop stopped at, from w_K + P e_K (both left
     // in place: every launch after the stop test returned at once)
     const int K = st.iter;
-    HIPCHK(smooth_chain<double>(p, 0, 1, true, cross_buf(p, K), p->d.u[1], f, u, nullptr,
+    HIPCHK(smooth_chain<double>(p, 0, 1, true, cross_buf<double>(p, K), p->d.u[1], f, u, nullptr,
                                 nullptr, nullptr, PC_POST0, nullptr));
     HIPCHK(hipStreamSynchronize(p->stream));
   }

@@ -1163,7 +1163,8 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
 }  // namespace
 
 // The three-stage pass runs in two forms only: interpolated correction in,
-// mid-pass norm, with or without the folded restriction (FP64).
+// mid-pass norm (FP64 solves) or none (the FP32 cycles of a refinement step),
+// with or without the folded restriction.
 #define GMG_CROSS_SWITCH(RUN, T, D, S, E, Y, N)                                        \
   switch (flags) {                                                                  \
     case F_PROLONG | F_BLACK_FIRST | F_NORM_MID:                                    \
@@ -1171,6 +1172,15 @@ hipError_t run_wj(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
     case F_PROLONG | F_BLACK_FIRST | F_NORM_MID | F_RESTRICT:                       \
       return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST | F_NORM_MID | F_RESTRICT>(   \
           a, st, tbl, nent);                                                        \
+    default: return hipErrorInvalidValue;                                           \
+  }
+
+#define GMG_CROSS32_SWITCH(RUN, T, D, S, E, Y, N)                                      \
+  switch (flags) {                                                                  \
+    case F_PROLONG | F_BLACK_FIRST:                                                 \
+      return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST>(a, st, tbl, nent);    \
+    case F_PROLONG | F_BLACK_FIRST | F_RESTRICT:                                    \
+      return RUN<T, D, S, E, Y, N, F_PROLONG | F_BLACK_FIRST | F_RESTRICT>(a, st, tbl, nent); \
     default: return hipErrorInvalidValue;                                           \
   }
 
@@ -1189,6 +1199,14 @@ hipError_t launch_rb_pass(int dim, int stages, int flags, int variant, PassArgs<
 #define GMG_TRY(D, S, E, Y, N)                                       \
   if (dim == D && stages == S && t.exp_ == E && t.ey == Y && t.nt == N) { \
     GMG_CROSS_SWITCH(run_rb, T, D, S, E, Y, N)                        \
+  }
+    GMG_RB3_S3(GMG_TRY) GMG_RB2_S3(GMG_TRY)
+#undef GMG_TRY
+  } else {
+    // FP32 (the inner cycles of the mixed form): no norm between them
+#define GMG_TRY(D, S, E, Y, N)                                       \
+  if (dim == D && stages == S && t.exp_ == E && t.ey == Y && t.nt == N) { \
+    GMG_CROSS32_SWITCH(run_rb, T, D, S, E, Y, N)                      \
   }
     GMG_RB3_S3(GMG_TRY) GMG_RB2_S3(GMG_TRY)
 #undef GMG_TRY

@@ -45,7 +45,7 @@ def test_status_strings(capi):
 
 def test_config_default(capi):
     c = capi.config_default(3, 8)
-    assert (c.dim, c.levels, c.nu1, c.nu2, c.smoother, c.precision, c.inner_cycles) == (3, 8, 2, 2, 0, 0, 2)
+    assert (c.dim, c.levels, c.nu1, c.nu2, c.smoother, c.precision, c.inner_cycles) == (3, 8, 2, 2, 0, 0, 4)
 
 
 @pytest.mark.parametrize("field,value", [("dim", 1), ("dim", 4), ("levels", 0), ("levels", 11),

@@ -163,3 +163,21 @@ def test_cross_nonfinite_and_diverged():
                           ctypes.byref(it), ctypes.byref(rel))
     torch.cuda.synchronize()
     assert s == c.GMG_ERR_DIVERGED and it.value == 1
+
+
+@pytest.mark.parametrize("dim,m,inner", [(3, 63, 1), (3, 63, 2), (3, 127, 4), (2, 255, 3)])
+def test_mixed_inner_cycles_cross_bitwise(dim, m, inner):
+    """Mixed precision, V(1,1): the FP32 cycles of a refinement step run the
+    cross-cycle schedule among themselves (no norm between them); the
+    iterates equal those of separate cycles bit for bit, and the solve
+    reaches 1e-10 by the oracle's FP64 residual."""
+    c = capi()
+    f = wl.rhs_uniform(dim, m, seed=206)
+    fd = dev(f)
+    kw = dict(nu1=1, nu2=1, precision="mixed", inner_cycles=inner)
+    a = solve(Plan(dim, levels_of(m), **kw), fd, rtol=1e-10)
+    b = solve(Plan(dim, levels_of(m), flags=c.GMG_NO_CROSS_CYCLE, **kw), fd, rtol=1e-10)
+    assert a[:2] == b[:2] and a[0] == 0
+    assert np.array_equal(a[3], b[3])
+    rr = oracle.norm2(oracle.residual(a[3], f)) / oracle.norm2(f)
+    assert rr <= 1e-10
