@@ -26,7 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_255_traffic.md")
+# committed rocprofv3 counter tables of the level-0 passes: (workload, kernel class) -> file
+TRAFFIC_PROFILES = {
+    ("poisson3d_255_sine_noise_fp64_v22", "smooth_pre_l0"):
+        os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_255_traffic.md"),
+    ("poisson3d_255_sine_noise_fp64_v22", "smooth_post_l0"):
+        os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_255_traffic.md"),
+    ("poisson3d_1023_sine_modes_fp64_v11", "smooth_cross_l0"):
+        os.path.join(ROOT, "profiles", "cross_pass_l0_poisson3d_1023_traffic.md"),
+}
 
 WORKLOADS = {
     # name: dim, levels, right-hand side, precision, sweeps nu1 = nu2, FP32
@@ -142,17 +150,18 @@ def cpu_baseline(spec, f, gpu_iters, budget_s=30.0):
                 "residual norm): %.1f s, scaled to %d cycles" % (k, gpu_iters, t, gpu_iters))
 
 
-def measured_traffic(workload, cls, tile):
-    """HBM bytes per launch of the level-0 pass class `cls` (smooth_pre_l0 /
-    smooth_post_l0) with tile (stages, variant, tz), from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE per dispatch, scaled
-    by a plain copy; one entry per autotuner candidate), or None when the
-    summary is for another workload or kernel source."""
+def measured_traffic(workload, cls, tile, folded):
+    """HBM bytes per launch of the level-0 pass class `cls` with tile
+    (stages, variant, tz), from a committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the runtime's copy of a
+    known size; one entry per autotuner candidate), or None when no summary
+    covers this workload and kernel source."""
     import hashlib
 
-    if workload != DEFAULT or tile is None or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get((workload, cls))
+    if path is None or tile is None or not os.path.exists(path):
         return None
-    line = [l for l in open(TRAFFIC_PROFILE) if l.startswith("traffic-json: ")]
+    line = [l for l in open(path) if l.startswith("traffic-json: ")]
     if not line:
         return None
     rec = json.loads(line[-1][len("traffic-json: "):])
@@ -161,10 +170,12 @@ def measured_traffic(workload, cls, tile):
         with open(os.path.join(csrc, name), "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != digest:
                 return None
-    role = {"smooth_pre_l0": "pre", "smooth_post_l0": "post"}.get(cls)
-    if role is None:
-        return None
-    return rec["tiles"].get("%s|%d|%d|%d" % ((role,) + tuple(tile)))
+    if cls == "smooth_cross_l0":
+        key = "cross|%d|%d|%d|%d" % (tile + (1 if folded else 0,))
+    else:
+        role = {"smooth_pre_l0": "pre", "smooth_post_l0": "post"}[cls]
+        key = "%s|%d|%d|%d" % ((role,) + tuple(tile))
+    return rec["tiles"].get(key)
 
 
 def bench_fmg(args, spec):
@@ -360,7 +371,7 @@ def mixed_vs_fp64(args, spec, f, u64, ms64, steps):
 
     d, L, nu = spec["dim"], spec["L"], spec.get("nu", 2)
     flags = args.flags | (0 if args.no_autotune else capi.GMG_AUTOTUNE)
-    pm = Plan(d, L, flags=flags, nu1=nu, nu2=nu, precision="mixed", inner_cycles=0)
+    pm = Plan(d, L, flags=flags, nu1=nu, nu2=nu, precision="mixed")
     um = torch.zeros_like(f)
     pm.solve(um, f, rtol=1e-10)  # warm-up (autotunes)
     ts = []
@@ -482,7 +493,7 @@ def main():
         st, it, rel = plan.solve(u, f, rtol=rtol)
     torch.cuda.synchronize()
     # timed region: hipEvents only around the level-0 smoothing passes
-    smoothers = ["smooth_pre_l0", "smooth_post_l0"]
+    smoothers = ["smooth_pre_l0", "smooth_post_l0", "smooth_cross_l0"]
     plan.profile_only(smoothers)
     plan.profile_reset()
     iters = []
@@ -502,7 +513,8 @@ def main():
     value = N / (t_total / args.steps)
     dom = max(smoothers, key=lambda k: prof[k]["ms"])
     pv = prof[dom]
-    tile = None if smoother == "mcgs" else plan.get_tile(0, 0 if dom == "smooth_pre_l0" else 1)
+    role = {"smooth_pre_l0": 0, "smooth_post_l0": 1, "smooth_cross_l0": 2}[dom]
+    tile = None if smoother == "mcgs" else plan.get_tile(0, role)
     achieved = pv["bytes"] / (pv["ms"] * 1e-3) / 1e9 if pv["ms"] > 0 else 0.0
     avg_us = 1e3 * pv["ms"] / max(pv["launches"], 1)
     bytes_per_launch = pv["bytes"] / max(pv["launches"], 1)
@@ -516,10 +528,11 @@ def main():
         u.zero_()
         plan.solve(u, f, rtol=rtol)
     full = plan.profile()
-    # the counter table covers the plain passes; a pre-smoothing pass with the
-    # restriction folded in (no separate restriction launches) is not in it
-    fused_pre = dom == "smooth_pre_l0" and full["resid_restrict_l0"]["launches"] == 0
-    traffic = None if fused_pre else measured_traffic(args.workload, dom, tile)
+    # the restriction runs inside the pass when no separate restriction ran
+    fused_pre = dom != "smooth_post_l0" and full["resid_restrict_l0"]["launches"] == 0
+    traffic = measured_traffic(args.workload, dom, tile, fused_pre)
+    if traffic is not None and dom == "smooth_pre_l0" and fused_pre:
+        traffic = None  # the 255^3 table covers the plain pre-smoothing pass only
     for k, v in full.items():
         if v["launches"]:
             print("#   %-22s launches %6d  avg %9.3f us  alg %8.1f GB/s" % (

@@ -1386,33 +1386,6 @@ hipError_t refine_best(gmg_plan *p, int l, int role, std::vector<Cand> &cands, h
   return hipSuccess;
 }
 
-// Tile order of the chosen candidate (3D): strips 1..8 tiles wide instead of
-// whole rows of tiles; a width is kept when it is at least 2% faster.  run()
-// launches with p->ch[l][role].
-template <typename F>
-hipError_t tune_strips(gmg_plan *p, int l, int role, int st, bool rst, PassChoice &c, double &us,
-                       hipEvent_t e0, hipEvent_t e1, int reps, F &&run) {
-  if (p->dim != 3 || us >= 1e30) return hipSuccess;
-  const bool wj = p->cfg.smoother == GMG_SMOOTH_WJ;
-  const PassTile t = pass_variant(p->dim, st, wj ? 1 : 0, c.var[st]);
-  const int ntx = pass_geometry(p->dim, p->m[l], st, t, c.tz[st], rst).ntx;
-  for (const int w : {1, 2, 3, 4, 6, 8}) {
-    if (w >= ntx) break;
-    PassChoice cs = c;
-    cs.sw[st] = w;
-    p->ch[l][role] = cs;
-    double u = 0.0;
-    hipError_t err = time_runs(p, e0, e1, reps, run, u);
-    if (err != hipSuccess) return err;
-    if (u < 0.98 * us) {
-      us = u;
-      c = cs;
-    }
-  }
-  p->ch[l][role] = c;
-  return hipSuccess;
-}
-
 // fc (pre-smoothing): the next coarser level's right-hand side.  Each
 // candidate is timed together with the restriction, fused into the last
 // pass where the tile allows it and as a kernel of its own, and the faster
@@ -1500,9 +1473,6 @@ hipError_t tune_role(gmg_plan *p, int l, int role, const T *src, const T *ec, co
   // (timing noise of a few percent would otherwise flip the choice)
   const int pick = best_us[1] < 0.97 * best_us[0] ? 1 : 0;
   p->ch[l][role] = best[pick];
-  if (err == hipSuccess)
-    err = tune_strips(p, l, role, best_st[pick], pick == 1, best[pick], best_us[pick], e0, e1,
-                      3 * reps, run);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err == hipSuccess) tune_cache_store(key, best[pick], best_st[pick], best_us[pick]);
@@ -1580,8 +1550,6 @@ hipError_t tune_cross(gmg_plan *p, const T *w, const T *ec, const T *f, T *wn, T
   }
   const int pick = best_us[1] < 0.97 * best_us[0] ? 1 : 0;
   p->ch[0][2] = best[pick];
-  if (err == hipSuccess)
-    err = tune_strips(p, 0, 2, 3, pick == 1, best[pick], best_us[pick], e0, e1, 3 * reps, run);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err == hipSuccess && best_us[pick] < 1e30)

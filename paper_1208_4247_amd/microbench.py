@@ -177,6 +177,141 @@ def cross_sweep(dim, m, strips=(0, 1, 2, 3, 4, 6, 8), variants=None, tzs=None):
         plan.close()
 
 
+def cross_traffic_table(dim, m):
+    """Every candidate the autotuner tries for the cross-cycle pass of an FP64
+    red-black V(1,1) solve (three-stage tile x z-chunk, restriction folded in
+    or not), two launches each inside a two-cycle solve, with one manifest
+    line per candidate.  Under a counter profiler restricted to the
+    three-stage kernels (FETCH_SIZE, WRITE_SIZE) the dispatches map two by
+    two onto the manifest."""
+    from . import capi
+
+    L = (m + 1).bit_length() - 1
+    g = torch.Generator(device="cuda").manual_seed(0)
+    f = torch.rand((m,) * dim, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    u = torch.zeros_like(f)
+    for fold in (True, False):
+        plan = Plan(dim, L, nu1=1, nu2=1, flags=0 if fold else capi.GMG_NO_FUSED_RESTRICT)
+        for v in range(plan.tile_variants(3)):
+            seen = set()
+            for tz in tuner_tz(m):
+                try:
+                    plan.set_tile(0, 3, v, tz)
+                except capi.GmgError:
+                    continue
+                tzv = plan.get_tile(0, 2)[2]
+                if tzv in seen:
+                    continue
+                seen.add(tzv)
+                u.zero_()
+                st, it, rel = plan.solve(u, f, rtol=1e-30, maxit=2)
+                if it != 2:
+                    continue
+                print(json.dumps(dict(manifest="cross", dim=dim, m=m, stages=3, variant=v,
+                                      tz=tzv, fold=fold, launches=2)), flush=True)
+        torch.cuda.synchronize()
+        plan.close()
+
+
+def traffic_report(manifest_log, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv,
+                   kernel_regex, title):
+    """The counter table of a traffic-table run as markdown: HBM bytes per
+    launch of every candidate from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), scaled by what the same counters read for the runtime's copy
+    of a 1 GiB buffer, and a last line with the table as JSON for bench.py."""
+    import csv
+    import re
+
+    man = [json.loads(l) for l in open(manifest_log) if l.startswith('{"manifest"')]
+
+    def disp(path, regex):
+        rows = [r for r in csv.DictReader(open(path)) if re.search(regex, r["Kernel_Name"])]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    fr = disp(fetch_csv, kernel_regex)
+    wr = disp(write_csv, kernel_regex)
+    need = sum(e["launches"] for e in man)
+    if len(fr) != need or len(wr) != need:
+        raise SystemExit("dispatch count %d/%d does not match the manifest (%d)" % (
+            len(fr), len(wr), need))
+    cf = [float(r["Counter_Value"]) for r in disp(copy_fetch_csv, "copyBuffer")]
+    cw = [float(r["Counter_Value"]) for r in disp(copy_write_csv, "copyBuffer")]
+    gib_kib = float(1 << 20)
+    kf, kw = gib_kib / (sum(cf) / len(cf)), gib_kib / (sum(cw) / len(cw))
+    out = ["# %s" % title, "",
+           "Calibration: the runtime's copy of a 1 GiB buffer (`__amd_rocclr_copyBuffer`) "
+           "reads %.0f KiB and writes %.0f KiB per dispatch by these counters, so bytes = "
+           "FETCH_SIZE x %.4f x 1024 and WRITE_SIZE x %.4f x 1024." % (
+               sum(cf) / len(cf), sum(cw) / len(cw), kf, kw), "",
+           "| candidate | kernel | FETCH KiB | WRITE KiB | traffic MB | algorithmic MB | "
+           "traffic / alg |", "|---|---|---|---|---|---|---|"]
+    table = {}
+    i = 0
+    for e in man:
+        n = e["launches"]
+        fk = sum(float(r["Counter_Value"]) for r in fr[i:i + n]) / n
+        wk = sum(float(r["Counter_Value"]) for r in wr[i:i + n]) / n
+        kern = fr[i]["Kernel_Name"].split("(")[0].replace("void gmg::", "")
+        i += n
+        # the pass's flags are its last template argument; 16: restriction
+        # folded in (a candidate asked to fold whose tile does not fit runs
+        # the plain pass, and is filed under it)
+        fold = (int(kern.rstrip(">").split(",")[-1]) & 16) != 0
+        m, d = e["m"], e["dim"]
+        mc = (m - 1) // 2
+        # w_k, f and the coarse correction read; w_{k+1} (and f_c) written
+        alg = 8.0 * (3 * m ** d + mc ** d + (mc ** d if fold else 0))
+        traffic = 1024.0 * (fk * kf + wk * kw)
+        key = "%s|%d|%d|%d|%d" % (e["manifest"], e["stages"], e["variant"], e["tz"],
+                                  1 if fold else 0)
+        table[key] = traffic
+        out.append("| %s | `%s` | %.0f | %.0f | %.1f | %.1f | %.3f |" % (
+            key, kern, fk, wk, traffic / 1e6, alg / 1e6, traffic / alg))
+    import hashlib
+    import os
+
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    sha = {n: hashlib.sha256(open(os.path.join(csrc, n), "rb").read()).hexdigest()
+           for n in ("smooth.hip", "gmg_internal.h")}
+    out += ["", "traffic-json: " + json.dumps({"tiles": table, "fetch_factor": kf,
+                                               "write_factor": kw, "sources_sha256": sha})]
+    print("\n".join(out))
+
+
+def trace_report(trace_csv, title, active_us=5.0):
+    """A rocprofv3 kernel trace (--kernel-trace, CSV) as markdown: per kernel
+    and grid size, the dispatches, those that did work (longer than
+    active_us: the launches a solve enqueues past its stop test return at
+    once) and their mean duration.  Meant for traced runs whose tile choices
+    come from an autotuner cache (GMG_TUNE_CACHE), so that every dispatch
+    belongs to a solve."""
+    import csv
+    import collections
+
+    rows = list(csv.DictReader(open(trace_csv)))
+    agg = collections.OrderedDict()
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("gmg::", "")
+        grid = int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+        wg = int(r.get("Workgroup_Size_X") or r.get("Workgroup_Size") or 0)
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = agg.setdefault((name, grid, wg), [0, 0, 0.0])
+        a[0] += 1
+        if us > active_us:
+            a[1] += 1
+            a[2] += us
+    out = ["# %s" % title, "",
+           "Dispatches that did work are those longer than %.0f us (launches enqueued past "
+           "a solve's stop test return at once)." % active_us, "",
+           "| kernel | grid | wg | dispatches | active | avg active (us) | total active (ms) |",
+           "|---|---|---|---|---|---|---|"]
+    for (name, grid, wg), (n, na, t) in sorted(agg.items(), key=lambda kv: -kv[1][2]):
+        out.append("| `%s` | %d | %d | %d | %d | %.2f | %.2f |" % (
+            name, grid, wg, n, na, t / na if na else 0.0, t / 1e3))
+    print("\n".join(out))
+
+
 def copy_calibration(mib, reps=20):
     """A plain device copy of known size (torch's copy kernel): the yardstick
     that converts the HBM byte counters of a profiler into bytes.  Also
@@ -215,6 +350,17 @@ def main():
     ap.add_argument("--cross-sweep", action="store_true",
                     help="time the cross-cycle pass over tiles, z-chunks and tile orders")
     ap.add_argument("--strips", type=int, nargs="+", default=[0, 1, 2, 3, 4, 6, 8])
+    ap.add_argument("--cross-traffic-table", action="store_true",
+                    help="launch every autotuner candidate of the cross-cycle pass twice "
+                    "(for a counter profiler)")
+    ap.add_argument("--traffic-report", nargs=5, metavar=("MANIFEST_LOG", "FETCH_CSV",
+                                                          "WRITE_CSV", "COPY_FETCH_CSV",
+                                                          "COPY_WRITE_CSV"),
+                    help="markdown counter table of a traffic-table run")
+    ap.add_argument("--trace-report", metavar="KERNEL_TRACE_CSV",
+                    help="markdown per-kernel summary of a rocprofv3 kernel trace")
+    ap.add_argument("--kernel-regex", default=r"k_rb_pass<double, 3, 3,")
+    ap.add_argument("--title", default="HBM traffic of the cross-cycle pass")
     ap.add_argument("--traffic-table", action="store_true",
                     help="launch every autotuner candidate of the level-0 passes twice "
                     "(for a counter profiler)")
@@ -223,6 +369,16 @@ def main():
         for m in a.m:
             cross_sweep(a.dim, m, tuple(a.strips), a.variants,
                         None if a.tz == [0] else a.tz)
+        return
+    if a.trace_report:
+        trace_report(a.trace_report, a.title)
+        return
+    if a.traffic_report:
+        traffic_report(*a.traffic_report, a.kernel_regex, a.title)
+        return
+    if a.cross_traffic_table:
+        for m in a.m:
+            cross_traffic_table(a.dim, m)
         return
     if a.traffic_table:
         for m in a.m:
