@@ -518,7 +518,10 @@ hipError_t cross_pass(gmg_plan *p, const T *w, const T *ec, const T *f, T *w_nex
                       double *partials, const int *active, T *fc, bool *fused, int *nparts) {
   const bool fz = can_fuse_cross(p, sizeof(T));
   *fused = fz;
-  const PassChoice &c = p->ch[0][2];
+  PassChoice &c = p->ch[0][2];
+  // a tile made for the folded form (odd row count) cannot run the plain
+  // one: the plain form then takes the first tile of the table
+  if (!fz && !rb_pass_fits(p->dim, 3, c.var[3], F_PROLONG, sizeof(T))) c.var[3] = 0;
   *nparts = pass_geometry(p->dim, p->m[0], 3, pass_variant(p->dim, 3, 0, c.var[3]), c.tz[3], fz)
                 .nblocks;
   const int flags =
@@ -1113,6 +1116,9 @@ PassChoice choice_for(const gmg_config &cfg, int dim, int m, int role, int smax_
     } else {
       v = (m >= 255 || nv == 1) ? 0 : 1;
     }
+    // the three-stage pass: a tile that runs the form with the restriction
+    // folded in (odd row count)
+    if (st == 3 && dim == 3 && !wj) v = 5;
     v = std::min(v, nv - 1);
     c.var[st] = v;
     const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
@@ -1522,14 +1528,16 @@ hipError_t tune_cross(gmg_plan *p, const T *w, const T *ec, const T *f, T *wn, T
     const PassTile t = pass_variant(p->dim, 3, 0, v);
     for (const int tzv : tune_z_chunks(p->dim, m, 3, t)) {
       if (pass_geometry(p->dim, m, 3, t, tzv).nblocks > kMaxPartials) continue;
-      if (!rb_pass_fits(p->dim, 3, v, F_PROLONG, sizeof(T))) continue;
       for (int fz = 1; fz >= 0 && err == hipSuccess; --fz) {
         PassChoice c = base;
         c.var[3] = v;
         c.tz[3] = tzv;
         c.fuse = fz;
         p->ch[0][2] = c;
-        if (fz && !can_fuse_cross(p, sizeof(T))) continue;
+        // each tile runs one form or both (folded: odd row count)
+        if (fz ? !can_fuse_cross(p, sizeof(T))
+               : !rb_pass_fits(p->dim, 3, v, F_PROLONG, sizeof(T)))
+          continue;
         double us = 0.0;
         err = time_runs(p, e0, e1, reps, run, us);
         if (err != hipSuccess) break;
@@ -2499,6 +2507,13 @@ gmg_status gmg_plan_set_tile(gmg_plan *p, int level, int stages, int variant, in
     return GMG_ERR_INVALID_ARG;
   if (!wj && stages == 3) {  // the cross-cycle pass of level 0
     if (level != 0) return GMG_ERR_INVALID_ARG;
+    // the tile must run the form the plan will use: the restriction folded
+    // in when the plan allows it and the tile fits, the plain form otherwise
+    const size_t elem = p->cfg.precision == GMG_MIXED_FP32_IR ? sizeof(float) : sizeof(double);
+    const bool fold = !(p->cfg.flags & GMG_NO_FUSED_RESTRICT) &&
+                      pass_geometry(p->dim, p->m[0], 3, t, tzv, true).nblocks <= kMaxPartials &&
+                      rb_pass_fits(p->dim, 3, variant, F_PROLONG | F_RESTRICT, elem);
+    if (!fold && !rb_pass_fits(p->dim, 3, variant, F_PROLONG, elem)) return GMG_ERR_INVALID_ARG;
     PassChoice &c = p->ch[0][2];
     c.var[3] = variant;
     c.tz[3] = tzv;
@@ -2536,7 +2551,7 @@ gmg_status gmg_plan_get_tile(const gmg_plan *p, int level, int role, int *stages
   const int wj = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
   int st;
   if (role == 2) {
-    if (level != 0 || !p->cross) return GMG_ERR_INVALID_ARG;
+    if (level != 0 || !(p->cross || p->cross32)) return GMG_ERR_INVALID_ARG;
     st = 3;
   } else {
     const int nu = role == 0 ? p->cfg.nu1 : p->cfg.nu2;

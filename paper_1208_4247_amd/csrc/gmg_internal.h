@@ -240,7 +240,21 @@ int pass_variant_count(int dim, int stages, int wj);
 PassTile pass_variant(int dim, int stages, int wj, int v);
 PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz,
                        bool restrict_ = false);
-// LDS of a red-black pass and whether it fits the per-workgroup limit
+// Halo of a red-black pass with S stages, in pairs (x) and rows (3D) on the
+// low and high side of the output tile.  Plain passes: S points rounded up to
+// a pair, and as many rows as points.  With the folded restriction the final
+// values must be exact one point past the tile on the low side and two past
+// it on the high side; low-side rows are rounded up to an even count so that
+// the tile origin stays on an even row (coarse rows are the odd ones).
+struct RbHalo {
+  int pl, ph, yl, yh;
+};
+constexpr RbHalo rb_halo(int S, bool rst) {
+  return rst ? RbHalo{(S + 2) / 2, (S + 3) / 2, (S + 2) & ~1, S + 2}
+             : RbHalo{(S + 1) / 2, (S + 1) / 2, 2 * ((S + 1) / 2), 2 * ((S + 1) / 2)};
+}
+// LDS of a red-black pass and whether it fits the per-workgroup limit and
+// leaves a valid output tile (an even, positive row count in 3D)
 constexpr size_t kMaxPassLds = 160 * 1024;
 size_t rb_pass_lds_bytes(int dim, int stages, int exp_, int ey, int flags, size_t elem);
 bool rb_pass_fits(int dim, int stages, int variant, int flags, size_t elem);

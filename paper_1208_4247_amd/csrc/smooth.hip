@@ -184,13 +184,15 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   constexpr bool NMID = (FL & F_NORM_MID) != 0;
   constexpr int QN = (S + 1) / 2;
   static_assert(!NMID || (S % 2 == 1 && S >= 3 && !NORM), "mid-pass norm: odd S >= 3");
-  // halo: S points for the stages; RST adds two, so the result is exact one
-  // point past the output tile (the residual there) and the residual one
-  // point past it on the high side (full weighting of the edge coarse points)
-  constexpr int HP = (S + 1) / 2 + (RST ? 1 : 0);  // halo in pairs
-  constexpr int HY = 2 * HP;                       // halo in rows (3D)
-  constexpr int TXP = EXP - 2 * HP;             // output pairs per row
-  constexpr int TY = DIM == 3 ? EY - 2 * HY : 1;
+  // halo (rb_halo): S points for the stages; RST needs the final values one
+  // point past the output tile on the low side (the residual at its first
+  // point) and two on the high side (the residual one point past it, for the
+  // full weighting of the edge coarse points)
+  constexpr RbHalo HA = rb_halo(S, RST);
+  constexpr int HPL = HA.pl, HPH = HA.ph;       // halo in pairs, low / high side
+  constexpr int HYL = HA.yl, HYH = HA.yh;       // halo in rows (3D), low / high side
+  constexpr int TXP = EXP - HPL - HPH;          // output pairs per row
+  constexpr int TY = DIM == 3 ? EY - HYL - HYH : 1;
   static_assert(TXP > 0 && TY > 0 && (DIM == 2 || TY % 2 == 0), "tile too small");
   constexpr int C1 = (FL & F_BLACK_FIRST) ? 1 : 0;
   constexpr int C0 = 1 - C1;  // colour the first stage reads
@@ -199,7 +201,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   // at a time, staged in LDS (two planes in a ring).  Column j <-> coarse x
   // index CX0 + j, row k <-> coarse y index CY0 + k; zero outside the grid.
   constexpr int NCX = EXP + 1;
-  constexpr int NCY = DIM == 3 ? EY / 2 + 1 : 1;
+  constexpr int NCY = DIM == 3 ? (EY + 1) / 2 + 1 : 1;
   constexpr int CPL = NCX * NCY;
   constexpr int NCP = PRO ? (CPL + NT - 1) / NT : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -245,15 +247,15 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     live[i] = q < PL;
     const int qc = live[i] ? q : PL - 1;
     const int p = qc % EXP, r = qc / EXP;
-    const int xb = X0 - 2 * HP + 2 * p;
-    const int y = DIM == 3 ? Y0 - HY + r : 0;
+    const int xb = X0 - 2 * HPL + 2 * p;
+    const int y = DIM == 3 ? Y0 - HYL + r : 0;
     const bool yin = DIM == 2 || (y >= 0 && y < m);
     const int par = (y + DIM) & 1;
     const int off = (DIM == 3 ? y * m : 0) + xb;
     const bool in0 = live[i] && yin && xb >= 0 && xb < m;
     const bool in1 = live[i] && yin && xb + 1 >= 0 && xb + 1 < m;
-    const bool outp = live[i] && yin && p >= HP && p < HP + TXP &&
-                      (DIM == 2 || (r >= HY && r < HY + TY)) && xb < m;
+    const bool outp = live[i] && yin && p >= HPL && p < HPL + TXP &&
+                      (DIM == 2 || (r >= HYL && r < HYL + TY)) && xb < m;
     const int o0 = in0 ? off * (int)sizeof(T) : kOOB;
     const int o1 = in1 ? (off + 1) * (int)sizeof(T) : kOOB;
     const bool half = in0 && !in1;
@@ -351,8 +353,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   // p reads coarse columns p (left) and p + 1 (right); an odd row r of the
   // extended tile lies on coarse row (r + 1) / 2, an even one halfway between
   // rows r / 2 and r / 2 + 1.
-  const int CX0 = ((X0 - 2 * HP) >> 1) - 1;
-  const int CY0 = DIM == 3 ? ((Y0 - HY) >> 1) - 1 : 0;
+  const int CX0 = ((X0 - 2 * HPL) >> 1) - 1;
+  const int CY0 = DIM == 3 ? ((Y0 - HYL) >> 1) - 1 : 0;
   const int cplane = DIM == 3 ? mc * mc : mc;
   int coff[NCP];
   if (PRO) {
@@ -421,7 +423,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   const int ccx = threadIdx.x % TXP, ccy = DIM == 3 ? threadIdx.x / TXP : 0;
   const int cgx = (X0 >> 1) + ccx, cgy = DIM == 3 ? (Y0 >> 1) + ccy : 0;
   const bool cown = RST && (int)threadIdx.x < NCC && cgx < mc && (DIM == 2 || cgy < mc);
-  const int cq = (DIM == 3 ? (HY + 2 * ccy + 1) * EXP : 0) + HP + ccx;  // slot of the centre
+  const int cq = (DIM == 3 ? (HYL + 2 * ccy + 1) * EXP : 0) + HPL + ccx;  // slot of the centre
   T cacc = T(0);
   static_assert(!RST || NCC <= NT, "one thread per coarse point");
   // PRO: coarse plane (t + 1) / 2 for the odd step t, loaded at the odd step
@@ -1006,9 +1008,11 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
 #define GMG_RB3_S4(X) X(3, 4, 36, 28, 1024) X(3, 4, 36, 24, 256) X(3, 4, 68, 22, 512) X(3, 4, 36, 24, 896)
 // Three stages (black, red, black): the pass that ends one cycle's backward
 // V(1,1) post-smoothing and starts the next cycle's forward sweep.
+// (Tiles with an even row count run the plain form, odd ones the form with
+// the restriction folded in: its halo is one row taller on the high side.)
 #define GMG_RB3_S3(X) \
   X(3, 3, 34, 30, 1024) X(3, 3, 36, 28, 1024) X(3, 3, 66, 30, 1024) X(3, 3, 34, 30, 512) \
-  X(3, 3, 66, 14, 512)
+  X(3, 3, 66, 14, 512) X(3, 3, 34, 29, 1024) X(3, 3, 36, 27, 1024) X(3, 3, 33, 31, 1024)
 #define GMG_RB2_S3(X) X(2, 3, 64, 1, 64) X(2, 3, 128, 1, 128)
 #define GMG_RB2_S2(X) X(2, 2, 64, 1, 64) X(2, 2, 128, 1, 128)
 #define GMG_RB2_S4(X) X(2, 4, 64, 1, 64) X(2, 4, 128, 1, 128)
@@ -1077,24 +1081,28 @@ size_t rb_pass_lds_bytes(int dim, int stages, int exp_, int ey, int flags, size_
   const size_t pl = (size_t)exp_ * ey;
   size_t n = 2 * pl * (size_t)(stages + ((flags & F_NORM_IN) ? 1 : 0));
   if (flags & F_RESTRICT) n += 8 * pl;
-  if (flags & F_PROLONG) n += 2 * (size_t)(exp_ + 1) * (dim == 3 ? ey / 2 + 1 : 1);
+  if (flags & F_PROLONG) n += 2 * (size_t)(exp_ + 1) * (dim == 3 ? (ey + 1) / 2 + 1 : 1);
   return n * elem;
 }
 
 bool rb_pass_fits(int dim, int stages, int variant, int flags, size_t elem) {
   const PassTile t = pass_variant(dim, stages, 0, variant);
-  return t.nt > 0 && rb_pass_lds_bytes(dim, stages, t.exp_, t.ey, flags, elem) <= kMaxPassLds;
+  if (t.nt == 0) return false;
+  const RbHalo h = rb_halo(stages, (flags & F_RESTRICT) != 0);
+  const int txp = t.exp_ - h.pl - h.ph, ty = dim == 3 ? t.ey - h.yl - h.yh : 2;
+  return txp > 0 && ty > 0 && ty % 2 == 0 &&
+         rb_pass_lds_bytes(dim, stages, t.exp_, t.ey, flags, elem) <= kMaxPassLds;
 }
 
 PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz, bool restrict_) {
-  // halo in points: S for red-black, rounded up to a pair for Jacobi; a pass
-  // that also restricts carries one more pair and two more rows
-  const int hp = (stages + 1) / 2 + (restrict_ ? 1 : 0);
-  const int tx = 2 * (t.exp_ - 2 * hp);
+  // the red-black halo (rb_halo); Jacobi passes use the plain one (S points
+  // rounded up to a pair on each side)
+  const RbHalo h = rb_halo(stages, restrict_);
+  const int tx = 2 * (t.exp_ - h.pl - h.ph);
   PassGeom g;
   g.ntx = (m + tx - 1) / tx;
   if (dim == 3) {
-    const int ty = t.ey - 4 * hp;
+    const int ty = t.ey - h.yl - h.yh;
     g.nty = (m + ty - 1) / ty;
   } else {
     g.nty = 1;
@@ -1109,6 +1117,11 @@ PassGeom pass_geometry(int dim, int m, int stages, const PassTile &t, int tz, bo
 namespace {
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
 hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nent) {
+  constexpr RbHalo h = rb_halo(S, (FL & F_RESTRICT) != 0);
+  constexpr int txp = EXP - h.pl - h.ph, ty = DIM == 3 ? EY - h.yl - h.yh : 2;
+  if constexpr (txp <= 0 || ty <= 0 || ty % 2 != 0) {
+    return hipErrorInvalidValue;  // this tile does not run this form
+  } else {
   const size_t lds = rb_pass_lds_bytes(DIM, S, EXP, EY, FL, sizeof(T));
   if (lds > kMaxPassLds) return hipErrorInvalidConfiguration;
   auto k = k_rb_pass<T, DIM, S, EXP, EY, NT, FL>;
@@ -1121,6 +1134,7 @@ hipError_t run_rb(PassArgs<T> a, hipStream_t st, const PassArgs<T> *tbl, int nen
   }
   gmg_launch(k, dim3(a.nblocks, nent), dim3(NT), lds, st, a, tbl);
   return hipGetLastError();
+  }
 }
 
 template <typename T, int DIM, int S, int EXP, int EY, int NT, int FL>
