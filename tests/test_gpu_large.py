@@ -140,7 +140,7 @@ def test_1023_fp64_solve_matches_oracle(big, big_oracle):
 def test_1023_mixed_reaches_1e10_by_oracle_residual(big, big_oracle):
     fd, f = big
     ur = big_oracle[0]
-    plan = tuned_plan(3, 10, nu1=1, nu2=1, precision="mixed", inner_cycles=2)
+    plan = tuned_plan(3, 10, nu1=1, nu2=1, precision="mixed")  # default inner cycles
     u = torch.zeros_like(fd)
     plan.solve(u, fd, rtol=1e-10)
     u.zero_()
