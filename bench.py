@@ -509,6 +509,17 @@ def main():
         t_total += t_each[-1]
         iters.append(it)
     prof = plan.profile()
+    # the same solves with no dispatch events at all: what the events of the
+    # timed region cost
+    plan.profile_only([])
+    t_plain = []
+    for _ in range(max(1, min(args.steps, 5))):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(u, f, rtol=rtol)
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
     ms_per_step = 1e3 * t_total / args.steps
     value = N / (t_total / args.steps)
     dom = max(smoothers, key=lambda k: prof[k]["ms"])
@@ -548,6 +559,7 @@ def main():
         "ms_per_step": ms_per_step,
         "ms_median": 1e3 * sorted(t_each)[len(t_each) // 2],
         "ms_min": 1e3 * min(t_each),
+        "ms_no_events": 1e3 * sum(t_plain) / len(t_plain),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

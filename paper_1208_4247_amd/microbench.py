@@ -312,6 +312,102 @@ def trace_report(trace_csv, title, active_us=5.0):
     print("\n".join(out))
 
 
+def solve_run(dim, m, cycles, nu=1, precision="fp64"):
+    """An autotuned solve of the bench's sine-modes right-hand side cut at
+    `cycles` cycles (rtol 1e-30), after one warm-up solve that tunes (or
+    reads GMG_TUNE_CACHE): the dispatches a counter profiler sees are those
+    of a production solve of this size."""
+    from . import capi
+    from . import workloads as wl
+
+    L = (m + 1).bit_length() - 1
+    f = wl.rhs_sine_modes_device(dim, m, 5, "cuda")
+    u = torch.zeros_like(f)
+    plan = Plan(dim, L, nu1=nu, nu2=nu, precision=precision, flags=capi.GMG_AUTOTUNE)
+    plan.solve(u, f, rtol=1e-30, maxit=2)
+    torch.cuda.synchronize()
+    u.zero_()
+    st, it, rel = plan.solve(u, f, rtol=1e-30, maxit=cycles)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(solve_run=True, dim=dim, m=m, cycles=it, relres=rel,
+                          level0_tiles=[plan.get_tile(0, r) for r in (0, 1)])), flush=True)
+
+
+def counter_report(pmc_csvs, kernel_regex, title, points, clock_ghz=2.4,
+                   active_us=5.0, cus=256):
+    """Counters of rocprofv3 --pmc runs, each with --kernel-trace (its
+    kernel_trace CSV beside the counter CSV gives every dispatch its
+    duration), for the kernels matching kernel_regex that did work (longer
+    than active_us), as markdown: the mean
+    of every counter per dispatch, and per fine point (points per dispatch)
+    the lane-instruction counts; the time the VALU instructions alone need
+    at one wave-instruction per 4 cycles per SIMD (FP64 and unpacked FP32
+    run 16 lanes a cycle), the LDS bank-conflict cycles per CU, and the
+    texture-address unit's busy share, against the measured duration."""
+    import collections
+    import csv
+    import re
+
+    def rows(path):
+        return list(csv.DictReader(open(path)))
+
+    groups = collections.OrderedDict()
+    for path in pmc_csvs:
+        tr = {}
+        tpath = path.replace("counter_collection", "kernel_trace")
+        for r in rows(tpath):
+            tr[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        for r in rows(path):
+            if not re.search(kernel_regex, r["Kernel_Name"]):
+                continue
+            us = tr.get(r["Dispatch_Id"])
+            if us is None or us < active_us:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("gmg::", "")
+            grid = int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0)
+            g = groups.setdefault((name, grid), collections.defaultdict(list))
+            g[r["Counter_Name"]].append(float(r["Counter_Value"]))
+            g["__us"].append((path, r["Dispatch_Id"], us))
+    out = ["# %s" % title, "",
+           "Means per dispatch longer than %.0f us. Per point: lane instructions "
+           "(wave instructions x 64) per fine point, %d points per dispatch. Clock: "
+           "GRBM_GUI_ACTIVE / (8 XCDs x duration) where counted, else %.1f GHz. VALU floor: "
+           "SQ_INSTS_VALU x 4 cycles / (4 SIMDs x %d CUs) at that clock. LDS conflict: "
+           "SQ_LDS_BANK_CONFLICT / %d CUs at that clock. TA busy: TA_TA_BUSY / (%d x duration "
+           "x clock)." % (active_us, points, clock_ghz, cus, cus, cus), ""]
+    for (name, grid), g in groups.items():
+        usl = list(set(g["__us"]))  # one entry per dispatch of each run
+        us = sum(v[2] for v in usl) / len(usl)
+        mean = {k: sum(v) / len(v) for k, v in g.items() if k != "__us"}
+        out += ["## `%s`, grid %d" % (name, grid), "",
+                "duration under the counter runs: %.1f us (mean of %d dispatches in %d runs)" % (
+                    us, len(usl), len(pmc_csvs)),
+                "", "| counter | mean per dispatch | per fine point |", "|---|---|---|"]
+        for k in sorted(mean):
+            pp = mean[k] * 64 / points if k.startswith("SQ_INSTS") else mean[k] / points
+            out.append("| %s | %.4g | %.3f |" % (k, mean[k], pp))
+        out.append("")
+        cyc = clock_ghz * 1e3  # cycles per microsecond at the rated clock
+        if "GRBM_GUI_ACTIVE" in mean:
+            # GRBM_GUI_ACTIVE sums the XCDs' active cycles: its rate over
+            # the dispatch is 8 x the shader clock
+            cyc = mean["GRBM_GUI_ACTIVE"] / (8 * us)
+            out.append("- mean shader clock GRBM_GUI_ACTIVE / (8 x duration): %.2f GHz" % (
+                cyc / 1e3))
+        if "SQ_INSTS_VALU" in mean:
+            fl = mean["SQ_INSTS_VALU"] * 4 / (4 * cus) / cyc
+            out.append("- VALU floor at that clock %.1f us = %.0f%% of the duration" % (
+                fl, 100 * fl / us))
+        if "SQ_LDS_BANK_CONFLICT" in mean:
+            lc = mean["SQ_LDS_BANK_CONFLICT"] / cus / cyc
+            out.append("- LDS bank-conflict cycles per CU: %.1f us = %.0f%% of the duration" % (
+                lc, 100 * lc / us))
+        if "TA_TA_BUSY" in mean:
+            out.append("- TA busy %.0f%%" % (100 * mean["TA_TA_BUSY"] / cus / (us * cyc)))
+        out.append("")
+    print("\n".join(out))
+
+
 def copy_calibration(mib, reps=20):
     """A plain device copy of known size (torch's copy kernel): the yardstick
     that converts the HBM byte counters of a profiler into bytes.  Also
@@ -361,10 +457,25 @@ def main():
                     help="markdown per-kernel summary of a rocprofv3 kernel trace")
     ap.add_argument("--kernel-regex", default=r"k_rb_pass<double, 3, 3,")
     ap.add_argument("--title", default="HBM traffic of the cross-cycle pass")
+    ap.add_argument("--solve-cycles", type=int, default=0,
+                    help="one autotuned solve of the sine-modes problem cut at this many cycles")
+    ap.add_argument("--counter-report", nargs="+", metavar="CSV",
+                    help="counter_collection CSVs of --pmc --kernel-trace runs")
+    ap.add_argument("--points", type=int, default=1023 ** 3)
+    ap.add_argument("--active-us", type=float, default=5.0,
+                    help="counter report: keep dispatches at least this long")
     ap.add_argument("--traffic-table", action="store_true",
                     help="launch every autotuner candidate of the level-0 passes twice "
                     "(for a counter profiler)")
     a = ap.parse_args()
+    if a.solve_cycles:
+        for m in a.m:
+            solve_run(a.dim, m, a.solve_cycles)
+        return
+    if a.counter_report:
+        counter_report(a.counter_report, a.kernel_regex, a.title, a.points,
+                       active_us=a.active_us)
+        return
     if a.cross_sweep:
         for m in a.m:
             cross_sweep(a.dim, m, tuple(a.strips), a.variants,
