@@ -16,6 +16,15 @@
 // Dirichlet zeros come for free.  In-place red-black Gauss-Seidel is
 // race-free because a colour's updates only read the other colour and every
 // colour ends with a barrier.
+//
+// Every step of a level is a pass over its points followed by a barrier, and
+// on the smallest levels the barrier is most of the cost: a step of a level
+// with a handful of points takes as long as one of a level with a thousand.
+// The levels whose every step fits one wavefront (one point per lane: side
+// <= 7 in 2D, <= 3 in 3D) therefore run in wavefront 0 alone, synchronised
+// by waiting for its own LDS operations, while the other wavefronts wait at
+// one barrier for the whole sub-cycle.  Each point is computed by the same
+// expression either way.
 #include "gmg_internal.h"
 
 namespace gmg {
@@ -36,15 +45,30 @@ __device__ __forceinline__ BL bl_make(int dim, int L, int l) {
   return b;
 }
 
+// The threads that run a step and how a step ends.  W = false: the whole
+// workgroup, ending with a barrier.  W = true: wavefront 0 alone (lane =
+// threadIdx.x < 64), ending when its LDS operations have completed; the
+// "memory" clobber keeps the compiler from moving LDS accesses across it.
+template <bool W>
+struct Team {
+  static __device__ __forceinline__ int stride() { return W ? 64 : (int)blockDim.x; }
+  static __device__ __forceinline__ void sync() {
+    if (W)
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else
+      __syncthreads();
+  }
+};
+
 // one colour of red-black Gauss-Seidel on an LDS level
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 __device__ void b_rb_colour(const BL &b, T *u, const T *f, int colour, T h2) {
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const int half = b.n >> 1;
   const int rows = DIM == 3 ? b.n * b.m : b.m;  // (y incl. pad row) x z, or y
   const int total = half * rows;
   const int sy = b.n, sz = b.n * b.n;
-  for (int h = threadIdx.x; h < total; h += blockDim.x) {
+  for (int h = threadIdx.x; h < total; h += Team<W>::stride()) {
     const int j = h & (half - 1);
     const int row = h >> (b.k - 1);
     int y, z;
@@ -68,14 +92,14 @@ __device__ void b_rb_colour(const BL &b, T *u, const T *f, int colour, T h2) {
     }
     u[i] = fma(h2, f[i], nb) * inv2d;
   }
-  __syncthreads();
+  Team<W>::sync();
 }
 
 // visit every interior point of a level: fn(i, x, y, z)
-template <int DIM, typename F>
+template <int DIM, bool W = false, typename F>
 __device__ __forceinline__ void b_for_all(const BL &b, F fn) {
   const int total = DIM == 3 ? b.m * b.n * b.n : b.m * b.n;
-  for (int h = threadIdx.x; h < total; h += blockDim.x) {
+  for (int h = threadIdx.x; h < total; h += Team<W>::stride()) {
     const int x = h & (b.n - 1);
     const int y = DIM == 3 ? (h >> b.k) & (b.n - 1) : h >> b.k;
     const int z = DIM == 3 ? h >> (2 * b.k) : 0;
@@ -85,11 +109,11 @@ __device__ __forceinline__ void b_for_all(const BL &b, F fn) {
   }
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 __device__ void b_wj(const BL &b, T *u, const T *f, T *tmp, T h2, T omega) {
   const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const int sy = b.n, sz = b.n * b.n;
-  b_for_all<DIM>(b, [&](int i, int, int, int) {
+  b_for_all<DIM, W>(b, [&](int i, int, int, int) {
     T nb = u[i - 1] + u[i + 1];
     nb += u[i - sy];
     nb += u[i + sy];
@@ -99,32 +123,33 @@ __device__ void b_wj(const BL &b, T *u, const T *f, T *tmp, T h2, T omega) {
     }
     tmp[i] = (T(1) - omega) * u[i] + omega * (fma(h2, f[i], nb) * inv2d);
   });
-  __syncthreads();
-  b_for_all<DIM>(b, [&](int i, int, int, int) { u[i] = tmp[i]; });
-  __syncthreads();
+  Team<W>::sync();
+  b_for_all<DIM, W>(b, [&](int i, int, int, int) { u[i] = tmp[i]; });
+  Team<W>::sync();
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool W>
 __device__ void b_smooth(const BL &b, T *u, const T *f, T *tmp, int nsw, bool black_first,
                          int smoother, T omega) {
-  const T h = T(1) / T(b.n);
+  // h = 1/n with n = 2^k: h and h^2 are exact powers of two
+  const T h = ldexp(T(1), -b.k);
   const T h2 = h * h;
   for (int s = 0; s < nsw; ++s) {
     if (smoother == 0) {
-      b_rb_colour<T, DIM>(b, u, f, black_first ? 1 : 0, h2);
-      b_rb_colour<T, DIM>(b, u, f, black_first ? 0 : 1, h2);
+      b_rb_colour<T, DIM, W>(b, u, f, black_first ? 1 : 0, h2);
+      b_rb_colour<T, DIM, W>(b, u, f, black_first ? 0 : 1, h2);
     } else {
-      b_wj<T, DIM>(b, u, f, tmp, h2, omega);
+      b_wj<T, DIM, W>(b, u, f, tmp, h2, omega);
     }
   }
 }
 
 // fc = FW(f - A u): the residual goes to r (LDS scratch) first
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __device__ void b_restrict(const BL &F, const T *u, const T *f, T *r, const BL &C, T *fc) {
   const T inv_h2 = T(F.n) * T(F.n);
   const int sy = F.n, sz = F.n * F.n;
-  b_for_all<DIM>(F, [&](int i, int, int, int) {
+  b_for_all<DIM, W>(F, [&](int i, int, int, int) {
     T nb = u[i - 1] + u[i + 1];
     nb += u[i - sy];
     nb += u[i + sy];
@@ -134,8 +159,8 @@ __device__ void b_restrict(const BL &F, const T *u, const T *f, T *r, const BL &
     }
     r[i] = f[i] - (T(2 * DIM) * u[i] - nb) * inv_h2;
   });
-  __syncthreads();
-  b_for_all<DIM>(C, [&](int ic, int a, int bb, int c) {
+  Team<W>::sync();
+  b_for_all<DIM, W>(C, [&](int ic, int a, int bb, int c) {
     // fine centre (2a+1, 2b+1, 2c+1)
     const int i = DIM == 3 ? ((2 * c + 2) * F.n + 2 * bb + 1) * F.n + 2 * a + 1
                            : (2 * bb + 2) * F.n + 2 * a + 1;
@@ -146,14 +171,14 @@ __device__ void b_restrict(const BL &F, const T *u, const T *f, T *r, const BL &
     fc[ic] = DIM == 3 ? T(0.25) * plane(i - sz) + T(0.5) * plane(i) + T(0.25) * plane(i + sz)
                       : plane(i);
   });
-  __syncthreads();
+  Team<W>::sync();
 }
 
 // u_F += P u_C (linear interpolation; coarse pads supply the boundary zeros)
-template <typename T, int DIM>
+template <typename T, int DIM, bool W = false>
 __device__ void b_prolong(const BL &F, T *u, const BL &C, const T *uc) {
   const int sy = C.n, sz = C.n * C.n;
-  b_for_all<DIM>(F, [&](int i, int x, int y, int z) {
+  b_for_all<DIM, W>(F, [&](int i, int x, int y, int z) {
     // per axis: fine storage x odd -> coarse storage (x-1)/2; even -> x/2-1 and x/2
     const int cx = (x - 1) >> 1, cy = (y - 1) >> 1, cz = (z - 1) >> 1;
     const bool ox = x & 1, oy = y & 1, oz = z & 1;
@@ -168,7 +193,7 @@ __device__ void b_prolong(const BL &F, T *u, const BL &C, const T *uc) {
       s = ys(ci);
     u[i] += s;
   });
-  __syncthreads();
+  Team<W>::sync();
 }
 
 // element offset of level l's u array (f follows it); levels are packed
@@ -179,40 +204,75 @@ __device__ __forceinline__ int bl_offset(int dim, int L, int l) {
   return off;
 }
 
-// One V-cycle (Algorithm 1) on the levels top .. L-1 of the LDS hierarchy,
-// from the start value held in level top's u; the coarser levels start from
-// zero (cleared here when `clear`, otherwise already zero).
-template <typename T, int DIM>
-__device__ void b_vcycle(const BottomArgs<T> &a, T *sm, T *R, int L, int top, bool clear) {
+// Levels of the bottom hierarchy run by wavefront 0 alone: those whose side
+// is at most 7 (2D) or 3 (3D), so that every step has at most one point per
+// lane (a colour of a 7 x 7 level has 28 points, the level with its pad
+// column 56; a 3^3 level with pads 48).
+__device__ __forceinline__ int bl_first_small(int dim, int L) {
+  return max(0, L - (dim == 3 ? 2 : 3));
+}
+
+// Descent on the levels lo .. hi-1 (smooth from the start value in u, then
+// restrict onto level l+1), run by team W.
+template <typename T, int DIM, bool W>
+__device__ void b_descend(const BottomArgs<T> &a, T *sm, T *R, int L, int lo, int hi, int top,
+                          bool clear) {
   const T omega = T(a.omega);
-  for (int l = top; l + 1 < L; ++l) {
+  for (int l = lo; l < hi; ++l) {
     const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
     T *U = sm + bl_offset(DIM, L, l);
     T *F = U + b.size;
     T *Fc = sm + bl_offset(DIM, L, l + 1) + c.size;
     if (clear && l > top) {
-      b_for_all<DIM>(b, [&](int i, int, int, int) { U[i] = T(0); });
-      __syncthreads();
+      b_for_all<DIM, W>(b, [&](int i, int, int, int) { U[i] = T(0); });
+      Team<W>::sync();
     }
-    b_smooth<T, DIM>(b, U, F, R, a.nu1, false, a.smoother, omega);
-    b_restrict<T, DIM>(b, U, F, R, c, Fc);
+    b_smooth<T, DIM, W>(b, U, F, R, a.nu1, false, a.smoother, omega);
+    b_restrict<T, DIM, W>(b, U, F, R, c, Fc);
   }
-  if (threadIdx.x == 0) {  // one-node level: 2d u / h^2 = f, in FP64
-    const BL c = bl_make(DIM, L, L - 1);
-    T *U = sm + bl_offset(DIM, L, L - 1);
-    const int i = DIM == 3 ? c.n * c.n : c.n;  // element (0,0[,0])
-    const double h = 1.0 / double(c.n);
-    U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
-  }
-  __syncthreads();
-  for (int l = L - 2; l >= top; --l) {
+}
+
+// Ascent on the levels hi-1 down to lo (interpolate and add the correction
+// from level l+1, then smooth), run by team W.
+template <typename T, int DIM, bool W>
+__device__ void b_ascend(const BottomArgs<T> &a, T *sm, T *R, int L, int lo, int hi) {
+  const T omega = T(a.omega);
+  for (int l = hi - 1; l >= lo; --l) {
     const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
     T *U = sm + bl_offset(DIM, L, l);
     T *F = U + b.size;
     const T *Uc = sm + bl_offset(DIM, L, l + 1);
-    b_prolong<T, DIM>(b, U, c, Uc);
-    b_smooth<T, DIM>(b, U, F, R, a.nu2, !a.post_forward, a.smoother, omega);
+    b_prolong<T, DIM, W>(b, U, c, Uc);
+    b_smooth<T, DIM, W>(b, U, F, R, a.nu2, !a.post_forward, a.smoother, omega);
   }
+}
+
+// one-node level: 2d u / h^2 = f, in FP64 (one lane)
+template <typename T, int DIM>
+__device__ __forceinline__ void b_coarsest(T *sm, int L) {
+  const BL c = bl_make(DIM, L, L - 1);
+  T *U = sm + bl_offset(DIM, L, L - 1);
+  const int i = DIM == 3 ? c.n * c.n : c.n;  // element (0,0[,0])
+  const double h = 1.0 / double(c.n);
+  U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
+}
+
+// One V-cycle (Algorithm 1) on the levels top .. L-1 of the LDS hierarchy,
+// from the start value held in level top's u; the coarser levels start from
+// zero (cleared here when `clear`, otherwise already zero).  The levels from
+// bl_first_small down, and the one-node level, run in wavefront 0.
+template <typename T, int DIM>
+__device__ void b_vcycle(const BottomArgs<T> &a, T *sm, T *R, int L, int top, bool clear) {
+  const int ls = max(top, bl_first_small(DIM, L));
+  b_descend<T, DIM, false>(a, sm, R, L, top, ls, top, clear);
+  if (threadIdx.x < 64) {
+    b_descend<T, DIM, true>(a, sm, R, L, ls, L - 1, top, clear);
+    if (threadIdx.x == 0) b_coarsest<T, DIM>(sm, L);
+    Team<true>::sync();
+    b_ascend<T, DIM, true>(a, sm, R, L, ls, L - 1);
+  }
+  __syncthreads();
+  b_ascend<T, DIM, false>(a, sm, R, L, top, ls);
 }
 
 template <typename T, int DIM>
@@ -242,13 +302,7 @@ __device__ void bottom_body(const BottomArgs<T> &a, const GMG_GLOBAL T *fin, GMG
       T *U = sm + bl_offset(DIM, L, l);
       b_restrict<T, DIM>(b, U, U + b.size, R, c, sm + bl_offset(DIM, L, l + 1) + c.size);
     }
-    if (threadIdx.x == 0) {
-      const BL c = bl_make(DIM, L, L - 1);
-      T *U = sm + bl_offset(DIM, L, L - 1);
-      const int i = DIM == 3 ? c.n * c.n : c.n;
-      const double h = 1.0 / double(c.n);
-      U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
-    }
+    if (threadIdx.x == 0) b_coarsest<T, DIM>(sm, L);
     __syncthreads();
     for (int l = L - 2; l >= 0; --l) {
       const BL b = bl_make(DIM, L, l), c = bl_make(DIM, L, l + 1);
