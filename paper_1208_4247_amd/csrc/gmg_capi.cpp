@@ -1641,12 +1641,45 @@ struct ChainEnt {
   double *src, *ec, *f, *dst, *tmp;
   bool src_user, f_user, dst_user;
   double *partials;
+  double *fc = nullptr;  // the coarse right-hand side, when the last pass restricts
 };
 
 PassChoice batch_choice(const gmg_plan *p, const Batch *b, int dim, int m, int role);
 
+// Sweeps of the last pass of a chain of nu sweeps in passes of at most smax
+// (the split build_chain and smooth_chain make), and the pass count.
+int last_pass_sweeps(int nu, int smax, int *npasses) {
+  const int K = (nu + smax - 1) / smax;
+  int left = nu, last = 0;
+  for (int k = 1; k <= K; ++k) {
+    last = std::min(smax, left - (K - k));
+    left -= last;
+  }
+  if (npasses) *npasses = K;
+  return last;
+}
+
+// Whether the pre-smoothing chains of the level size (dim, m) whose first
+// pass has first_flags end in a pass that also restricts, as single
+// problems do: red-black, the choice asks for it, the tile runs that form
+// and its workgroups fit a problem's partial-sum slice.
+bool batch_fold(const gmg_plan *p, const Batch *b, int dim, int m, int nu, int first_flags) {
+  if (p->cfg.smoother != GMG_SMOOTH_RBGS || (p->cfg.flags & GMG_NO_FUSED_RESTRICT) || nu < 1)
+    return false;
+  // the sizing build keeps every restriction entry: folding only removes
+  // entries, so its table bounds that of any choice
+  if (b->worst) return false;
+  const PassChoice c = batch_choice(p, b, dim, m, 0);
+  if (!c.fuse) return false;
+  int K = 0;
+  const int st = 2 * last_pass_sweeps(nu, c.smax, &K);
+  const PassTile t = pass_variant(dim, st, 0, c.var[st]);
+  if (pass_geometry(dim, m, st, t, c.tz[st], true).nblocks > kMaxPartials) return false;
+  return rb_pass_fits(dim, st, c.var[st], F_RESTRICT | (K == 1 ? first_flags : 0), sizeof(double));
+}
+
 void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_flags, bool backward,
-                 const std::vector<ChainEnt> &ents, int cls) {
+                 const std::vector<ChainEnt> &ents, int cls, bool fold = false) {
   gmg_plan *p = bb.p;
   Batch *b = bb.b;
   if (ents.empty() || nu == 0) return;
@@ -1661,9 +1694,11 @@ void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_f
     const int st = wj ? sw : 2 * sw;
     const int v = c.var[st];
     const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
-    const PassGeom g = pass_geometry(dim, m, st, t, c.tz[st]);
+    const bool rst = fold && k == K;  // the last pass restricts onto f_c
+    const PassGeom g = pass_geometry(dim, m, st, t, c.tz[st], rst);
     int flags = backward ? F_BLACK_FIRST : 0;
     if (k == 1) flags |= first_flags;
+    if (rst) flags |= F_RESTRICT;
     BOp op;
     op.kind = BO_PASS;
     op.dim = dim;
@@ -1685,6 +1720,7 @@ void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_f
       a.f = e.f;
       a.u_out = out_of(k);
       a.e_c = k == 1 ? e.ec : nullptr;
+      a.f_c = rst ? e.fc : nullptr;
       a.partials = (k == 1 && (first_flags & F_NORM_IN)) ? e.partials : nullptr;
       a.active = &b->pb[e.q].st->active;
       a.m = m;
@@ -1702,6 +1738,7 @@ void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_f
       if (e.f_user) b->patches.push_back({off + offsetof(PassArgs<double>, f), e.q, 1});
       if (out_user(k)) b->patches.push_back({off + offsetof(PassArgs<double>, u_out), e.q, 0});
       op.bytes += (double)npts(dim, m) * 8.0 * ((k == 1 && (first_flags & F_ZERO_IN)) ? 2 : 3);
+      if (rst) op.bytes += (double)npts(dim, mc) * 8.0;
     }
     b->ops.push_back(op);
     left -= sw;
@@ -1754,7 +1791,8 @@ int max_first_pass_blocks(const gmg_plan *p, int dim, int m) {
       const PassTile t = pass_variant(dim, st, wj ? 1 : 0, v);
       for (int tz : {1, 2, 4, 8, 16, 32, 64, 0}) {  // every z-chunk a choice may hold
         const int tzv = tz > 0 ? std::min(tz, m) : auto_tz(dim, m, st, t);
-        mx = std::max(mx, pass_geometry(dim, m, st, t, tzv).nblocks);
+        for (bool rst : {false, true})  // (with the restriction folded in: larger halo)
+          mx = std::max(mx, pass_geometry(dim, m, st, t, tzv, rst).nblocks);
       }
     }
   }
@@ -1767,7 +1805,9 @@ int first_pass_blocks(const gmg_plan *p, const Batch *b, int dim, int m, int nu)
   const int K = (nu + c.smax - 1) / c.smax;
   const int sw = std::min(c.smax, nu - (K - 1));
   const int st = wj ? sw : 2 * sw;
-  return pass_geometry(dim, m, st, pass_variant(dim, st, wj ? 1 : 0, c.var[st]), c.tz[st]).nblocks;
+  const bool rst = K == 1 && batch_fold(p, b, dim, m, nu, F_NORM_IN);
+  return pass_geometry(dim, m, st, pass_variant(dim, st, wj ? 1 : 0, c.var[st]), c.tz[st], rst)
+      .nblocks;
 }
 
 // Lay out the workspace and build the launch list.  ws == nullptr: sizing
@@ -1835,14 +1875,16 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
         if (l < 0 || l >= pr.B) continue;
         if (l == 0) {
           top.push_back({q, 0, nullptr, nullptr, nullptr, pr.w[0], pr.t[0], true, true, false,
-                         pr.partials});
+                         pr.partials, pr.f[1]});
           tops.push_back(q);
         } else {
           coarse.push_back({q, l, nullptr, nullptr, pr.f[l], pr.w[l], pr.t[l], false, false,
-                            false, nullptr});
+                            false, nullptr, pr.f[l + 1]});
         }
       }
-      build_chain(bb, dim, m, 0, nu1, F_NORM_IN, false, top, PC_PRE0);
+      const bool fold_top = batch_fold(p, b, dim, m, nu1, F_NORM_IN);
+      const bool fold_coarse = batch_fold(p, b, dim, m, nu1, F_ZERO_IN);
+      build_chain(bb, dim, m, 0, nu1, F_NORM_IN, false, top, PC_PRE0, fold_top);
       if (!tops.empty()) {
         BOp op;
         op.kind = BO_FIN;
@@ -1856,10 +1898,12 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
       // the coarse descent takes the plane-marching passes as well: in a
       // batch the LDS-tile descent kernel is slower (256-problem batch 61
       // against 52 ms)
-      build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C);
-      // residual + restriction for every entry of this size
-      std::vector<ChainEnt> all = top;
-      all.insert(all.end(), coarse.begin(), coarse.end());
+      build_chain(bb, dim, m, 0, nu1, F_ZERO_IN, false, coarse, PC_PRE_C, fold_coarse);
+      // residual + restriction for every entry of this size whose last
+      // pre-smoothing pass did not restrict
+      std::vector<ChainEnt> all;
+      if (!fold_top) all = top;
+      if (!fold_coarse) all.insert(all.end(), coarse.begin(), coarse.end());
       if (!all.empty()) {
         BOp op;
         op.kind = BO_RESTRICT;
@@ -2093,7 +2137,7 @@ hipError_t batch_tune(gmg_plan *p, double *const *u, const double *const *f) {
     gmg_config c = p->cfg;
     c.dim = pr.dim;
     c.levels = pr.L;
-    c.flags = (c.flags & ~(unsigned)GMG_PROFILE) | GMG_NO_FUSED_RESTRICT;
+    c.flags = c.flags & ~(unsigned)GMG_PROFILE;
     gmg_plan v;
     init_plan_shape(v, &c);
     v.cross = false;
@@ -2112,9 +2156,7 @@ hipError_t batch_tune(gmg_plan *p, double *const *u, const double *const *f) {
     if (e != hipSuccess) return e;
     for (int l = 0; l < v.B && l + 1 < v.L; ++l)
       for (int r = 0; r < 2; ++r) {
-        PassChoice ch = v.ch[l][r];
-        ch.fuse = 0;
-        b->choice.emplace(std::array<int, 3>{pr.dim, pr.m[l], r}, ch);
+        b->choice.emplace(std::array<int, 3>{pr.dim, pr.m[l], r}, v.ch[l][r]);
       }
   }
   batch_build(p, b, n, dims.data(), levels.data(), p->ws);
