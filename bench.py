@@ -570,6 +570,10 @@ def main():
                    "rtol": rtol, "iters": iters[-1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     # traffic: rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch of this
+                     # tile, from the committed counter table of the same sources
+                     "traffic_source": (os.path.relpath(TRAFFIC_PROFILES[(args.workload, dom)],
+                                                        ROOT) if traffic is not None else None),
                      "kernel": dom, "avg_us": avg_us, "alg_bytes_per_launch": bytes_per_launch,
                      "tile": ({"stages": tile[0], "variant": tile[1], "tz": tile[2]} if tile
                               else None),

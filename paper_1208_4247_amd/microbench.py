@@ -408,6 +408,34 @@ def counter_report(pmc_csvs, kernel_regex, title, points, clock_ghz=2.4,
     print("\n".join(out))
 
 
+def batch_solves(nsolves):
+    """The bench's 256-problem batch (128 2D problems of side 2^k - 1,
+    k ~ U{6..10}, 128 3D with k ~ U{5..7}; U[-1,1) right-hand sides, seed 4;
+    FP64 V(2,2) to 1e-10 each; graph-captured cycles, autotuned): one solve
+    that tunes (or reads GMG_TUNE_CACHE), then nsolves timed solves."""
+    import time
+
+    from . import capi
+    from . import workloads as wl
+    from .solver import BatchPlan
+
+    probs = wl.batch_problems(4)
+    fs = [torch.from_numpy(wl.batch_rhs(4, q, d, m)).cuda() for q, (d, m) in enumerate(probs)]
+    us = [torch.zeros_like(f) for f in fs]
+    plan = BatchPlan([(d, (m + 1).bit_length() - 1) for d, m in probs],
+                     flags=capi.GMG_USE_GRAPH | capi.GMG_AUTOTUNE)
+    for k in range(nsolves + 1):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, its, rels, sts = plan.solve(us, fs)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(batch_solve=k, ms=1e3 * (time.perf_counter() - t0),
+                              min_cycles=min(its), max_cycles=max(its),
+                              all_converged=all(x == 0 for x in sts))), flush=True)
+
+
 def copy_calibration(mib, reps=20):
     """A plain device copy of known size (torch's copy kernel): the yardstick
     that converts the HBM byte counters of a profiler into bytes.  Also
@@ -457,6 +485,8 @@ def main():
                     help="markdown per-kernel summary of a rocprofv3 kernel trace")
     ap.add_argument("--kernel-regex", default=r"k_rb_pass<double, 3, 3,")
     ap.add_argument("--title", default="HBM traffic of the cross-cycle pass")
+    ap.add_argument("--batch-solves", type=int, default=0,
+                    help="the 256-problem batch: a tuning solve, then this many solves")
     ap.add_argument("--solve-cycles", type=int, default=0,
                     help="one autotuned solve of the sine-modes problem cut at this many cycles")
     ap.add_argument("--counter-report", nargs="+", metavar="CSV",
@@ -468,6 +498,9 @@ def main():
                     help="launch every autotuner candidate of the level-0 passes twice "
                     "(for a counter profiler)")
     a = ap.parse_args()
+    if a.batch_solves:
+        batch_solves(a.batch_solves)
+        return
     if a.solve_cycles:
         for m in a.m:
             solve_run(a.dim, m, a.solve_cycles)
