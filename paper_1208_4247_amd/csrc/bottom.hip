@@ -257,26 +257,188 @@ __device__ __forceinline__ void b_coarsest(T *sm, int L) {
   U[i] = T((h * h * double(U[c.size + i])) / double(2 * DIM));
 }
 
+// ---- The smallest levels in registers (red-black smoothing) ---------------
+// A level with n = 2^k (side m = n - 1, n^DIM <= 64) maps one point to each
+// lane of wavefront 0: lane = (z n + y) n + x, x, y (, z) in [0, n), the
+// indices equal to m being the zero pads.  Neighbours come from other lanes
+// (__shfl), so a step is a few cross-lane reads and the point's arithmetic,
+// with no LDS round trip and no wait between steps.  Every expression is the
+// one the LDS steps above evaluate, in the same order, with zeros wherever
+// they read a pad.  Shuffles run on all lanes; the results are selected
+// afterwards.
+template <int DIM>
+struct RLev {
+  int n, m, x, y, z;
+  bool in;  // an interior point of this level
+};
+
+template <int DIM>
+__device__ __forceinline__ RLev<DIM> rl_make(int k) {
+  RLev<DIM> g;
+  const int lane = threadIdx.x;
+  g.n = 1 << k;
+  g.m = g.n - 1;
+  g.x = lane & (g.n - 1);
+  g.y = (lane >> k) & (g.n - 1);
+  g.z = DIM == 3 ? lane >> (2 * k) : 0;
+  const bool own = lane < (DIM == 3 ? g.n * g.n * g.n : g.n * g.n);
+  g.in = own && g.x < g.m && g.y < g.m && (DIM == 2 || g.z < g.m);
+  return g;
+}
+
+// the value of v in lane src, or zero when `ok` is false
+template <typename T>
+__device__ __forceinline__ T lane_val(T v, int src, bool ok) {
+  const T r = __shfl(v, src & 63);
+  return ok ? r : T(0);
+}
+
+// neighbour sum in the order of the LDS steps: x-1 + x+1, then y-1, y+1,
+// then z-1, z+1 (pads and indices below zero read as zero)
+template <typename T, int DIM>
+__device__ __forceinline__ T r_nbsum(const RLev<DIM> &g, T u) {
+  const int lane = threadIdx.x, sy = g.n, sz = g.n * g.n;
+  const T xm = lane_val(u, lane - 1, g.x > 0), xp = lane_val(u, lane + 1, g.x + 1 < g.m);
+  const T ym = lane_val(u, lane - sy, g.y > 0), yp = lane_val(u, lane + sy, g.y + 1 < g.m);
+  T nb = xm + xp;
+  nb += ym;
+  nb += yp;
+  if (DIM == 3) {
+    const T zm = lane_val(u, lane - sz, g.z > 0), zp = lane_val(u, lane + sz, g.z + 1 < g.m);
+    nb += zm;
+    nb += zp;
+  }
+  return nb;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T r_colour(const RLev<DIM> &g, T u, T f, int colour, T h2) {
+  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
+  const T nb = r_nbsum<T, DIM>(g, u);
+  const bool upd = g.in && ((g.x + g.y + g.z + DIM + colour) & 1) == 0;
+  return upd ? fma(h2, f, nb) * inv2d : u;
+}
+
+// full weighting of the fine level's residual onto the coarse lane's point
+template <typename T, int DIM>
+__device__ __forceinline__ T r_restrict(const RLev<DIM> &F, T u, T f, const RLev<DIM> &C) {
+  const T inv_h2 = T(F.n) * T(F.n);
+  const T nb = r_nbsum<T, DIM>(F, u);
+  const T r = F.in ? f - (T(2 * DIM) * u - nb) * inv_h2 : T(0);
+  const int sy = F.n, sz = F.n * F.n;
+  const int i = ((DIM == 3 ? (2 * C.z + 1) * F.n : 0) + 2 * C.y + 1) * F.n + 2 * C.x + 1;
+  auto R = [&](int j) { return __shfl(r, j & 63); };
+  auto rowsum = [&](int j) { return T(0.25) * R(j - 1) + T(0.5) * R(j) + T(0.25) * R(j + 1); };
+  auto plane = [&](int j) {
+    return T(0.25) * rowsum(j - sy) + T(0.5) * rowsum(j) + T(0.25) * rowsum(j + sy);
+  };
+  const T fc = DIM == 3 ? T(0.25) * plane(i - sz) + T(0.5) * plane(i) + T(0.25) * plane(i + sz)
+                        : plane(i);
+  return C.in ? fc : T(0);
+}
+
+// u + P uc (linear interpolation from the coarse lanes)
+template <typename T, int DIM>
+__device__ __forceinline__ T r_prolong(const RLev<DIM> &F, T u, const RLev<DIM> &C, T uc) {
+  const int cx = (F.x - 1) >> 1, cy = (F.y - 1) >> 1, cz = (F.z - 1) >> 1;
+  const bool ox = F.x & 1, oy = F.y & 1, oz = F.z & 1;
+  T v[2][2][2];  // coarse values at (cx + dx, cy + dy, cz + dz), zero outside
+#pragma unroll
+  for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int X = cx + dx, Y = cy + dy, Z = cz + dz;
+        const bool ok = X >= 0 && X < C.m && Y >= 0 && Y < C.m && (DIM == 2 || (Z >= 0 && Z < C.m));
+        v[dz][dy][dx] = lane_val(uc, ((DIM == 3 ? Z * C.n : 0) + Y) * C.n + X, ok);
+      }
+  auto xs = [&](int dz, int dy) {
+    return ox ? v[dz][dy][0] : T(0.5) * (v[dz][dy][0] + v[dz][dy][1]);
+  };
+  auto ys = [&](int dz) { return oy ? xs(dz, 0) : T(0.5) * (xs(dz, 0) + xs(dz, 1)); };
+  T s;
+  if (DIM == 3)
+    s = oz ? ys(0) : T(0.5) * (ys(0) + ys(1));
+  else
+    s = ys(0);
+  return F.in ? u + s : u;
+}
+
+// One V-cycle on D register levels from level side 2^k - 1 (start value u,
+// right-hand side f of this lane's point); D = 1 is the one-node level.
+template <typename T, int DIM, int D>
+__device__ __forceinline__ T r_vcycle(const BottomArgs<T> &a, int k, T u, T f) {
+  if constexpr (D == 1) {
+    const double h = 1.0 / double(1 << k);  // one-node level: 2d u / h^2 = f, in FP64
+    return threadIdx.x == 0 ? T((h * h * double(f)) / double(2 * DIM)) : T(0);
+  } else {
+    const RLev<DIM> F = rl_make<DIM>(k), C = rl_make<DIM>(k - 1);
+    const T h = ldexp(T(1), -k);
+    const T h2 = h * h;
+    for (int s = 0; s < a.nu1; ++s) {
+      u = r_colour<T, DIM>(F, u, f, 0, h2);
+      u = r_colour<T, DIM>(F, u, f, 1, h2);
+    }
+    const T fc = r_restrict<T, DIM>(F, u, f, C);
+    const T uc = r_vcycle<T, DIM, D - 1>(a, k - 1, T(0), fc);
+    u = r_prolong<T, DIM>(F, u, C, uc);
+    const int c0 = a.post_forward ? 0 : 1;
+    for (int s = 0; s < a.nu2; ++s) {
+      u = r_colour<T, DIM>(F, u, f, c0, h2);
+      u = r_colour<T, DIM>(F, u, f, 1 - c0, h2);
+    }
+    return u;
+  }
+}
+
+// The levels ls .. L-1 in registers (wavefront 0): start value and
+// right-hand side of level ls from LDS, the result back into its u.
+template <typename T, int DIM>
+__device__ __forceinline__ void b_regs_cycle(const BottomArgs<T> &a, T *sm, int L, int ls, bool from_lds) {
+  const BL b = bl_make(DIM, L, ls);
+  const RLev<DIM> g = rl_make<DIM>(b.k);
+  T *U = sm + bl_offset(DIM, L, ls);
+  const T *F = U + b.size;
+  const int i = DIM == 3 ? ((g.z + 1) * b.n + g.y) * b.n + g.x : (g.y + 1) * b.n + g.x;
+  const T f = g.in ? F[i] : T(0);
+  T u = (g.in && from_lds) ? U[i] : T(0);
+  switch (L - ls) {
+    case 1: u = r_vcycle<T, DIM, 1>(a, b.k, u, f); break;
+    case 2: u = r_vcycle<T, DIM, 2>(a, b.k, u, f); break;
+    default:
+      if constexpr (DIM == 2) u = r_vcycle<T, DIM, 3>(a, b.k, u, f);
+      break;
+  }
+  if (g.in) U[i] = u;
+}
+
 // One V-cycle (Algorithm 1) on the levels top .. L-1 of the LDS hierarchy,
 // from the start value held in level top's u; the coarser levels start from
 // zero (cleared here when `clear`, otherwise already zero).  The levels from
-// bl_first_small down, and the one-node level, run in wavefront 0.
+// bl_first_small down, and the one-node level, run in wavefront 0: in
+// registers with red-black smoothing, in LDS with weighted Jacobi.
 template <typename T, int DIM>
-__device__ void b_vcycle(const BottomArgs<T> &a, T *sm, T *R, int L, int top, bool clear) {
+__device__ __forceinline__ void b_vcycle(const BottomArgs<T> &a, T *sm, T *R, int L, int top, bool clear) {
   const int ls = max(top, bl_first_small(DIM, L));
   b_descend<T, DIM, false>(a, sm, R, L, top, ls, top, clear);
   if (threadIdx.x < 64) {
-    b_descend<T, DIM, true>(a, sm, R, L, ls, L - 1, top, clear);
-    if (threadIdx.x == 0) b_coarsest<T, DIM>(sm, L);
-    Team<true>::sync();
-    b_ascend<T, DIM, true>(a, sm, R, L, ls, L - 1);
+    if (a.smoother == 0) {
+      // the start value of level ls: the caller's at the top, else zero
+      b_regs_cycle<T, DIM>(a, sm, L, ls, ls == top);
+    } else {
+      b_descend<T, DIM, true>(a, sm, R, L, ls, L - 1, top, clear);
+      if (threadIdx.x == 0) b_coarsest<T, DIM>(sm, L);
+      Team<true>::sync();
+      b_ascend<T, DIM, true>(a, sm, R, L, ls, L - 1);
+    }
   }
   __syncthreads();
   b_ascend<T, DIM, false>(a, sm, R, L, top, ls);
 }
 
 template <typename T, int DIM>
-__device__ void bottom_body(const BottomArgs<T> &a, const GMG_GLOBAL T *fin, GMG_GLOBAL T *uout, T *sm) {
+__device__ __forceinline__ void bottom_body(const BottomArgs<T> &a, const GMG_GLOBAL T *fin, GMG_GLOBAL T *uout, T *sm) {
   const int L = a.L;
   const int total = bl_offset(DIM, L, L) + bl_make(DIM, L, 0).size;
   T *R = sm + bl_offset(DIM, L, L);  // residual / Jacobi scratch, size of level 0

@@ -370,6 +370,19 @@ int pass_blocks(const gmg_plan *p, int level, int role, int sweeps, bool rst = f
   return pass_geometry(p->dim, p->m[level], st, t, c.tz[st], rst).nblocks;
 }
 
+// Sweeps of the last pass of a chain of nu sweeps in passes of at most smax
+// (the split build_chain and smooth_chain make), and the pass count.
+int last_pass_sweeps(int nu, int smax, int *npasses) {
+  const int K = (nu + smax - 1) / smax;
+  int left = nu, last = 0;
+  for (int k = 1; k <= K; ++k) {
+    last = std::min(smax, left - (K - k));
+    left -= last;
+  }
+  if (npasses) *npasses = K;
+  return last;
+}
+
 // Whether the pre-smoothing of `level` (nsweeps sweeps in passes of the
 // level's pre choice) can end in a pass that also restricts: red-black, a
 // coarser level exists, the choice asks for it, and the last pass's tile
@@ -379,15 +392,7 @@ bool can_fuse_restrict(const gmg_plan *p, int level, int nsweeps, size_t elem) {
   if (nsweeps < 1 || level + 1 >= p->L) return false;
   const PassChoice &c = p->ch[level][0];
   if (!c.fuse) return false;
-  // sweeps of the chain's last pass (the split smooth_chain makes)
-  const int smax = c.smax;
-  const int K = (nsweeps + smax - 1) / smax;
-  int left = nsweeps, last = 0;
-  for (int k = 1; k <= K; ++k) {
-    last = std::min(smax, left - (K - k));
-    left -= last;
-  }
-  const int st = stages_of(p, last);
+  const int st = stages_of(p, last_pass_sweeps(nsweeps, c.smax, nullptr));
   if (pass_geometry(p->dim, p->m[level], st, pass_variant(p->dim, st, 0, c.var[st]), c.tz[st], true)
           .nblocks > kMaxPartials)
     return false;
@@ -1645,19 +1650,6 @@ struct ChainEnt {
 };
 
 PassChoice batch_choice(const gmg_plan *p, const Batch *b, int dim, int m, int role);
-
-// Sweeps of the last pass of a chain of nu sweeps in passes of at most smax
-// (the split build_chain and smooth_chain make), and the pass count.
-int last_pass_sweeps(int nu, int smax, int *npasses) {
-  const int K = (nu + smax - 1) / smax;
-  int left = nu, last = 0;
-  for (int k = 1; k <= K; ++k) {
-    last = std::min(smax, left - (K - k));
-    left -= last;
-  }
-  if (npasses) *npasses = K;
-  return last;
-}
 
 // Whether the pre-smoothing chains of the level size (dim, m) whose first
 // pass has first_flags end in a pass that also restricts, as single
