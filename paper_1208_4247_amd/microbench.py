@@ -254,17 +254,22 @@ def traffic_report(manifest_log, fetch_csv, write_csv, copy_fetch_csv, copy_writ
         wk = sum(float(r["Counter_Value"]) for r in wr[i:i + n]) / n
         kern = fr[i]["Kernel_Name"].split("(")[0].replace("void gmg::", "")
         i += n
-        # the pass's flags are its last template argument; 16: restriction
-        # folded in (a candidate asked to fold whose tile does not fit runs
-        # the plain pass, and is filed under it)
-        fold = (int(kern.rstrip(">").split(",")[-1]) & 16) != 0
         m, d = e["m"], e["dim"]
         mc = (m - 1) // 2
-        # w_k, f and the coarse correction read; w_{k+1} (and f_c) written
-        alg = 8.0 * (3 * m ** d + mc ** d + (mc ** d if fold else 0))
         traffic = 1024.0 * (fk * kf + wk * kw)
-        key = "%s|%d|%d|%d|%d" % (e["manifest"], e["stages"], e["variant"], e["tz"],
-                                  1 if fold else 0)
+        if e["manifest"] == "cross":
+            # the pass's flags are its last template argument; 16: restriction
+            # folded in (a candidate asked to fold whose tile does not fit runs
+            # the plain pass, and is filed under it)
+            fold = (int(kern.rstrip(">").split(",")[-1]) & 16) != 0
+            # w_k, f and the coarse correction read; w_{k+1} (and f_c) written
+            alg = 8.0 * (3 * m ** d + mc ** d + (mc ** d if fold else 0))
+            key = "%s|%d|%d|%d|%d" % (e["manifest"], e["stages"], e["variant"], e["tz"],
+                                      1 if fold else 0)
+        else:
+            # pre: u, f read, result written; post: the coarse correction too
+            alg = 8.0 * (3 * m ** d + (mc ** d if e["manifest"] == "post" else 0))
+            key = "%s|%d|%d|%d" % (e["manifest"], e["stages"], e["variant"], e["tz"])
         table[key] = traffic
         out.append("| %s | `%s` | %.0f | %.0f | %.1f | %.1f | %.3f |" % (
             key, kern, fk, wk, traffic / 1e6, alg / 1e6, traffic / alg))
