@@ -32,6 +32,10 @@ TRAFFIC_PROFILES = {
         os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_255_traffic.md"),
     ("poisson3d_255_sine_noise_fp64_v22", "smooth_post_l0"):
         os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_255_traffic.md"),
+    ("poisson3d_511_uniform_fp64_v22", "smooth_pre_l0"):
+        os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_511_traffic.md"),
+    ("poisson3d_511_uniform_fp64_v22", "smooth_post_l0"):
+        os.path.join(ROOT, "profiles", "rb_pass_l0_poisson3d_511_traffic.md"),
     ("poisson3d_1023_sine_modes_fp64_v11", "smooth_cross_l0"):
         os.path.join(ROOT, "profiles", "cross_pass_l0_poisson3d_1023_traffic.md"),
 }
@@ -543,7 +547,7 @@ def main():
     fused_pre = dom != "smooth_post_l0" and full["resid_restrict_l0"]["launches"] == 0
     traffic = measured_traffic(args.workload, dom, tile, fused_pre)
     if traffic is not None and dom == "smooth_pre_l0" and fused_pre:
-        traffic = None  # the 255^3 table covers the plain pre-smoothing pass only
+        traffic = None  # the 255^3 and 511^3 tables cover the plain pre-smoothing pass only
     for k, v in full.items():
         if v["launches"]:
             print("#   %-22s launches %6d  avg %9.3f us  alg %8.1f GB/s" % (
