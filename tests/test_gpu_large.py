@@ -10,6 +10,11 @@ the oracle's full solve (same status and cycle count, iterates within 1e-12,
 the oracle run once on every host thread, about two minutes); the mixed
 solve reaches 1e-10 by the oracle's residual and its distance from the
 oracle's iterate is reported.
+2D 8191^2 (the largest 2D grid the library takes, uniform RHS, V(2,2)): the
+FP64 solve equals the oracle's at rtol 1e-7 (same cycle count, iterates
+within 1e-12).  At this h the rounding floor of the residual itself is near
+1e-9 of ||f|| (about eps * 8 |u| / h^2), so 1e-10 is out of reach for any
+FP64 solver there.
 """
 import os
 import time
@@ -152,3 +157,23 @@ def test_1023_mixed_reaches_1e10_by_oracle_residual(big, big_oracle):
     print("1023^3 mixed: %d steps, relres %.3e (oracle residual %.3e); distance from the "
           "oracle's FP64 iterate %.3e" % (it, rel, rr, diff), flush=True)
     assert st == 0 and rr <= 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_8191sq_fp64_solve_matches_oracle():
+    f = wl.rhs_uniform(2, 8191, seed=13)
+    fd = torch.from_numpy(f).cuda()
+    plan = tuned_plan(2, 13)
+    u = torch.zeros_like(fd)
+    plan.solve(u, fd, rtol=1e-7)  # tunes
+    u.zero_()
+    st, it, rel = plan.solve(u, fd, rtol=1e-7)
+    ug = host(u)
+    del u, fd
+    t0 = time.perf_counter()
+    ur, itr, relr, str_, _ = oracle.solve(f, rtol=1e-7)
+    diff = float(np.linalg.norm(ug - ur) / np.linalg.norm(ur))
+    print("8191^2 fp64: %d cycles, relres %.3e; oracle %d cycles (%.0f s); rel diff %.3e" % (
+        it, rel, itr, time.perf_counter() - t0, diff), flush=True)
+    assert (st, it) == (str_, itr) == (0, itr)
+    assert diff <= 1e-12
