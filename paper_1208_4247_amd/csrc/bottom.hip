@@ -264,8 +264,9 @@ __device__ __forceinline__ void b_coarsest(T *sm, int L) {
 // (__shfl), so a step is a few cross-lane reads and the point's arithmetic,
 // with no LDS round trip and no wait between steps.  Every expression is the
 // one the LDS steps above evaluate, in the same order, with zeros wherever
-// they read a pad.  Shuffles run on all lanes; the results are selected
-// afterwards.
+// they read a pad.  Every lane takes part in every shuffle (a lane that sits
+// one out does not supply its value to the others); the results are
+// selected afterwards.
 template <int DIM>
 struct RLev {
   int n, m, x, y, z;
