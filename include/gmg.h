@@ -109,6 +109,10 @@ typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_dtype;
                                        cycle's level-0 post-smoothing and the
                                        next cycle's pre-smoothing as two passes
                                        instead of one (same iterates)         */
+#define GMG_BATCH_ONE_STREAM 0x400u /* batched plans holding 2D and 3D problems:
+                                       run all launches in order on the plan's
+                                       stream instead of the 2D problems' on a
+                                       concurrent side stream (same results)  */
 
 typedef struct {
   int dim;                 /* 2 or 3                                            */

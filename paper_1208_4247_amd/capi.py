@@ -39,6 +39,7 @@ GMG_NO_FUSED_RESTRICT = 0x40
 GMG_FE_TRANSFER = 0x80
 GMG_COARSE_RELAX = 0x100
 GMG_NO_CROSS_CYCLE = 0x200
+GMG_BATCH_ONE_STREAM = 0x400
 GMG_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = [

@@ -110,6 +110,7 @@ struct BOp {
   size_t lds = 0;      // bottom: LDS bytes for the largest entry
   int bottom_L = 0;    // bottom: largest sub-hierarchy
   int bottom_dim = 3;
+  int branch = 0;      // 0: the plan's stream; 1: the side stream (2D problems)
 };
 
 struct Batch {
@@ -134,6 +135,14 @@ struct Batch {
   std::map<std::array<int, 2>, int> shape_count;
   bool worst = false;      // sizing: one sweep per pass everywhere (most launches)
   size_t tbl_reserve = 0;  // table region reserved for any choice
+  // 2D and 3D problems share no launch and no data, so a batch holding both
+  // runs them as two concurrent branches: the 3D launches on the plan's
+  // stream, the 2D ones on a side stream forked from it at the start of a
+  // cycle and joined back at its end (the same launches as one stream, so
+  // the same bits)
+  bool two = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct gmg_plan {
@@ -1880,6 +1889,7 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
       if (!tops.empty()) {
         BOp op;
         op.kind = BO_FIN;
+        op.dim = dim;
         op.nent = (int)tops.size();
         op.cls = PC_FIN;
         bb.align_tbl();
@@ -1923,15 +1933,18 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
       }
     }
   }
-  {  // bottom levels of every problem, one workgroup each
+  for (int dim = 3; dim >= 2; --dim) {  // bottom levels, one workgroup per problem
     BOp op;
     op.kind = BO_BOTTOM;
-    op.nent = n;
+    op.dim = dim;
+    op.nent = 0;
     op.cls = PC_BOTTOM;
     bb.align_tbl();
     op.tbl_off = b->host_tbl.size();
     for (int q = 0; q < n; ++q) {
       BProblem &pr = b->pb[q];
+      if (pr.dim != dim) continue;
+      ++op.nent;
       BottomArgs<double> a{};
       a.f = pr.f[pr.B];
       a.u = pr.u[pr.B];
@@ -1951,7 +1964,7 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
         op.bottom_dim = pr.dim;
       }
     }
-    b->ops.push_back(op);
+    if (op.nent > 0) b->ops.push_back(op);
   }
   for (int dim = 3; dim >= 2; --dim) {
     int Emax = 0;
@@ -1973,6 +1986,10 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
       build_chain(bb, dim, m, 1, nu2, F_PROLONG, bwd, ents, PC_POST_C);
     }
   }
+  bool has2 = false, has3 = false;
+  for (const auto &pr : b->pb) (pr.dim == 2 ? has2 : has3) = true;
+  b->two = has2 && has3 && !(p->cfg.flags & GMG_BATCH_ONE_STREAM);
+  for (BOp &op : b->ops) op.branch = b->two && op.dim == 2 ? 1 : 0;
   bb.align_tbl();
   const size_t tbl_off = bb.take_bytes(std::max(b->host_tbl.size(), b->tbl_reserve));
   b->dev_tbl = ws + tbl_off;
@@ -1981,40 +1998,59 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
 
 hipError_t batch_enqueue_cycle(gmg_plan *p) {
   Batch *b = p->batch;
+  // profiled cycles time every launch on the plan's stream: one branch
+  const bool fork = b->two && !p->profile;
+  if (fork) {
+    hipError_t e = hipSuccess;
+    if (!b->side) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess && !b->ev_fork)
+      e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess && !b->ev_join)
+      e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_fork, p->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    if (e != hipSuccess) return e;
+  }
   for (const BOp &op : b->ops) {
     const char *tbl = b->dev_tbl + op.tbl_off;
     const char *host = b->host_tbl.data() + op.tbl_off;
+    const hipStream_t s = fork && op.branch ? b->side : p->stream;
     hipError_t e = hipSuccess;
     ProfScope ps(p, op.cls, op.bytes);
     switch (op.kind) {
       case BO_PASS: {
         PassArgs<double> a;
         std::memcpy(&a, host, sizeof(a));
-        e = op.wj ? launch_wj_pass<double>(op.dim, op.stages, op.flags, op.variant, a, p->stream,
+        e = op.wj ? launch_wj_pass<double>(op.dim, op.stages, op.flags, op.variant, a, s,
                                            (const PassArgs<double> *)tbl, op.nent)
-                  : launch_rb_pass<double>(op.dim, op.stages, op.flags, op.variant, a, p->stream,
+                  : launch_rb_pass<double>(op.dim, op.stages, op.flags, op.variant, a, s,
                                            (const PassArgs<double> *)tbl, op.nent);
         break;
       }
       case BO_RESTRICT: {
         RestrictArgs<double> a{};
         std::memcpy(&a, host, sizeof(a));
-        e = launch_restrict<double>(op.dim, a, p->stream, (const RestrictArgs<double> *)tbl,
+        e = launch_restrict<double>(op.dim, a, s, (const RestrictArgs<double> *)tbl,
                                     op.nent);
         break;
       }
       case BO_FIN:
-        e = launch_finalize_batch((const FinEntry *)tbl, op.nent, p->stream);
+        e = launch_finalize_batch((const FinEntry *)tbl, op.nent, s);
         break;
       case BO_BOTTOM: {
         BottomArgs<double> a{};
         a.dim = op.bottom_dim;
         a.L = op.bottom_L;
         a.smoother = p->cfg.smoother == GMG_SMOOTH_WJ ? 1 : 0;
-        e = launch_bottom<double>(op.nent, a, (const BottomArgs<double> *)tbl, p->stream, op.lds);
+        e = launch_bottom<double>(op.nent, a, (const BottomArgs<double> *)tbl, s, op.lds);
         break;
       }
     }
+    if (e != hipSuccess) return e;
+  }
+  if (fork) {
+    hipError_t e = hipEventRecord(b->ev_join, b->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, b->ev_join, 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -2328,6 +2364,9 @@ gmg_status gmg_destroy(gmg_plan *p) {
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   if (p->batch) {
     if (p->batch->graph) (void)hipGraphExecDestroy(p->batch->graph);
+    if (p->batch->ev_fork) (void)hipEventDestroy(p->batch->ev_fork);
+    if (p->batch->ev_join) (void)hipEventDestroy(p->batch->ev_join);
+    if (p->batch->side) (void)hipStreamDestroy(p->batch->side);
     if (p->batch->pinned) (void)hipHostFree(p->batch->pinned);
     if (p->batch->hstates) (void)hipHostFree(p->batch->hstates);
     delete p->batch;

@@ -413,11 +413,12 @@ def counter_report(pmc_csvs, kernel_regex, title, points, clock_ghz=2.4,
     print("\n".join(out))
 
 
-def batch_solves(nsolves):
+def batch_solves(nsolves, flags=0):
     """The bench's 256-problem batch (128 2D problems of side 2^k - 1,
     k ~ U{6..10}, 128 3D with k ~ U{5..7}; U[-1,1) right-hand sides, seed 4;
     FP64 V(2,2) to 1e-10 each; graph-captured cycles, autotuned): one solve
-    that tunes (or reads GMG_TUNE_CACHE), then nsolves timed solves."""
+    that tunes (or reads GMG_TUNE_CACHE), then nsolves timed solves.  flags
+    are added to the plan's (GMG_BATCH_ONE_STREAM: one stream)."""
     import time
 
     from . import capi
@@ -428,7 +429,7 @@ def batch_solves(nsolves):
     fs = [torch.from_numpy(wl.batch_rhs(4, q, d, m)).cuda() for q, (d, m) in enumerate(probs)]
     us = [torch.zeros_like(f) for f in fs]
     plan = BatchPlan([(d, (m + 1).bit_length() - 1) for d, m in probs],
-                     flags=capi.GMG_USE_GRAPH | capi.GMG_AUTOTUNE)
+                     flags=capi.GMG_USE_GRAPH | capi.GMG_AUTOTUNE | flags)
     for k in range(nsolves + 1):
         for u in us:
             u.zero_()
@@ -490,6 +491,8 @@ def main():
                     help="markdown per-kernel summary of a rocprofv3 kernel trace")
     ap.add_argument("--kernel-regex", default=r"k_rb_pass<double, 3, 3,")
     ap.add_argument("--title", default="HBM traffic of the cross-cycle pass")
+    ap.add_argument("--batch-flags", type=lambda v: int(v, 0), default=0,
+                    help="plan flags added to the batch plan of --batch-solves")
     ap.add_argument("--batch-solves", type=int, default=0,
                     help="the 256-problem batch: a tuning solve, then this many solves")
     ap.add_argument("--solve-cycles", type=int, default=0,
@@ -504,7 +507,7 @@ def main():
                     "(for a counter profiler)")
     a = ap.parse_args()
     if a.batch_solves:
-        batch_solves(a.batch_solves)
+        batch_solves(a.batch_solves, a.batch_flags)
         return
     if a.solve_cycles:
         for m in a.m:

@@ -125,6 +125,33 @@ def test_batch_graph_replay_bitwise():
             assert np.array_equal(host(a), b)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_two_branches_equal_one_stream(graph):
+    """A batch of 2D and 3D problems runs them as two concurrent branches
+    (the 2D launches on a side stream); with GMG_BATCH_ONE_STREAM every
+    launch runs in order on one stream.  Same launches, so the same bits and
+    cycle counts, on every replay of a captured cycle."""
+    from paper_1208_4247_amd import capi
+
+    probs = SMALL
+    rhs = [wl.batch_rhs(19, q, d, m) for q, (d, m) in enumerate(probs)]
+    g = capi.GMG_USE_GRAPH if graph else 0
+    _, us_1, its_1, rels_1, _ = run_batch(probs, rhs, flags=g | capi.GMG_BATCH_ONE_STREAM)
+    plan, us_2, its_2, rels_2, _ = run_batch(probs, rhs, flags=g)
+    assert its_1 == its_2 and rels_1 == rels_2
+    for a, b in zip(us_1, us_2):
+        assert np.array_equal(a, b)
+    fs = [dev(f) for f in rhs]
+    for rep in range(2):
+        us = [torch.zeros_like(f) for f in fs]
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()
+        s, its, rels, sts = plan.solve(us, fs, rtol=1e-10)
+        assert its == its_1
+        for a, b in zip(us, us_1):
+            assert np.array_equal(host(a), b)
+
+
 def test_single_problem_graph_replay_bitwise():
     from paper_1208_4247_amd import capi
     from paper_1208_4247_amd.solver import Plan
