@@ -111,6 +111,17 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
 }
 
 
+// two adjacent elements in one store (the counterpart of bload2)
+template <typename T>
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, T lo, T hi) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const PairOf<T> v{lo, hi};
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gmg_u32x2, v), r, off, 0, 0);
+}
+
 // Flags of a fused smoothing pass.
 enum PassFlags : int {
   F_ZERO_IN = 1,     // start value is zero: u_in is not read

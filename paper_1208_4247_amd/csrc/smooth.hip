@@ -216,6 +216,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   int tx, ty, tzc;
   tile_coords<DIM>(xcd_remap(blockIdx.x, a.nblocks), a.ntx, a.nty, a.sw, tx, ty, tzc);
   const int X0 = tx * 2 * TXP;
+  const bool xend = (m & 1) && X0 + 2 * TXP >= m;  // the output tile holds x = m - 1
   const int Y0 = ty * TY;
   const int Z0 = tzc * a.tz;
   const int Z1 = min(Z0 + a.tz, m);
@@ -232,14 +233,17 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   // the high half.  hP / hQ: element P / Q is the high half of the load.
   int o2[NS];
   bool hP[NS], hQ[NS];
-  int sP[NS], sQ[NS];    // store offsets, kOOB outside the grid or the output tile
+  // stores: a pair of the output tile with both elements in the grid takes
+  // one 16-byte store at w2; the lone element of a row-end pair (m odd) an
+  // 8-byte store at w1 (kOOB elsewhere)
+  int w2[NS], w1[NS];
   bool nP[NS], nQ[NS];   // NORM: element inside the grid and the output tile
   bool kP[NS], kQ[NS];   // element inside the grid
   int lq[NS], lP[NS], lQ[NS], lu[NS], ld[NS];  // LDS: self, x-side of P / Q, y-1, y+1
   bool live[NS];
   int cb[PRO ? NS : 1];
   bool c2[PRO ? NS : 1];
-  bool pone[(PRO || RST) ? NS : 1];  // element P is element 1 of the pair
+  bool pone[NS];  // element P is element 1 of the pair
   bool k0[RST ? NS : 1], k1[RST ? NS : 1];  // element 0 / 1 inside the grid
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
@@ -264,8 +268,8 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     hQ[i] = par ? half : true;
     kP[i] = par ? in1 : in0;
     kQ[i] = par ? in0 : in1;
-    sP[i] = outp ? (par ? o1 : o0) : kOOB;
-    sQ[i] = outp ? (par ? o0 : o1) : kOOB;
+    w2[i] = (outp && in1) ? o0 : kOOB;
+    w1[i] = (outp && half) ? o0 : kOOB;
     nP[i] = outp && kP[i];
     nQ[i] = outp && kQ[i];
     lq[i] = qc;
@@ -274,7 +278,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
     lQ[i] = par ? left : right;
     lu[i] = max(qc - EXP, 0);
     ld[i] = min(qc + EXP, PL - 1);
-    if (PRO || RST) pone[i] = par != 0;
+    pone[i] = par != 0;
     if (RST) {
       k0[i] = in0;
       k1[i] = in1;
@@ -605,15 +609,19 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         acc += use ? r * r : 0.0;
       }
     }
-    // ---- output plane t-S: last stage's colour from newS, the other from S-1
+    // ---- output plane t-S: last stage's colour from newS, the other from
+    // S-1; both elements in one store (the tile at the high x end of a grid
+    // of odd side adds the 8-byte store of its row-end elements)
     const int zo = t - S;
     {
       const __amdgpu_buffer_rsrc_t r = plane_rsrc_if(a.u_out, zo, zo >= Z0 && zo < Z1, planeS);
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        const T o_new = newS[i], o_old = W[S - 1][i][1];
-        bstore<T>(r, isP(S) ? sP[i] : sQ[i], o_new);
-        bstore<T>(r, isP(S) ? sQ[i] : sP[i], o_old);
+        const T vP = isP(S) ? newS[i] : W[S - 1][i][1];
+        const T vQ = isP(S) ? W[S - 1][i][1] : newS[i];
+        const T e0 = pone[i] ? vQ : vP, e1 = pone[i] ? vP : vQ;
+        bstore2<T>(r, w2[i], e0, e1);
+        if (xend) bstore<T>(r, w1[i], e0);
       }
     }
     // ---- RST: final values of plane t-S into the window; residual of plane
@@ -718,6 +726,7 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
   int tx, ty, tzc;
   tile_coords<DIM>(xcd_remap(blockIdx.x, a.nblocks), a.ntx, a.nty, a.sw, tx, ty, tzc);
   const int X0 = tx * 2 * TXP;
+  const bool xend = (m & 1) && X0 + 2 * TXP >= m;  // the output tile holds x = m - 1
   const int Y0 = ty * TY;
   const int Z0 = tzc * a.tz;
   const int Z1 = min(Z0 + a.tz, m);
@@ -730,7 +739,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
   // per-slot geometry (see the red-black pass; here elements keep their
   // index: k0 / k1 element inside the grid, h0 element 0 is the high half of
   // the pair load)
-  int o2[NS], s0[NS], s1[NS], lq[NS], lft[NS], rgt[NS], lu[NS], ld[NS];
+  // stores as in the red-black pass: w2 a whole pair, w1 a row-end element
+  int o2[NS], w2[NS], w1[NS], lq[NS], lft[NS], rgt[NS], lu[NS], ld[NS];
   bool h0[NS], k0[NS], k1[NS], n0[NS], n1[NS], live[NS];
   int cb[PRO ? NS : 1];
   bool c2[PRO ? NS : 1];
@@ -753,8 +763,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
     h0[i] = half;
     k0[i] = in0;
     k1[i] = in1;
-    s0[i] = (outp && in0) ? off * (int)sizeof(T) : kOOB;
-    s1[i] = (outp && in1) ? (off + 1) * (int)sizeof(T) : kOOB;
+    w2[i] = (outp && in1) ? off * (int)sizeof(T) : kOOB;
+    w1[i] = (outp && half) ? off * (int)sizeof(T) : kOOB;
     n0[i] = outp && in0;
     n1[i] = outp && in1;
     lq[i] = qc;
@@ -955,8 +965,8 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
       const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a.u_out, zo, m, planeS);
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        bstore<T>(rs, s0[i], newS[i][0]);
-        bstore<T>(rs, s1[i], newS[i][1]);
+        bstore2<T>(rs, w2[i], newS[i][0], newS[i][1]);
+        if (xend) bstore<T>(rs, w1[i], newS[i][0]);
       }
     }
     // ---- publish the newest plane of every stage (both elements)
