@@ -115,6 +115,25 @@ def test_mixed_solve_odd_and_even_step_counts_land_in_u():
         assert abs(r - rel) <= 1e-6 * rel
 
 
+@pytest.mark.parametrize("dim,m", [(2, 1), (2, 3), (2, 7), (2, 255), (2, 511),
+                                   (3, 1), (3, 3), (3, 7), (3, 15), (3, 127)])
+def test_refinement_step_residual_at_grid_edges(dim, m):
+    """The refinement step moves x-pairs: the lone element at the end of
+    every row of an odd side, the tile edges and the one-point grid must give
+    the iterate and residual norm that the oracle computes from the returned
+    iterate (one and two refinement steps from zero)."""
+    f = wl.rhs_uniform(dim, m, seed=100 + m)
+    plan = Plan(dim, levels_of(m), precision="mixed")
+    fd = dev(f)
+    for maxit in (1, 2) if m > 7 else (1,):
+        ud = torch.zeros_like(fd)
+        st, it, rel = plan.solve(ud, fd, rtol=1e-30, maxit=maxit)
+        u = host(ud)
+        assert it == maxit and np.all(np.isfinite(u))
+        r = oracle.norm2(oracle.residual(u, f)) / oracle.norm2(f)
+        assert abs(r - rel) <= 1e-6 * rel, (dim, m, maxit, r, rel)
+
+
 @pytest.mark.parametrize("inner", [1, 2])
 def test_mixed_vcycle_is_one_refinement_step(inner):
     """gmg_vcycle on a mixed plan: one refinement step x <- x + e with e
