@@ -157,6 +157,7 @@ struct gmg_plan {
   int smax_cap = 2;           // most sweeps fused into one pass
   bool need_tmp = false;
   bool tuned = false;
+  double omega_user = 0.0;  // WJ weight as the caller gave it (0: the default of each dimension)
 
   SolveState *state = nullptr;
   double *partials = nullptr;
@@ -1171,10 +1172,17 @@ gmg_status validate_cfg(const gmg_config *c) {
   return GMG_OK;
 }
 
+// Weighted-Jacobi weight for a problem of dimension dim: the caller's, or
+// 2d / (2d + 1) when the caller left it 0 (Remark 1's choice per dimension;
+// a batch can hold both dimensions)
+double wj_omega(const gmg_plan *p, int dim) {
+  return p->omega_user == 0.0 ? (dim == 3 ? 6.0 / 7.0 : 0.8) : p->omega_user;
+}
+
 gmg_status init_plan_shape(gmg_plan &p, const gmg_config *cfg) {
   p.cfg = *cfg;
-  if (p.cfg.smoother == GMG_SMOOTH_WJ && p.cfg.omega == 0.0)
-    p.cfg.omega = cfg->dim == 3 ? 6.0 / 7.0 : 0.8;
+  p.omega_user = cfg->omega;
+  if (p.cfg.smoother == GMG_SMOOTH_WJ) p.cfg.omega = wj_omega(&p, cfg->dim);
   p.dim = cfg->dim;
   p.L = cfg->levels;
   p.m.resize(p.L);
@@ -1732,7 +1740,7 @@ void build_chain(BatchBuilder &bb, int dim, int m, int role, int nu, int first_f
       a.nblocks = g.nblocks;
       a.h2 = h * h;
       a.inv_h2 = 1.0 / (h * h);
-      a.omega = p->cfg.omega;
+      a.omega = wj_omega(p, dim);
       const size_t off = bb.push(a);
       const bool in_user = k == 1 ? e.src_user : out_user(k - 1);
       if (in_user) b->patches.push_back({off + offsetof(PassArgs<double>, u_in), e.q, 0});
@@ -1955,7 +1963,7 @@ size_t batch_build(gmg_plan *p, Batch *b, int n, const int *dims, const int *lev
       a.nu2 = nu2;
       a.smoother = sm;
       a.post_forward = bwd ? 0 : 1;
-      a.omega = p->cfg.omega;
+      a.omega = wj_omega(p, pr.dim);
       bb.push(a);
       const size_t lds = bottom_lds_bytes(pr.dim, a.L, sm, sizeof(double));
       if (lds > op.lds) {
@@ -2165,6 +2173,7 @@ hipError_t batch_tune(gmg_plan *p, double *const *u, const double *const *f) {
     gmg_config c = p->cfg;
     c.dim = pr.dim;
     c.levels = pr.L;
+    c.omega = p->omega_user;
     c.flags = c.flags & ~(unsigned)GMG_PROFILE;
     gmg_plan v;
     init_plan_shape(v, &c);

@@ -89,6 +89,41 @@ def test_batch_equals_single_plans_bitwise(post_forward):
         plan.close()
 
 
+@pytest.mark.parametrize("smoother,nu1,nu2", [("wj", 2, 2), ("rbgs", 1, 1), ("rbgs", 1, 2),
+                                              ("rbgs", 3, 3)])
+def test_batch_smoothers_and_sweep_counts(smoother, nu1, nu2):
+    """Weighted Jacobi and other sweep counts through the batch's tables
+    and its two concurrent branches: every problem gives the bits and cycle
+    count of its own single-problem plan (for V(1,1) that plan runs the
+    cross-cycle schedule), and one problem of each dimension those of the
+    oracle's solve to 1e-12."""
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import BatchPlan, Plan
+
+    probs = [(3, 31), (2, 127), (3, 63), (2, 255)]
+    rhs = [wl.batch_rhs(23, q, d, m) for q, (d, m) in enumerate(probs)]
+    plan = BatchPlan([(d, levels_of(m)) for d, m in probs], smoother=smoother, nu1=nu1, nu2=nu2,
+                     flags=capi.GMG_USE_GRAPH)
+    fs = [dev(f) for f in rhs]
+    us = [torch.zeros_like(f) for f in fs]
+    s, its, rels, sts = plan.solve(us, fs, rtol=1e-10, maxit=80)
+    for q, (d, m) in enumerate(probs):
+        single = Plan(d, levels_of(m), smoother=smoother, nu1=nu1, nu2=nu2)
+        ud = torch.zeros_like(fs[q])
+        st, it, _ = single.solve(ud, fs[q], rtol=1e-10, maxit=80)
+        assert (sts[q], its[q]) == (st, it) == (0, it), (q, d, m)
+        assert np.array_equal(host(us[q]), host(ud)), (q, d, m)
+        single.close()
+    wj = smoother == "wj"
+    for q in (0, 1):
+        d = probs[q][0]
+        u_ref, it_ref, _, st_ref, _ = oracle.solve(
+            rhs[q], nu1=nu1, nu2=nu2, smoother=oracle.WJ if wj else oracle.RBGS,
+            omega=(6.0 / 7.0 if d == 3 else 0.8), rtol=1e-10, maxit=80)
+        assert (sts[q], its[q]) == (st_ref, it_ref), (q, its[q], it_ref)
+        assert rel2(host(us[q]), u_ref) <= 1e-12
+
+
 def test_batch_per_problem_stop_tests():
     """A zero RHS stops at once, an easy RHS early, the rest later; the
     batch result of each equals its own solve."""
