@@ -2,7 +2,9 @@
 weighted Jacobi, with uneven sweep counts and with the flags that change the
 schedule (each must reach the FP64 residual by the oracle's own residual);
 FP64 solves without temporal blocking, which must give the bits of the
-fused-sweep passes (every half-sweep is the same per-point expression).
+fused-sweep passes (every half-sweep is the same per-point expression); the
+captured coarse part against eager launches for every schedule; batches with
+the schedule flags against single-problem plans.
 """
 import numpy as np
 import pytest
@@ -80,3 +82,51 @@ def test_no_temporal_blocking_same_bits(dim, m, smoother, nu):
         plan.close()
     assert out[0][:2] == out[1][:2] and out[0][0] == 0
     assert np.array_equal(out[0][2], out[1][2])
+
+
+@pytest.mark.parametrize("kw", [dict(precision="mixed"), dict(smoother="wj"),
+                                dict(nu1=1, nu2=1), dict(nu1=1, nu2=1, precision="mixed"),
+                                dict(nu1=3, nu2=1)])
+def test_graph_replay_equals_eager(kw):
+    """The captured coarse part of a cycle (GMG_USE_GRAPH) gives the bits of
+    eager launches for every schedule, on the first solve and on replays
+    with other work in between."""
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import Plan
+
+    fd = dev(wl.rhs_uniform(3, 63, seed=401))
+    eager = Plan(3, 6, **kw)
+    ue = torch.zeros_like(fd)
+    st_e, it_e, _ = eager.solve(ue, fd, rtol=1e-10)
+    graph = Plan(3, 6, flags=capi.GMG_USE_GRAPH, **kw)
+    for rep in range(3):
+        ug = torch.zeros_like(fd)
+        _ = torch.ones(1000, device="cuda").sum().item()
+        st_g, it_g, _ = graph.solve(ug, fd, rtol=1e-10)
+        assert (st_g, it_g) == (st_e, it_e) == (0, it_e)
+        assert np.array_equal(host(ug), host(ue)), rep
+    eager.close()
+    graph.close()
+
+
+@pytest.mark.parametrize("flag", ["GMG_NO_TEMPORAL_BLOCKING", "GMG_NO_FUSED_RESTRICT",
+                                  "GMG_NO_FUSED_COARSE"])
+def test_batch_schedule_flags_equal_single_plans(flag):
+    """The batch honours the flags that change a plan's schedule: each
+    problem gives the bits and cycle count of its own plan with the flag."""
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import BatchPlan, Plan
+
+    flags = getattr(capi, flag)
+    probs = [(3, 63), (2, 255), (3, 31), (2, 511)]
+    fs = [dev(wl.batch_rhs(29, q, d, m)) for q, (d, m) in enumerate(probs)]
+    plan = BatchPlan([(d, levels_of(m)) for d, m in probs], flags=flags | capi.GMG_USE_GRAPH)
+    us = [torch.zeros_like(f) for f in fs]
+    s, its, rels, sts = plan.solve(us, fs, rtol=1e-10)
+    for q, (d, m) in enumerate(probs):
+        single = Plan(d, levels_of(m), flags=flags)
+        ud = torch.zeros_like(fs[q])
+        st, it, _ = single.solve(ud, fs[q], rtol=1e-10)
+        assert (sts[q], its[q]) == (st, it) == (0, it), (q, d, m)
+        assert np.array_equal(host(us[q]), host(ud)), (q, d, m)
+        single.close()
