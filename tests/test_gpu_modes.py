@@ -130,3 +130,26 @@ def test_batch_schedule_flags_equal_single_plans(flag):
         assert (sts[q], its[q]) == (st, it) == (0, it), (q, d, m)
         assert np.array_equal(host(us[q]), host(ud)), (q, d, m)
         single.close()
+
+
+@pytest.mark.parametrize("dim,L", [(2, 7), (3, 5)])
+def test_paper_variant_graph_and_profile_flags_same_bits(dim, L):
+    """The paper's smoother and transfers (multicolour GS, finite-element
+    transfers) under GMG_USE_GRAPH and GMG_PROFILE: the bits and cycle count
+    of the plain plan."""
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import Plan
+
+    m = (1 << L) - 1
+    fd = dev(wl.rhs_uniform(dim, m, seed=500 + m))
+    out = []
+    for extra in (0, capi.GMG_USE_GRAPH, capi.GMG_PROFILE):
+        plan = Plan(dim, L, smoother="mcgs", nu1=1, nu2=1, flags=capi.GMG_FE_TRANSFER | extra)
+        for _ in range(2):
+            ud = torch.zeros_like(fd)
+            st, it, rel = plan.solve(ud, fd, rtol=1e-8)
+            out.append((st, it, host(ud)))
+        plan.close()
+    for st, it, u in out[1:]:
+        assert (st, it) == out[0][:2] and out[0][0] == 0
+        assert np.array_equal(u, out[0][2])
