@@ -153,3 +153,23 @@ def test_paper_variant_graph_and_profile_flags_same_bits(dim, L):
     for st, it, u in out[1:]:
         assert (st, it) == out[0][:2] and out[0][0] == 0
         assert np.array_equal(u, out[0][2])
+
+
+def test_batch_profile_mode_same_bits():
+    """A profiled batch (every launch timed on the plan's stream, one branch)
+    gives the bits and cycle counts of the unprofiled, two-branch batch."""
+    from paper_1208_4247_amd import capi
+    from paper_1208_4247_amd.solver import BatchPlan
+
+    probs = [(3, 63), (2, 255), (3, 31), (2, 127)]
+    fs = [dev(wl.batch_rhs(31, q, d, m)) for q, (d, m) in enumerate(probs)]
+    out = []
+    for flags in (capi.GMG_USE_GRAPH, capi.GMG_PROFILE):
+        plan = BatchPlan([(d, levels_of(m)) for d, m in probs], flags=flags)
+        us = [torch.zeros_like(f) for f in fs]
+        s, its, rels, sts = plan.solve(us, fs, rtol=1e-10)
+        out.append((list(its), list(sts), [host(u) for u in us]))
+        plan.close()
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1] == [0] * len(probs)
+    for a, b in zip(out[0][2], out[1][2]):
+        assert np.array_equal(a, b)
