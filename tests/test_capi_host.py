@@ -37,6 +37,23 @@ def test_every_declared_symbol_is_exported(capi):
     assert set(syms) == set(capi.EXPORTED)
 
 
+def test_flag_values_match_the_header(capi):
+    """The binding's flag constants are the header's: every GMG_* flag
+    #define has a constant of the same value, and the flags are distinct
+    bits."""
+    hdr = open(os.path.join(ROOT, "include", "gmg.h")).read()
+    flags = dict(re.findall(r"#define (GMG_[A-Z0-9_]+) (0x[0-9a-fA-F]+)u", hdr))
+    assert len(flags) >= 11
+    seen = 0
+    for name, val in flags.items():
+        v = int(val, 16)
+        assert getattr(capi, name) == v, name
+        assert v & (v - 1) == 0 and not (seen & v), name  # one bit, not reused
+        seen |= v
+    m = re.search(r"#define GMG_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert capi.GMG_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+
+
 def test_status_strings(capi):
     for s, name in [(0, "GMG_OK"), (1, "GMG_NOT_CONVERGED"), (-1, "GMG_ERR_INVALID_ARG"),
                     (-2, "GMG_ERR_WORKSPACE"), (-5, "GMG_ERR_HIP"), (-6, "GMG_ERR_UNSUPPORTED")]:
