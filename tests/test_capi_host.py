@@ -37,8 +37,8 @@ def test_every_declared_symbol_is_exported(capi):
     assert set(syms) == set(capi.EXPORTED)
 
 
-def test_flag_values_match_the_header(capi):
-    """The binding's flag constants are the header's: every GMG_* flag
+def test_constants_match_the_header(capi):
+    """The binding's constants are the header's: every GMG_* flag
     #define has a constant of the same value, and the flags are distinct
     bits."""
     hdr = open(os.path.join(ROOT, "include", "gmg.h")).read()
@@ -52,6 +52,12 @@ def test_flag_values_match_the_header(capi):
         seen |= v
     m = re.search(r"#define GMG_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
     assert capi.GMG_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
+    # enumerators (status codes, smoothers, precisions, element types)
+    body = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    enums = re.findall(r"\b(GMG_[A-Z0-9_]+)\s*=\s*(-?\d+)", body)
+    assert len(enums) >= 12
+    for name, val in enums:
+        assert getattr(capi, name) == int(val), name
 
 
 def test_status_strings(capi):
