@@ -1319,7 +1319,7 @@ bool parse_cache_line(const char *line, std::string &key, PassChoice &c, int &st
 }
 
 // The level shape a key describes (dimension, side, Jacobi or not, sweep cap)
-// and whether the key carries this build's tile-table hash.
+// and whether the key carries the tile-table hash compiled into this library.
 bool key_shape(const std::string &key, int &dim, int &m, bool &wj, int &cap) {
   const size_t bar = key.find('|');
   if (bar == std::string::npos) return false;
