@@ -63,7 +63,6 @@ struct Team {
 // one colour of red-black Gauss-Seidel on an LDS level
 template <typename T, int DIM, bool W>
 __device__ void b_rb_colour(const BL &b, T *u, const T *f, int colour, T h2) {
-  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const int half = b.n >> 1;
   const int rows = DIM == 3 ? b.n * b.m : b.m;  // (y incl. pad row) x z, or y
   const int total = half * rows;
@@ -90,7 +89,7 @@ __device__ void b_rb_colour(const BL &b, T *u, const T *f, int colour, T h2) {
       nb += u[i - sz];
       nb += u[i + sz];
     }
-    u[i] = fma(h2, f[i], nb) * inv2d;
+    u[i] = point_solve<T, DIM>(h2, f[i], nb);
   }
   Team<W>::sync();
 }
@@ -111,7 +110,6 @@ __device__ __forceinline__ void b_for_all(const BL &b, F fn) {
 
 template <typename T, int DIM, bool W>
 __device__ void b_wj(const BL &b, T *u, const T *f, T *tmp, T h2, T omega) {
-  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const int sy = b.n, sz = b.n * b.n;
   b_for_all<DIM, W>(b, [&](int i, int, int, int) {
     T nb = u[i - 1] + u[i + 1];
@@ -121,7 +119,7 @@ __device__ void b_wj(const BL &b, T *u, const T *f, T *tmp, T h2, T omega) {
       nb += u[i - sz];
       nb += u[i + sz];
     }
-    tmp[i] = (T(1) - omega) * u[i] + omega * (fma(h2, f[i], nb) * inv2d);
+    tmp[i] = (T(1) - omega) * u[i] + omega * point_solve<T, DIM>(h2, f[i], nb);
   });
   Team<W>::sync();
   b_for_all<DIM, W>(b, [&](int i, int, int, int) { u[i] = tmp[i]; });
@@ -314,10 +312,9 @@ __device__ __forceinline__ T r_nbsum(const RLev<DIM> &g, T u) {
 
 template <typename T, int DIM>
 __device__ __forceinline__ T r_colour(const RLev<DIM> &g, T u, T f, int colour, T h2) {
-  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const T nb = r_nbsum<T, DIM>(g, u);
   const bool upd = g.in && ((g.x + g.y + g.z + DIM + colour) & 1) == 0;
-  return upd ? fma(h2, f, nb) * inv2d : u;
+  return upd ? point_solve<T, DIM>(h2, f, nb) : u;
 }
 
 // full weighting of the fine level's residual onto the coarse lane's point

@@ -122,6 +122,25 @@ __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, T lo,
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gmg_u32x2, v), r, off, 0, 0);
 }
 
+// The pointwise solve (h^2 f + nb) / (2d) of a Gauss-Seidel or Jacobi update
+// (the relaxation of Sec. 3.2), rounded as written: the product h^2 f, the sum
+// and the quotient each rounded to nearest.  The quotient by 4 is exact; the
+// quotient by 6 takes the rounded reciprocal and one FMA correction, which
+// returns the correctly rounded quotient (Markstein's theorem: the first
+// quotient is within one ulp and the reciprocal within half an ulp; the FMA
+// residual y - 6q is exact).
+template <typename T, int DIM>
+__device__ __forceinline__ T point_solve(T h2, T f, T nb) {
+  const T y = h2 * f + nb;
+  if constexpr (DIM == 2) {
+    return y * T(0.25);
+  } else {
+    const T r6 = T(1.0 / 6.0);
+    const T q = y * r6;
+    return fma(fma(T(-6), q, y), r6, q);
+  }
+}
+
 // Flags of a fused smoothing pass.
 enum PassFlags : int {
   F_ZERO_IN = 1,     // start value is zero: u_in is not read

@@ -87,7 +87,6 @@ __device__ __forceinline__ size_t gidx(const Box<DIM> &b, int lx, int ly, int lz
 // S red-black half-sweeps in LDS, stage s on local coordinates [s, E-s)
 template <typename T, int DIM>
 __device__ void lds_sweeps(const Box<DIM> &b, T *u, const T *f, int S, int c1, int m, T h2) {
-  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const int E = b.E;
   for (int s = 1; s <= S; ++s) {
     const int cs = (c1 + s - 1) & 1;
@@ -95,7 +94,7 @@ __device__ void lds_sweeps(const Box<DIM> &b, T *u, const T *f, int S, int c1, i
       const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = DIM == 3 ? b.o[2] + lz : 0;
       if (((gx + gy + gz + DIM) & 1) != cs) return;
       if (!in_dom<DIM>(b, lx, ly, lz, m)) return;
-      u[i] = fma(h2, f[i], nb_sum<T, DIM>(u, i, E)) * inv2d;
+      u[i] = point_solve<T, DIM>(h2, f[i], nb_sum<T, DIM>(u, i, E));
     });
     __syncthreads();
   }

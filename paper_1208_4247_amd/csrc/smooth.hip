@@ -222,7 +222,6 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
   const int Z1 = min(Z0 + a.tz, m);
   const int planeS = DIM == 3 ? m * m : m;
   const T h2 = T(a.h2);
-  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
 
   // ---- per-slot geometry.  "P" is the element whose index equals the row
   // parity par = (y + DIM) & 1, "Q" the other one; an element e of plane z
@@ -567,7 +566,7 @@ __global__ void __launch_bounds__(NT) k_rb_pass(PassArgs<T> arg, const PassArgs<
         nb += W[s - 1][i][0];  // marching axis + 1
         const bool in = zin && (isP(s) ? kP[i] : kQ[i]);
         const T fv = isP(s) ? fP[s][i] : fQ[s][i];
-        const T v = in ? fma(h2, fv, nb) * inv2d : T(0);
+        const T v = in ? point_solve<T, DIM>(h2, fv, nb) : T(0);
         if (NMID && s == QN) {
           // the updated colour's residual after stage QN, from the same
           // neighbour sum: plane t - QN
@@ -732,7 +731,6 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
   const int Z1 = min(Z0 + a.tz, m);
   const int planeS = DIM == 3 ? m * m : m;
   const T h2 = T(a.h2);
-  const T inv2d = DIM == 3 ? T(1.0 / 6.0) : T(0.25);
   const T om = T(a.omega);
   const T om1 = T(1.0 - a.omega);
 
@@ -945,7 +943,7 @@ __global__ void __launch_bounds__(NT) k_wj_pass(PassArgs<T> arg, const PassArgs<
           const T nb = nbsum(L, W[s - 1], i, e);
           const T fv = e ? fe1[s][i] : fe0[s][i];
           const bool in = zin && (e ? k1[i] : k0[i]);
-          nv[e] = in ? om1 * W[s - 1][i][e][1] + om * (fma(h2, fv, nb) * inv2d) : T(0);
+          nv[e] = in ? om1 * W[s - 1][i][e][1] + om * point_solve<T, DIM>(h2, fv, nb) : T(0);
         }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {

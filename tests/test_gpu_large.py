@@ -12,10 +12,13 @@ solve reaches 1e-10 by the oracle's residual and its distance from the
 oracle's iterate is reported.
 2D 8191^2 (the largest 2D grid the library takes, uniform RHS, V(2,2)): the
 FP64 solve equals the oracle's at rtol 1e-7 (same cycle count, iterates
-within 1e-12).  At this h the rounding floor of the residual itself is near
+within 1e-12).
+FMG at the FMG benchmark sizes (2D 4095^2, 3D 255^3 and 1023^3, model
+problem): one autotuned pass equals the oracle's FMG to 1e-12 of the max.  At this h the rounding floor of the residual itself is near
 1e-9 of ||f|| (about eps * 8 |u| / h^2), so 1e-10 is out of reach for any
 FP64 solver there.
 """
+import math
 import os
 import time
 
@@ -177,3 +180,26 @@ def test_8191sq_fp64_solve_matches_oracle():
         it, rel, itr, time.perf_counter() - t0, diff), flush=True)
     assert (st, it) == (str_, itr) == (0, itr)
     assert diff <= 1e-12
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dim,L,nu", [(2, 12, 2), (3, 8, 2), (3, 10, 3)])
+def test_fmg_at_benchmark_sizes_matches_oracle(dim, L, nu):
+    """One FMG(nu,nu) pass (Algorithm 2) for f = d pi^2 prod sin(pi x_i), the
+    FMG workloads of bench.py with their autotuned tiles, equals the oracle's
+    FMG element by element (1e-12 of the max).  Every pointwise solve is
+    rounded as the oracle rounds it, so what remains is the order of the
+    transfers' sums (about 1e-15 at every size)."""
+    m = (1 << L) - 1
+    fd = (dim * math.pi ** 2) * wl.sine_product_device(dim, m, "cuda")
+    plan = tuned_plan(dim, L, nu1=nu, nu2=nu)
+    u = torch.empty_like(fd)
+    plan.fmg(u, fd)  # tunes
+    plan.fmg(u, fd)
+    ug, f = host(u), host(fd)
+    del u, fd
+    plan.close()
+    want = oracle.fmg(f, nu, nu)
+    err = float(np.max(np.abs(ug - want))) / float(np.max(np.abs(want)))
+    print("FMG(%d,%d) %dD %d: max rel diff %.3e" % (nu, nu, dim, m, err), flush=True)
+    assert err <= 1e-12
