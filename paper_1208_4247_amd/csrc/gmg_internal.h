@@ -123,21 +123,27 @@ __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, T lo,
 }
 
 // The pointwise solve (h^2 f + nb) / (2d) of a Gauss-Seidel or Jacobi update
-// (the relaxation of Sec. 3.2), rounded as written: the product h^2 f, the sum
-// and the quotient each rounded to nearest.  The quotient by 4 is exact; the
+// (the relaxation of Sec. 3.2).  FP64: rounded as written -- the product
+// h^2 f, the sum and the quotient each rounded to nearest, so the iterates are
+// those of the formula evaluated literally.  The quotient by 4 is exact; the
 // quotient by 6 takes the rounded reciprocal and one FMA correction, which
 // returns the correctly rounded quotient (Markstein's theorem: the first
 // quotient is within one ulp and the reciprocal within half an ulp; the FMA
-// residual y - 6q is exact).
+// residual y - 6q is exact).  FP32 (the inner cycles of the mixed form, whose
+// corrections the FP64 refinement checks): one FMA and the rounded reciprocal.
 template <typename T, int DIM>
 __device__ __forceinline__ T point_solve(T h2, T f, T nb) {
-  const T y = h2 * f + nb;
-  if constexpr (DIM == 2) {
-    return y * T(0.25);
+  if constexpr (sizeof(T) == 4) {
+    return fma(h2, f, nb) * (DIM == 3 ? T(1.0 / 6.0) : T(0.25));
   } else {
-    const T r6 = T(1.0 / 6.0);
-    const T q = y * r6;
-    return fma(fma(T(-6), q, y), r6, q);
+    const T y = h2 * f + nb;
+    if constexpr (DIM == 2) {
+      return y * T(0.25);
+    } else {
+      const T r6 = T(1.0 / 6.0);
+      const T q = y * r6;
+      return fma(fma(T(-6), q, y), r6, q);
+    }
   }
 }
 
