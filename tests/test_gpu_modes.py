@@ -173,3 +173,29 @@ def test_batch_profile_mode_same_bits():
     assert out[0][0] == out[1][0] and out[0][1] == out[1][1] == [0] * len(probs)
     for a, b in zip(out[0][2], out[1][2]):
         assert np.array_equal(a, b)
+
+
+SWEEP_CASES = [(2, 7), (2, 127), (2, 1023), (3, 3), (3, 31), (3, 127)]
+
+
+@pytest.mark.parametrize("dim,m", SWEEP_CASES)
+@pytest.mark.parametrize("nsweeps,backward", [(1, False), (2, True), (3, False)])
+def test_fp64_sweeps_give_the_oracles_bits(dim, m, nsweeps, backward):
+    """Every FP64 pointwise solve is (h^2 f + nb) / (2d) rounded as written,
+    with the oracle's neighbour order (x-1, x+1, y-1, y+1, z-1, z+1): a
+    red-black or weighted-Jacobi pass over any tile gives the oracle's sweep
+    bit for bit."""
+    from paper_1208_4247_amd.solver import Plan
+
+    f = wl.rhs_uniform(dim, m, seed=600 + m)
+    u0 = wl.rhs_uniform(dim, m, seed=700 + m) * 1e-3
+    out = torch.empty((m,) * dim, dtype=torch.float64, device="cuda")
+    plan = Plan(dim, levels_of(m), nu1=3, nu2=3)
+    plan.op_smooth(0, nsweeps, backward, dev(u0), dev(f), None, out)
+    assert np.array_equal(host(out), oracle.rbgs(u0, f, nsweeps, backward=backward))
+    plan.close()
+    omega = 2 * dim / (2 * dim + 1)
+    plan = Plan(dim, levels_of(m), smoother="wj", omega=omega, nu1=3, nu2=3)
+    plan.op_smooth(0, nsweeps, False, dev(u0), dev(f), None, out)
+    assert np.array_equal(host(out), oracle.wj(u0, f, omega, nsweeps))
+    plan.close()
