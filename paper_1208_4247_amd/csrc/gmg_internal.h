@@ -125,12 +125,16 @@ __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, int off, T lo,
 // The pointwise solve (h^2 f + nb) / (2d) of a Gauss-Seidel or Jacobi update
 // (the relaxation of Sec. 3.2).  FP64: rounded as written -- the product
 // h^2 f, the sum and the quotient each rounded to nearest, so the iterates are
-// those of the formula evaluated literally.  The quotient by 4 is exact; the
-// quotient by 6 takes the rounded reciprocal and one FMA correction, which
-// returns the correctly rounded quotient (Markstein's theorem: the first
-// quotient is within one ulp and the reciprocal within half an ulp; the FMA
-// residual y - 6q is exact).  FP32 (the inner cycles of the mixed form, whose
-// corrections the FP64 refinement checks): one FMA and the rounded reciprocal.
+// those of the formula evaluated literally.  The quotient by 4 is exact.  The
+// quotient by 6 is y * (C_hi + C_lo) with C_hi = RN(1/6), C_lo = RN(1/6 - C_hi),
+// formed as one FMA over the small product: fma(y, C_hi, RN(y C_lo)).  That is
+// the correctly rounded y/6 for every y whose y C_lo stays normal
+// (|y| > 2^-965): y/3 has a 53-bit integer numerator over 3, so it lies at
+// least 1/6 ulp from any rounding midpoint, while the value the FMA rounds
+// differs from y/6 by at most 2^-108 |y|.  Two dependent operations where the
+// reciprocal-and-correction form (Markstein) takes three.  FP32 (the inner
+// cycles of the mixed form, whose corrections the FP64 refinement checks): one
+// FMA and the rounded reciprocal.
 template <typename T, int DIM>
 __device__ __forceinline__ T point_solve(T h2, T f, T nb) {
   if constexpr (sizeof(T) == 4) {
@@ -140,9 +144,7 @@ __device__ __forceinline__ T point_solve(T h2, T f, T nb) {
     if constexpr (DIM == 2) {
       return y * T(0.25);
     } else {
-      const T r6 = T(1.0 / 6.0);
-      const T q = y * r6;
-      return fma(fma(T(-6), q, y), r6, q);
+      return fma(y, T(0x1.5555555555555p-3), y * T(0x1.5555555555555p-57));
     }
   }
 }
