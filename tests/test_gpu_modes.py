@@ -199,3 +199,29 @@ def test_fp64_sweeps_give_the_oracles_bits(dim, m, nsweeps, backward):
     plan.op_smooth(0, nsweeps, False, dev(u0), dev(f), None, out)
     assert np.array_equal(host(out), oracle.wj(u0, f, omega, nsweeps))
     plan.close()
+
+
+@pytest.mark.parametrize("dim,m", [(2, 127), (3, 31), (3, 127)])
+@pytest.mark.parametrize("scale", [2.0 ** -900, 1e-250, 1e250, 2.0 ** 1000])
+def test_fp64_sweeps_give_the_oracles_bits_at_extreme_scales(dim, m, scale):
+    """The same bitwise equality with the data scaled far from 1, so that
+    the quotients by 6 (and by 4) of the pointwise solve run over operands
+    near both ends of the exponent range (|h^2 f + nb| down to about 2^-910
+    and up to about 2^1000)."""
+    from paper_1208_4247_amd.solver import Plan
+
+    f = wl.rhs_uniform(dim, m, seed=800 + m) * scale
+    u0 = wl.rhs_uniform(dim, m, seed=900 + m) * (scale / 16.0)
+    assert np.all(np.isfinite(f)) and np.all(np.isfinite(u0))
+    out = torch.empty((m,) * dim, dtype=torch.float64, device="cuda")
+    plan = Plan(dim, levels_of(m), nu1=2, nu2=2)
+    plan.op_smooth(0, 2, True, dev(u0), dev(f), None, out)
+    want = oracle.rbgs(u0, f, 2, backward=True)
+    assert np.all(np.isfinite(want))
+    assert np.array_equal(host(out), want)
+    plan.close()
+    omega = 2 * dim / (2 * dim + 1)
+    plan = Plan(dim, levels_of(m), smoother="wj", omega=omega, nu1=2, nu2=2)
+    plan.op_smooth(0, 2, False, dev(u0), dev(f), None, out)
+    assert np.array_equal(host(out), oracle.wj(u0, f, omega, 2))
+    plan.close()
